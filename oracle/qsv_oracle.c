@@ -1,0 +1,478 @@
+/*
+ * qsv_oracle.c -- CPU test oracle for the reverse-mode energy gradient.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the plain, slow, complex128 statement of what the GPU
+ * library computes. Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+ * load it; the library never does, and the two share no code (this file includes no header of the
+ * library and repeats the few interface codes it needs).
+ *
+ * Source: T. Jones and J. Gacon, "Efficient calculation of gradients in classical simulations of
+ * variational quantum algorithms" (arXiv:2009.02823).
+ *   - energy <E> = <in| U^dag H U |in>, U = U_G ... U_1 ......................... Sec. 2.2
+ *   - reverse-mode gradient with states lambda, phi, mu ........................... Algorithm 1
+ *   - reference O(P^2) gradient, one re-simulation per entry .... Eq. (reference_gradient), Alg. 2
+ *   - rotation derivative dR/dtheta = alpha i G R(theta), alpha = -1/2 ............ Appendix A
+ *   - phase-gate and controlled-gate derivatives ................................. Appendix A
+ *   - several parameters in one gate: one clone/derivative/product per parameter . Algorithm 3
+ *   - repeated parameters: entries of one parameter are summed .......... App. B.2, Algorithm 4
+ * Fixed (parameter-free) gates are un-applied from phi and lambda like any other gate and give no
+ * gradient entry (the recurrences of Sec. 2.2 hold for any unitary).
+ *
+ * Conventions: qubit q is bit q of an amplitude index; a two-qubit gate on (q0, q1) uses the local
+ * basis index 2*bit(q0) + bit(q1), q0 being the control of controlled gates; |in> defaults to
+ * |0...0>. Gate matrices are built from their definitions and applied as dense 2x2 / 4x4 blocks;
+ * the Hamiltonian is applied term by term, one Pauli factor (a 2x2 matrix) at a time.
+ *
+ * Inner products use pairwise summation over fixed power-of-two blocks, so the result does not
+ * depend on the number of OpenMP threads.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+/* qsv_gate_kind codes of the C-ABI (an interface format; repeated, not included) */
+enum {
+  K_RX = 0, K_RY, K_RZ, K_H, K_X, K_Y, K_Z, K_S, K_CNOT, K_CZ,
+  K_PHASE, K_CRX, K_CRY, K_CRZ, K_RXX, K_RYY, K_RZZ, K_U3, K_T, K_SDG, K_NKINDS
+};
+
+typedef struct {
+  int32_t kind, q0, q1, p[3];
+} orc_gate;
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2 };
+
+/* ------------------------------------------------------------------------------------------ */
+/* Gate matrices                                                                              */
+/* ------------------------------------------------------------------------------------------ */
+
+static void pauli(int code, cplx m[2][2]) {
+  /* 0 = I, 1 = X, 2 = Y, 3 = Z */
+  static const double r[4][2][2][2] = {
+      {{{1, 0}, {0, 0}}, {{0, 0}, {1, 0}}},
+      {{{0, 0}, {1, 0}}, {{1, 0}, {0, 0}}},
+      {{{0, 0}, {0, -1}}, {{0, 1}, {0, 0}}},
+      {{{1, 0}, {0, 0}}, {{0, 0}, {-1, 0}}},
+  };
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) m[a][b] = r[code][a][b][0] + I * r[code][a][b][1];
+}
+
+static void kron2(cplx a[2][2], cplx b[2][2], cplx out[4][4]) {
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 2; ++k)
+        for (int l = 0; l < 2; ++l) out[2 * i + k][2 * j + l] = a[i][j] * b[k][l];
+}
+
+/* R_G(theta) = exp(-i theta G / 2) = cos(theta/2) 1 - i sin(theta/2) G for an involutory G
+   (G^2 = 1), and its derivative -sin(theta/2)/2 1 - (i/2) cos(theta/2) G, which equals
+   alpha i G R_G(theta) with alpha = -1/2 (Appendix A). dim = 2 or 4. */
+static void rotation(int dim, cplx G[4][4], double theta, int deriv, cplx out[4][4]) {
+  double c = cos(0.5 * theta), s = sin(0.5 * theta);
+  double ci = deriv ? -0.5 * s : c;   /* coefficient of the identity */
+  cplx cg = deriv ? -0.5 * I * c : -I * s; /* coefficient of G */
+  for (int a = 0; a < dim; ++a)
+    for (int b = 0; b < dim; ++b) out[a][b] = (a == b ? ci : 0.0) + cg * G[a][b];
+}
+
+static int gate_nparams(int kind) {
+  switch (kind) {
+    case K_RX: case K_RY: case K_RZ: case K_PHASE: case K_CRX: case K_CRY: case K_CRZ:
+    case K_RXX: case K_RYY: case K_RZZ:
+      return 1;
+    case K_U3:
+      return 3;
+    default:
+      return 0;
+  }
+}
+
+static int gate_nqubits(int kind) {
+  switch (kind) {
+    case K_CNOT: case K_CZ: case K_CRX: case K_CRY: case K_CRZ: case K_RXX: case K_RYY:
+    case K_RZZ:
+      return 2;
+    default:
+      return 1;
+  }
+}
+
+/* Matrix of gate g (deriv < 0) or of its partial derivative with respect to its deriv-th
+   parameter, written into m (2x2 in the top-left corner for one-qubit gates). */
+static int gate_matrix(const orc_gate* g, const double* theta, int deriv, cplx m[4][4]) {
+  memset(m, 0, sizeof(cplx) * 16);
+  double th[3] = {0, 0, 0};
+  for (int j = 0; j < gate_nparams(g->kind); ++j) th[j] = theta[g->p[j]];
+  int d = deriv >= 0;
+  cplx P[2][2], Q[2][2], G4[4][4], R2[4][4];
+  switch (g->kind) {
+    case K_RX: case K_RY: case K_RZ: {
+      pauli(g->kind - K_RX + 1, P);
+      cplx G[4][4] = {{P[0][0], P[0][1]}, {P[1][0], P[1][1]}};
+      rotation(2, G, th[0], d, m);
+      return 1;
+    }
+    case K_H:
+      m[0][0] = m[0][1] = m[1][0] = M_SQRT1_2;
+      m[1][1] = -M_SQRT1_2;
+      return 1;
+    case K_X: case K_Y: case K_Z:
+      pauli(g->kind - K_X + 1, P);
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) m[a][b] = P[a][b];
+      return 1;
+    case K_S:
+      m[0][0] = 1; m[1][1] = I;
+      return 1;
+    case K_SDG:
+      m[0][0] = 1; m[1][1] = -I;
+      return 1;
+    case K_T:
+      m[0][0] = 1; m[1][1] = cexp(I * M_PI / 4);
+      return 1;
+    case K_PHASE:
+      /* diag(1, e^{i theta}); derivative i e^{i theta} |1><1| (Appendix A) */
+      if (d) m[1][1] = I * cexp(I * th[0]);
+      else { m[0][0] = 1; m[1][1] = cexp(I * th[0]); }
+      return 1;
+    case K_U3: {
+      /* U3(t, f, l) = [[cos t/2, -e^{il} sin t/2], [e^{if} sin t/2, e^{i(f+l)} cos t/2]] */
+      double t = th[0], f = th[1], l = th[2];
+      double c = cos(0.5 * t), s = sin(0.5 * t);
+      cplx ef = cexp(I * f), el = cexp(I * l), efl = cexp(I * (f + l));
+      if (!d) {
+        m[0][0] = c; m[0][1] = -el * s; m[1][0] = ef * s; m[1][1] = efl * c;
+      } else if (deriv == 0) {
+        m[0][0] = -0.5 * s; m[0][1] = -el * 0.5 * c; m[1][0] = ef * 0.5 * c; m[1][1] = -efl * 0.5 * s;
+      } else if (deriv == 1) {
+        m[1][0] = I * ef * s; m[1][1] = I * efl * c;
+      } else {
+        m[0][1] = -I * el * s; m[1][1] = I * efl * c;
+      }
+      return 1;
+    }
+    case K_CNOT:
+      m[0][0] = m[1][1] = m[2][3] = m[3][2] = 1;
+      return 2;
+    case K_CZ:
+      m[0][0] = m[1][1] = m[2][2] = 1; m[3][3] = -1;
+      return 2;
+    case K_CRX: case K_CRY: case K_CRZ: {
+      /* |0><0| (x) 1 + |1><1| (x) R_G(theta); derivative |1><1| (x) dR_G (Appendix A) */
+      pauli(g->kind - K_CRX + 1, P);
+      cplx G[4][4] = {{P[0][0], P[0][1]}, {P[1][0], P[1][1]}};
+      rotation(2, G, th[0], d, R2);
+      if (!d) m[0][0] = m[1][1] = 1;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) m[2 + a][2 + b] = R2[a][b];
+      return 2;
+    }
+    case K_RXX: case K_RYY: case K_RZZ: {
+      /* exp(-i theta (s (x) s) / 2) for s = X, Y, Z (a rotation about a Pauli product) */
+      pauli(g->kind - K_RXX + 1, P);
+      pauli(g->kind - K_RXX + 1, Q);
+      kron2(P, Q, G4);
+      rotation(4, G4, th[0], d, m);
+      return 2;
+    }
+    default:
+      return 0;
+  }
+}
+
+static void adjoint(int dim, cplx m[4][4]) {
+  cplx t[4][4];
+  for (int a = 0; a < dim; ++a)
+    for (int b = 0; b < dim; ++b) t[a][b] = conj(m[b][a]);
+  for (int a = 0; a < dim; ++a)
+    for (int b = 0; b < dim; ++b) m[a][b] = t[a][b];
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* State-vector primitives: apply a matrix, clone, inner product                              */
+/* ------------------------------------------------------------------------------------------ */
+
+/* psi <- M psi for M acting on qubit q (2x2). Every index j with bit q clear names one pair. */
+static void apply_1q(cplx* psi, int n, int q, cplx m[4][4]) {
+  const int64_t dim = (int64_t)1 << n, bit = (int64_t)1 << q;
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < dim; ++j) {
+    if (j & bit) continue;
+    cplx a = psi[j], b = psi[j | bit];
+    psi[j] = m[0][0] * a + m[0][1] * b;
+    psi[j | bit] = m[1][0] * a + m[1][1] * b;
+  }
+}
+
+/* psi <- M psi for M acting on qubits (q0, q1) (4x4, local index 2 bit(q0) + bit(q1)). */
+static void apply_2q(cplx* psi, int n, int q0, int q1, cplx m[4][4]) {
+  const int64_t dim = (int64_t)1 << n, b0 = (int64_t)1 << q0, b1 = (int64_t)1 << q1;
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < dim; ++j) {
+    if (j & (b0 | b1)) continue;
+    int64_t idx[4] = {j, j | b1, j | b0, j | b0 | b1};
+    cplx v[4], w[4];
+    for (int k = 0; k < 4; ++k) v[k] = psi[idx[k]];
+    for (int r = 0; r < 4; ++r) {
+      w[r] = 0;
+      for (int k = 0; k < 4; ++k) w[r] += m[r][k] * v[k];
+    }
+    for (int k = 0; k < 4; ++k) psi[idx[k]] = w[k];
+  }
+}
+
+static void apply_matrix(cplx* psi, int n, const orc_gate* g, int nq, cplx m[4][4]) {
+  if (nq == 1) apply_1q(psi, n, g->q0, m);
+  else apply_2q(psi, n, g->q0, g->q1, m);
+}
+
+/* psi <- U psi (adj = 0) or psi <- U^dag psi (adj = 1) */
+static void apply_gate(cplx* psi, int n, const orc_gate* g, const double* theta, int adj) {
+  cplx m[4][4];
+  int nq = gate_matrix(g, theta, -1, m);
+  if (adj) adjoint(nq == 1 ? 2 : 4, m);
+  apply_matrix(psi, n, g, nq, m);
+}
+
+/* psi <- (dU/d theta_{p_j}) psi : a non-unitary matrix (Algorithm 1, derivative step) */
+static void apply_derivative(cplx* psi, int n, const orc_gate* g, const double* theta, int j) {
+  cplx m[4][4];
+  int nq = gate_matrix(g, theta, j, m);
+  apply_matrix(psi, n, g, nq, m);
+}
+
+static void clone(cplx* dst, const cplx* src, int n) {
+  memcpy(dst, src, sizeof(cplx) * ((size_t)1 << n));
+}
+
+static cplx dot_pairwise(const cplx* a, const cplx* b, int64_t len) {
+  if (len <= 8) {
+    cplx s = 0;
+    for (int64_t i = 0; i < len; ++i) s += conj(a[i]) * b[i];
+    return s;
+  }
+  int64_t h = len / 2;
+  return dot_pairwise(a, b, h) + dot_pairwise(a + h, b + h, len - h);
+}
+
+/* <a|b> = sum_j conj(a_j) b_j. Blocks of 2^14 amplitudes are summed pairwise (in parallel), then
+   the block sums pairwise; for power-of-two lengths this equals one pairwise sum. */
+static cplx inner(const cplx* a, const cplx* b, int n) {
+  const int64_t dim = (int64_t)1 << n;
+  const int64_t blk = dim < (1 << 14) ? dim : (1 << 14);
+  const int64_t nb = dim / blk;
+  cplx* part = (cplx*)malloc(sizeof(cplx) * nb);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nb; ++i) part[i] = dot_pairwise(a + i * blk, b + i * blk, blk);
+  /* pairwise over the block sums */
+  int64_t m = nb;
+  while (m > 1) {
+    int64_t h = m / 2;
+    for (int64_t i = 0; i < h; ++i) part[i] = part[2 * i] + part[2 * i + 1];
+    if (m & 1) part[h] = part[m - 1];
+    m = h + (m & 1);
+  }
+  cplx s = part[0];
+  free(part);
+  return s;
+}
+
+/* out <- H psi = sum_t c_t P_t psi, each Pauli string applied one factor at a time to a copy of
+   psi (tmp), then accumulated. The result is unnormalised (Algorithm 1, apply-H step). */
+static void apply_pauli_sum(const cplx* psi, cplx* out, cplx* tmp, int n, int n_terms,
+                            const uint8_t* codes, const double* coeffs) {
+  const int64_t dim = (int64_t)1 << n;
+  memset(out, 0, sizeof(cplx) * dim);
+  for (int t = 0; t < n_terms; ++t) {
+    clone(tmp, psi, n);
+    for (int q = 0; q < n; ++q) {
+      int code = codes[(int64_t)t * n + q];
+      if (code == 0) continue;
+      cplx p2[2][2], m[4][4] = {{0}};
+      pauli(code, p2);
+      m[0][0] = p2[0][0]; m[0][1] = p2[0][1]; m[1][0] = p2[1][0]; m[1][1] = p2[1][1];
+      apply_1q(tmp, n, q, m);
+    }
+    const double c = coeffs[t];
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < dim; ++j) out[j] += c * tmp[j];
+  }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Validation                                                                                 */
+/* ------------------------------------------------------------------------------------------ */
+
+static int check_inputs(int n, const orc_gate* gates, int n_gates, int n_theta, int n_terms,
+                        const uint8_t* codes, const double* coeffs) {
+  if (n < 1 || n > 34 || n_gates < 0 || n_theta < 0 || n_terms < 0) return ORC_EINVAL;
+  for (int k = 0; k < n_gates; ++k) {
+    const orc_gate* g = &gates[k];
+    if (g->kind < 0 || g->kind >= K_NKINDS) return ORC_EINVAL;
+    int nq = gate_nqubits(g->kind);
+    if (g->q0 < 0 || g->q0 >= n) return ORC_EINVAL;
+    if (nq == 2 && (g->q1 < 0 || g->q1 >= n || g->q1 == g->q0)) return ORC_EINVAL;
+    for (int j = 0; j < gate_nparams(g->kind); ++j)
+      if (g->p[j] < 0 || g->p[j] >= n_theta) return ORC_EINVAL;
+  }
+  if (n_terms && (!codes || !coeffs)) return ORC_EINVAL;
+  for (int64_t i = 0; i < (int64_t)n_terms * n; ++i)
+    if (codes[i] > 3) return ORC_EINVAL;
+  return ORC_OK;
+}
+
+static cplx* new_state(int n) { return (cplx*)malloc(sizeof(cplx) * ((size_t)1 << n)); }
+
+static void set_input(cplx* psi, const cplx* in, int n) {
+  if (in) {
+    clone(psi, in, n);
+  } else {
+    memset(psi, 0, sizeof(cplx) * ((size_t)1 << n));
+    psi[0] = 1;
+  }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Exported entry points (called through ctypes by the tests)                                 */
+/* ------------------------------------------------------------------------------------------ */
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* psi <- U_G ... U_1 psi, in place */
+int orc_apply_circuit(int n, cplx* psi, const orc_gate* gates, int n_gates, const double* theta,
+                      int n_theta, int adjoint_order) {
+  if (check_inputs(n, gates, n_gates, n_theta, 0, NULL, NULL)) return ORC_EINVAL;
+  if (!adjoint_order) {
+    for (int k = 0; k < n_gates; ++k) apply_gate(psi, n, &gates[k], theta, 0);
+  } else { /* psi <- U_1^dag ... U_G^dag psi, the inverse circuit */
+    for (int k = n_gates - 1; k >= 0; --k) apply_gate(psi, n, &gates[k], theta, 1);
+  }
+  return ORC_OK;
+}
+
+/* psi <- (dU_k / d theta_{p_j}) psi, for tests of the derivative matrices */
+int orc_apply_derivative(int n, cplx* psi, const orc_gate* g, const double* theta, int n_theta,
+                         int j) {
+  if (check_inputs(n, g, 1, n_theta, 0, NULL, NULL)) return ORC_EINVAL;
+  if (j < 0 || j >= gate_nparams(g->kind)) return ORC_EINVAL;
+  apply_derivative(psi, n, g, theta, j);
+  return ORC_OK;
+}
+
+/* out <- H psi */
+int orc_apply_pauli_sum(int n, const cplx* psi, cplx* out, int n_terms, const uint8_t* codes,
+                        const double* coeffs) {
+  if (check_inputs(n, NULL, 0, 0, n_terms, codes, coeffs)) return ORC_EINVAL;
+  cplx* tmp = new_state(n);
+  if (!tmp) return ORC_ENOMEM;
+  apply_pauli_sum(psi, out, tmp, n, n_terms, codes, coeffs);
+  free(tmp);
+  return ORC_OK;
+}
+
+/* <a|b> */
+int orc_inner(int n, const cplx* a, const cplx* b, double* out_re_im) {
+  cplx s = inner(a, b, n);
+  out_re_im[0] = creal(s);
+  out_re_im[1] = cimag(s);
+  return ORC_OK;
+}
+
+/* <E> = <psi|H|psi>, psi = U |in> (Sec. 2.2). energy = (Re, Im); Im is a Hermiticity check. */
+int orc_energy(int n, const cplx* in, const orc_gate* gates, int n_gates, const double* theta,
+               int n_theta, int n_terms, const uint8_t* codes, const double* coeffs,
+               double* energy) {
+  if (check_inputs(n, gates, n_gates, n_theta, n_terms, codes, coeffs)) return ORC_EINVAL;
+  cplx *psi = new_state(n), *hpsi = new_state(n), *tmp = new_state(n);
+  if (!psi || !hpsi || !tmp) { free(psi); free(hpsi); free(tmp); return ORC_ENOMEM; }
+  set_input(psi, in, n);
+  for (int k = 0; k < n_gates; ++k) apply_gate(psi, n, &gates[k], theta, 0);
+  apply_pauli_sum(psi, hpsi, tmp, n, n_terms, codes, coeffs);
+  cplx e = inner(psi, hpsi, n);
+  energy[0] = creal(e);
+  energy[1] = cimag(e);
+  free(psi); free(hpsi); free(tmp);
+  return ORC_OK;
+}
+
+/* Algorithm 1 ("reverse mode"). Writes energy = <psi|H|psi> (Re, Im) and grad[0..n_theta) as
+   sums over every (gate, parameter-slot) occurrence of a parameter. If prods is non-NULL it
+   receives the complex <lambda|mu> of each occurrence, in sweep order (last gate first), as
+   (Re, Im) pairs: the products whose real parts, doubled, form the gradient. */
+int orc_adjoint_gradient(int n, const cplx* in, const orc_gate* gates, int n_gates,
+                         const double* theta, int n_theta, int n_terms, const uint8_t* codes,
+                         const double* coeffs, double* energy, double* grad, double* prods) {
+  if (check_inputs(n, gates, n_gates, n_theta, n_terms, codes, coeffs)) return ORC_EINVAL;
+  cplx *lam = new_state(n), *phi = new_state(n), *mu = new_state(n);
+  if (!lam || !phi || !mu) { free(lam); free(phi); free(mu); return ORC_ENOMEM; }
+  for (int p = 0; p < n_theta; ++p) grad[p] = 0.0;
+
+  set_input(lam, in, n);                                      /* lambda := |in>          */
+  for (int k = 0; k < n_gates; ++k)                           /* lambda <- U_{1:P} lambda */
+    apply_gate(lam, n, &gates[k], theta, 0);
+  clone(phi, lam, n);                                         /* phi := lambda           */
+  apply_pauli_sum(phi, lam, mu, n, n_terms, codes, coeffs);   /* lambda <- H lambda (mu is
+                                                                 scratch here)            */
+  cplx e = inner(phi, lam, n);
+  energy[0] = creal(e);
+  energy[1] = cimag(e);
+
+  int64_t occ = 0;
+  for (int k = n_gates - 1; k >= 0; --k) {                    /* i = P ... 1             */
+    const orc_gate* g = &gates[k];
+    apply_gate(phi, n, g, theta, 1);                          /* phi <- U_i^dag phi      */
+    for (int j = 0; j < gate_nparams(g->kind); ++j) {         /* one pass per parameter  */
+      clone(mu, phi, n);                                      /* mu := phi               */
+      apply_derivative(mu, n, g, theta, j);                   /* mu <- dU_i/dtheta mu    */
+      cplx lm = inner(lam, mu, n);                            /* <lambda|mu>             */
+      grad[g->p[j]] += 2.0 * creal(lm);                       /* 2 Re <lambda|mu>        */
+      if (prods) { prods[2 * occ] = creal(lm); prods[2 * occ + 1] = cimag(lm); }
+      ++occ;
+    }
+    if (k > 0) apply_gate(lam, n, g, theta, 1);               /* lambda <- U_i^dag lambda */
+  }
+  free(lam); free(phi); free(mu);
+  return ORC_OK;
+}
+
+/* Algorithm 2, the reference gradient: for every parameter occurrence, re-simulate
+   mu = U_{i+1:P} (dU_i/dtheta) U_{1:i-1} |in> and take 2 Re <lambda|mu>, lambda = H U |in>. */
+int orc_reference_gradient(int n, const cplx* in, const orc_gate* gates, int n_gates,
+                           const double* theta, int n_theta, int n_terms, const uint8_t* codes,
+                           const double* coeffs, double* grad) {
+  if (check_inputs(n, gates, n_gates, n_theta, n_terms, codes, coeffs)) return ORC_EINVAL;
+  cplx *lam = new_state(n), *mu = new_state(n), *tmp = new_state(n);
+  if (!lam || !mu || !tmp) { free(lam); free(mu); free(tmp); return ORC_ENOMEM; }
+  for (int p = 0; p < n_theta; ++p) grad[p] = 0.0;
+
+  set_input(tmp, in, n);                                      /* lambda := |in>          */
+  for (int k = 0; k < n_gates; ++k) apply_gate(tmp, n, &gates[k], theta, 0);
+  apply_pauli_sum(tmp, lam, mu, n, n_terms, codes, coeffs);   /* lambda <- H U_{1:P}|in> */
+
+  for (int i = 0; i < n_gates; ++i) {                         /* i = 1 ... P             */
+    const orc_gate* g = &gates[i];
+    for (int j = 0; j < gate_nparams(g->kind); ++j) {
+      set_input(mu, in, n);                                   /* mu := |in>              */
+      for (int k = 0; k < i; ++k) apply_gate(mu, n, &gates[k], theta, 0); /* U_{1:i-1}   */
+      apply_derivative(mu, n, g, theta, j);                   /* dU_i / dtheta           */
+      for (int k = i + 1; k < n_gates; ++k) apply_gate(mu, n, &gates[k], theta, 0); /* U_{i+1:P} */
+      grad[g->p[j]] += 2.0 * creal(inner(lam, mu, n));        /* 2 Re <lambda|mu>        */
+    }
+  }
+  free(lam); free(mu); free(tmp);
+  return ORC_OK;
+}

@@ -1,0 +1,203 @@
+"""Benchmark: full reverse-mode gradients per second on one MI355X, against GPU parameter shift
+and the CPU oracle.
+
+Workload (one "step" = one energy + one full gradient, Algorithm 1): the hardware-efficient
+ansatz on 20 qubits with 20 layers of RY and RZ on every qubit plus a CNOT ladder (P = 800
+angles, seeded uniform in [0, 2pi)), under the open transverse-field Ising chain
+sum Z_i Z_{i+1} + 0.7 sum X_i, complex128 storage. Inputs are synthetic and resident on the GPU
+before the timed region starts.
+
+Prints one JSON line. Besides the headline value it carries:
+  roofline      the dominant kernel family's algorithmic bytes per launch over its average
+                launch duration (HIP events around each of its launches in the timed region),
+                against the 8 TB/s HBM peak;
+  c64           the same workload with complex64 storage and FP64 reductions;
+  param_shift   the faithful O(P^2) gradient on the same GPU, timed on a sample of entries;
+  cpu_baseline  the CPU oracle (Algorithm 1, complex128) on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "full gradients/sec and HBM GB/s, adjoint vs parameter-shift, at stated grad error"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2009_02823_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(family: str, workload: str, dtype: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
+    current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{family}_{workload}_{dtype}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_adjoint(qsv, torch, prob, dtype, steps, warmup, family_filter=None):
+    sv = qsv.StateVector(prob.n_qubits, dtype, device="cuda:0")
+    theta = torch.as_tensor(prob.theta, device="cuda:0")
+    e = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    g = torch.empty(prob.n_params, dtype=torch.float64, device="cuda:0")
+    # warm-up with every kernel timed, to find the dominant kernel family
+    sv.timing_enable("")
+    for _ in range(max(warmup, 1)):
+        sv.adjoint_gradient(prob.gates, theta, prob.codes, prob.coeffs, e, g)
+    stats = sv.timing_read()
+    dominant = stats[0]["name"] if family_filter is None else family_filter
+    sv.timing_enable(dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sv.adjoint_gradient(prob.gates, theta, prob.codes, prob.coeffs, e, g)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dom = sv.timing_read()
+    sv.timing_enable(None)
+    out = {"seconds": dt, "ms_per_step": 1e3 * dt / steps, "value": steps / dt,
+           "energy": float(e.cpu()[0]), "grad": g.cpu().numpy(), "warmup_stats": stats,
+           "dominant": dom[0] if dom else None}
+    sv.close()
+    return out
+
+
+def grad_error(prob, energy, grad, dtype):
+    import numpy as np
+    import make_golden
+    ref = make_golden.read(prob.name)
+    if ref is None:
+        return None
+    e_ref, g_ref = ref
+    d = {"max_abs_grad_err": float(np.max(np.abs(grad - g_ref))),
+         "abs_energy_err": abs(energy - e_ref.real),
+         "max_abs_grad_ref": float(np.max(np.abs(g_ref)))}
+    d["rel_grad_err"] = d["max_abs_grad_err"] / d["max_abs_grad_ref"]
+    d["tolerance"] = "1e-10 abs" if dtype == "c128" else "2e-4 * max|g_oracle|"
+    d["ok"] = (d["max_abs_grad_err"] <= 1e-10 if dtype == "c128" else d["rel_grad_err"] <= 2e-4)
+    return d
+
+
+def run_param_shift(qsv, torch, prob, dtype, entries, adj_grad):
+    import numpy as np
+    sv = qsv.StateVector(prob.n_qubits, dtype, device="cuda:0")
+    theta = torch.as_tensor(prob.theta, device="cuda:0")
+    g = torch.zeros(prob.n_params, dtype=torch.float64, device="cuda:0")
+    sv.param_shift_gradient(prob.gates, theta, prob.codes, prob.coeffs, 0, 1, g)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv.param_shift_gradient(prob.gates, theta, prob.codes, prob.coeffs, 0, entries, g)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gs = g.cpu().numpy()[:entries]
+    sv.close()
+    per_grad = dt * prob.n_params / entries
+    return {"seconds_per_gradient": per_grad, "value": 1.0 / per_grad,
+            "sampled_entries": entries, "sample_seconds": dt,
+            "max_abs_diff_vs_adjoint": float(np.max(np.abs(gs - adj_grad[:entries])))}
+
+
+def run_cpu_baseline(prob, budget_s):
+    from oracle import oracle as O
+    O.lib()
+    t0 = time.perf_counter()
+    O.adjoint_gradient(prob.n_qubits, prob.gates, prob.theta, prob.codes, prob.coeffs)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "gradients/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"one full energy + gradient of {prob.name} (Algorithm 1, complex128, "
+                      f"{dt:.1f} s)", "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--ps-entries", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-param-shift", action="store_true")
+    ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of the state is a design, not a build, here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2009_02823_amd import qsv
+    from paper_2009_02823_amd import workloads as W
+
+    prob = W.config2()
+    log(f"workload {prob.name}: n={prob.n_qubits} gates={prob.n_gates} P={prob.n_params}")
+    res = run_adjoint(qsv, torch, prob, "c128", args.steps, args.warmup)
+    log(f"c128 adjoint: {res['ms_per_step']:.3f} ms/gradient")
+    err = grad_error(prob, res["energy"], res["grad"], "c128")
+    dom = res["dominant"]
+    S = 16.0 * (1 << prob.n_qubits)
+    roof = None
+    if dom:
+        avg_s = dom["total_ms"] * 1e-3 / dom["launches"]
+        achieved = dom["bytes_per_launch"] / avg_s / 1e9
+        traffic = traffic_for(dom["name"], prob.name, "c128")
+        roof = {"bound": "hbm", "kernel": dom["name"], "achieved": achieved,
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                "traffic": traffic, "bytes_per_launch": dom["bytes_per_launch"],
+                "avg_launch_us": 1e6 * avg_s, "launches_per_step": dom["launches"] / args.steps,
+                "share_of_step": dom["total_ms"] / (res["ms_per_step"] * args.steps),
+                "state_bytes": S}
+    out = {
+        "metric": METRIC, "value": res["value"], "unit": "gradients/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": prob.name, "n_qubits": prob.n_qubits, "layers": 20,
+                   "n_params": prob.n_params, "n_gates": prob.n_gates,
+                   "hamiltonian": "open TFIM sum Z_iZ_{i+1} + 0.7 sum X_i (39 terms)",
+                   "storage": "complex128", "parallelism": "single GPU"},
+        "grad_error": err,
+        "roofline": roof,
+    }
+    if not args.no_c64:
+        r64 = run_adjoint(qsv, torch, prob, "c64", args.steps, args.warmup)
+        log(f"c64 adjoint: {r64['ms_per_step']:.3f} ms/gradient")
+        out["c64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
+                      "grad_error": grad_error(prob, r64["energy"], r64["grad"], "c64"),
+                      "dominant_kernel": r64["dominant"]}
+    if not args.no_param_shift:
+        ps = run_param_shift(qsv, torch, prob, "c128", args.ps_entries, res["grad"])
+        ps["speedup_of_adjoint"] = ps["seconds_per_gradient"] / (res["ms_per_step"] * 1e-3)
+        log(f"param shift: {ps['seconds_per_gradient']:.3f} s/gradient (sampled)")
+        out["param_shift"] = ps
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline(prob, args.cpu_budget)
+        log(f"cpu oracle: {out['cpu_baseline']['seconds']:.2f} s/gradient")
+    out["kernel_source_sha"] = kernel_source_sha()
+    print(json.dumps(out, default=float))
+
+
+if __name__ == "__main__":
+    main()

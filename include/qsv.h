@@ -1,0 +1,205 @@
+/*
+ * qsv.h -- C-ABI of the MI355X state-vector library for reverse-mode ("adjoint") energy gradients.
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950), the energy
+ *     E(theta) = <psi|H|psi>,   |psi> = U_G(theta) ... U_1(theta) |in>            (paper Sec. 2.2)
+ * of a parameterised circuit of one- and two-qubit gates under a Hamiltonian given as a real-
+ * weighted sum of Pauli strings, and its full gradient in one forward pass, one application of H
+ * and one backward sweep that un-applies every gate from two states phi and lambda, applies the
+ * gate derivative to (a register copy of) phi and accumulates 2 Re <lambda|mu> per parameter
+ * (paper Algorithm 1, Eq. recurrent_grad). Paper: T. Jones, J. Gacon, "Efficient calculation of
+ * gradients in classical simulations of variational quantum algorithms", arXiv:2009.02823.
+ *
+ * Conventions
+ *   - Qubit q is bit q of an amplitude index (little-endian). A state of n qubits is 2^n
+ *     contiguous interleaved complex amplitudes: (re, im) doubles for QSV_C128 (16 B each) or
+ *     floats for QSV_C64 (8 B each).
+ *   - Rotations are R_G(t) = exp(-i t G / 2) for a Pauli G (the paper's alpha = -1/2, App. A).
+ *   - A two-qubit gate on (q0, q1) has the local basis index 2 bit(q0) + bit(q1); q0 is the
+ *     control of controlled gates.
+ *   - Parameters, energies and gradients are float64 in both storage types.
+ *
+ * Memory and streams
+ *   - Every state and every array whose name starts with d_ is DEVICE memory owned by the caller;
+ *     gate tables and Pauli sums are HOST memory, copied (and cached by content) before return.
+ *   - Small internal tables (gate matrices, schedules, reduction partials) are allocated by the
+ *     library on first use and reused; a call that has to grow them allocates device memory.
+ *   - All work is enqueued on the handle's stream (a hipStream_t passed as void*; NULL = the
+ *     default stream) and is asynchronous: outputs are valid once the stream reaches the point
+ *     of the call (qsv_sync, or any later stream-ordered consumer).
+ *
+ * Errors
+ *   - Every entry point validates its arguments on the host before enqueueing anything; on an
+ *     error it returns a nonzero qsv_status, enqueues nothing, leaves every output untouched and
+ *     records a message readable with qsv_last_error() (thread-local).
+ *   - QSV_ERR_HIP reports a failed HIP call; faults of earlier asynchronous work surface there or
+ *     at qsv_sync. No call aborts the process or throws across the ABI.
+ *   - A handle must not be used by two threads at once; distinct handles are independent.
+ */
+#ifndef QSV_PUBLIC_API_H
+#define QSV_PUBLIC_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QSV_OK = 0,
+  QSV_ERR_INVALID_ARG = 1,
+  QSV_ERR_UNSUPPORTED = 2,
+  QSV_ERR_OUT_OF_MEMORY = 3,
+  QSV_ERR_HIP = 4,
+  QSV_ERR_INTERNAL = 5
+} qsv_status;
+
+typedef enum { QSV_C64 = 0, QSV_C128 = 1 } qsv_dtype;
+
+/* Gate kinds. Parameterised kinds read theta[param[j]] for j < (number of parameters). */
+typedef enum {
+  QSV_RX = 0,     /* exp(-i t X/2) on q0                           1 parameter            */
+  QSV_RY = 1,     /* exp(-i t Y/2) on q0                           1 parameter            */
+  QSV_RZ = 2,     /* exp(-i t Z/2) on q0                           1 parameter            */
+  QSV_H = 3,      /* Hadamard on q0                                                       */
+  QSV_X = 4,      /* Pauli X on q0                                                        */
+  QSV_Y = 5,      /* Pauli Y on q0                                                        */
+  QSV_Z = 6,      /* Pauli Z on q0                                                        */
+  QSV_S = 7,      /* diag(1, i) on q0                                                     */
+  QSV_CNOT = 8,   /* control q0, target q1                                                */
+  QSV_CZ = 9,     /* diag(1, 1, 1, -1) on (q0, q1)                                        */
+  QSV_PHASE = 10, /* diag(1, e^{i t}) on q0                        1 parameter            */
+  QSV_CRX = 11,   /* control q0, exp(-i t X/2) on target q1        1 parameter            */
+  QSV_CRY = 12,   /* control q0, exp(-i t Y/2) on target q1        1 parameter            */
+  QSV_CRZ = 13,   /* control q0, exp(-i t Z/2) on target q1        1 parameter            */
+  QSV_RXX = 14,   /* exp(-i t X(x)X/2) on (q0, q1)                 1 parameter            */
+  QSV_RYY = 15,   /* exp(-i t Y(x)Y/2) on (q0, q1)                 1 parameter            */
+  QSV_RZZ = 16,   /* exp(-i t Z(x)Z/2) on (q0, q1)                 1 parameter            */
+  QSV_U3 = 17,    /* [[c, -e^{il} s], [e^{if} s, e^{i(f+l)} c]], c = cos(t/2), s = sin(t/2),
+                     parameters (t, f, l) = theta[param[0..2]]   3 parameters            */
+  QSV_T = 18,     /* diag(1, e^{i pi/4}) on q0                                            */
+  QSV_SDG = 19    /* diag(1, -i) on q0                                                    */
+} qsv_gate_kind;
+
+/* One gate of a circuit. Circuits are arrays applied in index order (U_1 first).
+   q1 = -1 for one-qubit kinds. param[j] = index into theta for the j-th parameter of the kind,
+   -1 for the unused slots. Several gates may name the same parameter; its gradient entry is then
+   the sum over its occurrences (paper App. B.2). */
+typedef struct {
+  int32_t kind;
+  int32_t q0;
+  int32_t q1;
+  int32_t param[3];
+} qsv_gate;
+
+/* H = sum_t coeffs[t] P_t with P_t = (x)_q sigma(codes[t * n_qubits + q]) and the codes
+   0 = I, 1 = X, 2 = Y, 3 = Z. Coefficients are real (H Hermitian, paper Sec. 2.2). Host memory. */
+typedef struct {
+  int32_t n_terms;
+  const uint8_t* codes;   /* [n_terms * n_qubits] */
+  const double* coeffs;   /* [n_terms]            */
+} qsv_pauli_sum;
+
+typedef struct qsv_state qsv_state;
+
+/* ---- host-only validation (no GPU needed) ------------------------------------------------- */
+
+/* Checks a gate table against n_qubits and n_theta: known kinds, qubits in range and distinct,
+   q1 = -1 for one-qubit kinds, parameter slots in [0, n_theta) where used and -1 elsewhere. */
+qsv_status qsv_validate_circuit(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates,
+                                int32_t n_theta);
+
+/* Checks a Pauli sum: n_terms >= 0, codes <= 3, finite coefficients, non-NULL arrays. */
+qsv_status qsv_validate_pauli_sum(int32_t n_qubits, const qsv_pauli_sum* H);
+
+/* Bytes of caller-provided device workspace qsv_create needs: two states (phi and lambda of
+   Algorithm 1). Returns 0 for an invalid (n_qubits, dtype). */
+size_t qsv_workspace_bytes(int32_t n_qubits, qsv_dtype dtype);
+
+/* Bytes of one state of n_qubits in dtype (2^n amplitudes). 0 if invalid. */
+size_t qsv_state_bytes(int32_t n_qubits, qsv_dtype dtype);
+
+/* Message of the last failed call on this thread ("" if none). Valid until the next call. */
+const char* qsv_last_error(void);
+
+/* ---- handles ------------------------------------------------------------------------------ */
+
+/* Creates a handle for an n_qubits state (1 <= n_qubits <= 34) on the current HIP device.
+   d_state: caller-owned device buffer of qsv_state_bytes(n_qubits, dtype) bytes holding the
+            immutable input state |in> of Algorithm 1; qsv_create writes |0...0> into it.
+   d_work:  caller-owned device buffer of at least qsv_workspace_bytes(n_qubits, dtype) bytes.
+   stream:  hipStream_t (as void*) all work of this handle is ordered on.
+   Both buffers must be 256-byte aligned and stay valid until qsv_destroy. */
+qsv_status qsv_create(int32_t n_qubits, qsv_dtype dtype, void* d_state, void* d_work,
+                      size_t work_bytes, void* stream, qsv_state** out);
+
+/* Releases the library-owned tables of the handle; never frees caller buffers. NULL is a no-op. */
+qsv_status qsv_destroy(qsv_state* s);
+
+/* Changes the stream later calls of this handle enqueue on. */
+qsv_status qsv_set_stream(qsv_state* s, void* stream);
+
+/* Writes |0...0> into the handle's state. */
+qsv_status qsv_reset(qsv_state* s);
+
+/* Blocks until all work enqueued on the handle's stream has finished; reports asynchronous
+   HIP errors. */
+qsv_status qsv_sync(qsv_state* s);
+
+/* ---- the computation ---------------------------------------------------------------------- */
+
+/* state <- U_G(theta) ... U_1(theta) state   (Algorithm 1, apply-circuit step; Sec. 2.2).
+   d_theta: device float64[n_theta] (may be NULL if no gate has a parameter). */
+qsv_status qsv_apply_circuit(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                             const double* d_theta, int32_t n_theta);
+
+/* *d_energy <- <state|H|state> (real part; the state is not modified, nothing is written into the
+   workspace). d_energy: device float64[1]. (Sec. 2.2, the energy functional.) */
+qsv_status qsv_expectation_pauli_sum(qsv_state* s, const qsv_pauli_sum* H, double* d_energy);
+
+/* Reverse-mode gradient (Algorithm 1) with the handle's state as |in> (left unchanged):
+     psi = U |in>,  lambda = H psi,  E = <psi|lambda>;
+     for i = G..1:  phi <- U_i^dag phi;  grad[param_i] += 2 Re <lambda| dU_i/dtheta |phi>;
+                    lambda <- U_i^dag lambda (for i > 1).
+   d_energy: device float64[1] <- E.   d_grad: device float64[n_theta], overwritten (entries of
+   parameters no gate uses are 0). Uses the workspace as phi and lambda. */
+qsv_status qsv_adjoint_gradient(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                                const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
+                                double* d_energy, double* d_grad);
+
+/* Faithful O(P^2) baseline on the same GPU (the re-simulation the paper's introduction calls
+   "faithful" emulation, here in its parameter-shift form): for p in [first, first + count),
+     grad[p] = ( E(theta + (pi/2) e_p) - E(theta - (pi/2) e_p) ) / 2,
+   each E a full reset + forward pass + expectation with the same kernels as the adjoint path.
+   Exact for parameters used by exactly one gate whose generator has two eigenvalues that differ
+   by 1 (RX RY RZ RXX RYY RZZ PHASE U3); returns QSV_ERR_UNSUPPORTED for controlled rotations or
+   repeated parameters. Entries outside the range are not written. Uses the workspace. */
+qsv_status qsv_param_shift_gradient(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                                    const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
+                                    int32_t first, int32_t count, double* d_grad);
+
+/* ---- measurement -------------------------------------------------------------------------- */
+
+/* Per-kernel-family statistics gathered from HIP events recorded on the handle's stream right
+   before and after every timed launch. */
+typedef struct {
+  char name[48];     /* kernel family: a substring of the kernel's symbol name                  */
+  int64_t launches;  /* timed launches                                                          */
+  double total_ms;   /* sum of the launches' event-to-event durations                           */
+  double bytes;      /* sum of their algorithmic bytes: unique state bytes read plus written    */
+} qsv_kernel_stat;
+
+/* Starts timing launches whose family name contains name_filter ("" = every kernel) and clears
+   earlier statistics; name_filter = NULL stops timing. */
+qsv_status qsv_timing_enable(qsv_state* s, const char* name_filter);
+
+/* Waits for the handle's stream, folds the recorded events into per-family statistics and copies
+   up to max_out of them (sorted by total time, largest first) to out; *n_out = number copied. */
+qsv_status qsv_timing_read(qsv_state* s, qsv_kernel_stat* out, int32_t max_out, int32_t* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSV_PUBLIC_API_H */

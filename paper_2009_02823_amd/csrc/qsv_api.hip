@@ -1,0 +1,679 @@
+// C-ABI of the qsv library: argument validation, handles, plan caching and the launch sequences
+// of the forward pass, the Hamiltonian application and the reverse sweep (Algorithm 1).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/qsv.h"
+#include "qsv_internal.h"
+#include "sv_kernels.h"
+
+using namespace qsv;
+
+static_assert(sizeof(qsv_gate) == sizeof(GateDesc), "qsv_gate and GateDesc must match");
+
+// ------------------------------------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static qsv_status fail(qsv_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(QSV_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),        \
+                  __FILE__, __LINE__);                                                       \
+  } while (0)
+
+#define QSV_TRY(expr)                 \
+  do {                                \
+    qsv_status s_ = (expr);           \
+    if (s_ != QSV_OK) return s_;      \
+  } while (0)
+
+extern "C" const char* qsv_last_error(void) { return g_last_error.c_str(); }
+
+static constexpr int kMaxQubits = 34;
+
+// ------------------------------------------------------------------------------------------------
+// validation (host only)
+// ------------------------------------------------------------------------------------------------
+extern "C" qsv_status qsv_validate_circuit(int32_t n, const qsv_gate* gates, int32_t n_gates,
+                                           int32_t n_theta) {
+  if (n < 1 || n > kMaxQubits)
+    return fail(QSV_ERR_INVALID_ARG, "n_qubits = %d outside [1, %d]", n, kMaxQubits);
+  if (n_gates < 0) return fail(QSV_ERR_INVALID_ARG, "n_gates = %d < 0", n_gates);
+  if (n_theta < 0) return fail(QSV_ERR_INVALID_ARG, "n_theta = %d < 0", n_theta);
+  if (n_gates > 0 && !gates) return fail(QSV_ERR_INVALID_ARG, "gates is NULL");
+  for (int32_t k = 0; k < n_gates; ++k) {
+    const qsv_gate& g = gates[k];
+    if (g.kind < 0 || g.kind >= K_NKINDS)
+      return fail(QSV_ERR_INVALID_ARG, "gate %d: unknown kind %d", k, g.kind);
+    if (g.q0 < 0 || g.q0 >= n)
+      return fail(QSV_ERR_INVALID_ARG, "gate %d: qubit q0 = %d outside [0, %d)", k, g.q0, n);
+    if (kind_nqubits(g.kind) == 2) {
+      if (g.q1 < 0 || g.q1 >= n)
+        return fail(QSV_ERR_INVALID_ARG, "gate %d: qubit q1 = %d outside [0, %d)", k, g.q1, n);
+      if (g.q1 == g.q0)
+        return fail(QSV_ERR_INVALID_ARG, "gate %d: two-qubit gate on one qubit %d", k, g.q0);
+    } else if (g.q1 != -1) {
+      return fail(QSV_ERR_INVALID_ARG, "gate %d: one-qubit kind with q1 = %d (must be -1)", k,
+                  g.q1);
+    }
+    const int np = kind_nparams(g.kind);
+    for (int j = 0; j < 3; ++j) {
+      if (j < np && (g.param[j] < 0 || g.param[j] >= n_theta))
+        return fail(QSV_ERR_INVALID_ARG, "gate %d: param[%d] = %d outside [0, %d)", k, j,
+                    g.param[j], n_theta);
+      if (j >= np && g.param[j] != -1)
+        return fail(QSV_ERR_INVALID_ARG, "gate %d: unused param[%d] = %d (must be -1)", k, j,
+                    g.param[j]);
+    }
+  }
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_validate_pauli_sum(int32_t n, const qsv_pauli_sum* H) {
+  if (n < 1 || n > kMaxQubits)
+    return fail(QSV_ERR_INVALID_ARG, "n_qubits = %d outside [1, %d]", n, kMaxQubits);
+  if (!H) return fail(QSV_ERR_INVALID_ARG, "Pauli sum is NULL");
+  if (H->n_terms < 0) return fail(QSV_ERR_INVALID_ARG, "n_terms = %d < 0", H->n_terms);
+  if (H->n_terms == 0) return QSV_OK;
+  if (!H->codes || !H->coeffs) return fail(QSV_ERR_INVALID_ARG, "Pauli codes/coeffs NULL");
+  for (int64_t i = 0; i < (int64_t)H->n_terms * n; ++i)
+    if (H->codes[i] > 3)
+      return fail(QSV_ERR_INVALID_ARG, "Pauli code %d at term %lld qubit %lld (must be 0..3)",
+                  (int)H->codes[i], (long long)(i / n), (long long)(i % n));
+  for (int32_t t = 0; t < H->n_terms; ++t)
+    if (!std::isfinite(H->coeffs[t]))
+      return fail(QSV_ERR_INVALID_ARG, "coefficient %d is not finite", t);
+  return QSV_OK;
+}
+
+extern "C" size_t qsv_state_bytes(int32_t n, qsv_dtype dt) {
+  if (n < 1 || n > kMaxQubits || (dt != QSV_C64 && dt != QSV_C128)) return 0;
+  return ((size_t)1 << n) * (dt == QSV_C128 ? 16 : 8);
+}
+
+extern "C" size_t qsv_workspace_bytes(int32_t n, qsv_dtype dt) {
+  return 2 * qsv_state_bytes(n, dt);
+}
+
+// ------------------------------------------------------------------------------------------------
+// device buffers owned by the library
+// ------------------------------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  // Grows to at least `bytes`; waits for `st` first so no queued kernel still uses the old one.
+  qsv_status ensure(size_t bytes, hipStream_t st) {
+    if (bytes <= cap) return QSV_OK;
+    HIP_TRY(hipStreamSynchronize(st));
+    if (p) HIP_TRY(hipFree(p));
+    p = nullptr;
+    cap = 0;
+    size_t want = bytes < 256 ? 256 : bytes;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail(QSV_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+    }
+    cap = want;
+    return QSV_OK;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+static uint64_t fnv1a(const void* data, size_t len, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* b = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < len; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// A circuit lowered for the device: gate table, matrix records, and the map from parameters to
+// the reduction slots of their occurrences (in sweep order, last gate first).
+struct Plan {
+  std::vector<GateDesc> gates;
+  int n_theta = 0;
+  int n_occ = 0;
+  std::vector<int32_t> slot_of_gate;  // first reduction slot of gate k (-1 if none)
+  std::vector<int32_t> param_ptr, occ;
+  DevBuf d_gates, d_recs, d_param_ptr, d_occ;
+};
+
+struct PauliPlan {
+  std::vector<PauliGroup> groups;
+  std::vector<PauliTerm> terms;
+  DevBuf d_groups, d_terms;
+};
+
+// Per-launch HIP-event timing of selected kernel families (qsv_timing_enable / _read).
+struct Timer {
+  bool on = false;
+  std::string filter;
+  struct Pending {
+    const char* name;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pending;
+  std::map<std::string, qsv_kernel_stat> agg;
+  ~Timer() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+  bool wants(const char* name) const {
+    return on && (filter.empty() || std::strstr(name, filter.c_str()) != nullptr);
+  }
+  hipError_t take(hipEvent_t* e) {
+    if (!pool.empty()) {
+      *e = pool.back();
+      pool.pop_back();
+      return hipSuccess;
+    }
+    return hipEventCreate(e);
+  }
+};
+
+struct qsv_state {
+  int n = 0;
+  qsv_dtype dt = QSV_C128;
+  void* d_state = nullptr;
+  void* d_work = nullptr;
+  size_t work_bytes = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int nb = 1;
+  std::unordered_map<uint64_t, std::unique_ptr<Plan>> plans;
+  std::unordered_map<uint64_t, std::unique_ptr<PauliPlan>> paulis;
+  DevBuf partials, epartials, theta_scratch, energies;
+  Timer timer;
+};
+
+static constexpr size_t kMaxCachedPlans = 64;
+
+static qsv_status check_handle(qsv_state* s) {
+  if (!s) return fail(QSV_ERR_INVALID_ARG, "handle is NULL");
+  HIP_TRY(hipSetDevice(s->device));
+  return QSV_OK;
+}
+
+// Runs `launch` (which enqueues exactly one kernel on s->stream) between two timing events when
+// the kernel family `name` is being timed.
+template <typename F>
+static qsv_status timed(qsv_state* s, const char* name, double bytes, F&& launch) {
+  const bool t = s->timer.wants(name);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (t) {
+    HIP_TRY(s->timer.take(&a));
+    HIP_TRY(s->timer.take(&b));
+    HIP_TRY(hipEventRecord(a, s->stream));
+  }
+  HIP_TRY(launch());
+  if (t) {
+    HIP_TRY(hipEventRecord(b, s->stream));
+    s->timer.pending.push_back({name, bytes, a, b});
+  }
+  return QSV_OK;
+}
+
+// Algorithmic bytes of one gate-granular launch: unique state bytes read plus written.
+static double forward_bytes(const GateDesc& g, double S) {
+  if (g.kind == K_CNOT) return S;        // the control = 1 half, read and written
+  if (g.kind == K_CZ) return 0.5 * S;    // the 11 quarter, read and written
+  return 2 * S;
+}
+static double backward_bytes(const GateDesc& g, double S, bool undo_lam) {
+  const bool reads_lam = kind_nparams(g.kind) > 0 || undo_lam;
+  const double phi = forward_bytes(g, S);
+  const double lam = undo_lam ? phi : (reads_lam ? 0.5 * phi : 0.0);
+  return phi + lam;
+}
+
+static qsv_status get_plan(qsv_state* s, const qsv_gate* gates, int32_t n_gates, int32_t n_theta,
+                           Plan** out) {
+  uint64_t h = fnv1a(gates, sizeof(qsv_gate) * (size_t)n_gates);
+  h = fnv1a(&n_theta, sizeof n_theta, h);
+  h = fnv1a(&n_gates, sizeof n_gates, h);
+  auto it = s->plans.find(h);
+  if (it != s->plans.end()) {
+    Plan* p = it->second.get();
+    if ((int32_t)p->gates.size() == n_gates && p->n_theta == n_theta &&
+        (n_gates == 0 || std::memcmp(p->gates.data(), gates, sizeof(qsv_gate) * n_gates) == 0)) {
+      *out = p;
+      return QSV_OK;
+    }
+  }
+  if (s->plans.size() >= kMaxCachedPlans) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->plans.clear();
+  }
+  auto p = std::make_unique<Plan>();
+  p->gates.assign(reinterpret_cast<const GateDesc*>(gates),
+                  reinterpret_cast<const GateDesc*>(gates) + n_gates);
+  p->n_theta = n_theta;
+  p->slot_of_gate.assign(n_gates, -1);
+  std::vector<std::vector<int32_t>> per_param(n_theta);
+  int slot = 0;
+  for (int k = n_gates - 1; k >= 0; --k) {
+    const GateDesc& g = p->gates[k];
+    const int np = kind_nparams(g.kind);
+    if (!np) continue;
+    p->slot_of_gate[k] = slot;
+    for (int j = 0; j < np; ++j) per_param[g.p[j]].push_back(slot + j);
+    slot += np;
+  }
+  p->n_occ = slot;
+  p->param_ptr.assign(n_theta + 1, 0);
+  for (int q = 0; q < n_theta; ++q) {
+    p->param_ptr[q + 1] = p->param_ptr[q] + (int32_t)per_param[q].size();
+    p->occ.insert(p->occ.end(), per_param[q].begin(), per_param[q].end());
+  }
+  const hipStream_t st = s->stream;
+  QSV_TRY(p->d_gates.ensure(sizeof(GateDesc) * (n_gates ? n_gates : 1), st));
+  QSV_TRY(p->d_recs.ensure(sizeof(GateRec) * (n_gates ? n_gates : 1), st));
+  QSV_TRY(p->d_param_ptr.ensure(sizeof(int32_t) * (n_theta + 1), st));
+  QSV_TRY(p->d_occ.ensure(sizeof(int32_t) * (p->occ.size() + 1), st));
+  if (n_gates)
+    HIP_TRY(hipMemcpyAsync(p->d_gates.p, p->gates.data(), sizeof(GateDesc) * n_gates,
+                           hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(p->d_param_ptr.p, p->param_ptr.data(), sizeof(int32_t) * (n_theta + 1),
+                         hipMemcpyHostToDevice, st));
+  if (!p->occ.empty())
+    HIP_TRY(hipMemcpyAsync(p->d_occ.p, p->occ.data(), sizeof(int32_t) * p->occ.size(),
+                           hipMemcpyHostToDevice, st));
+  *out = p.get();
+  s->plans[h] = std::move(p);
+  return QSV_OK;
+}
+
+static qsv_status get_pauli(qsv_state* s, const qsv_pauli_sum* H, PauliPlan** out) {
+  const int n = s->n;
+  uint64_t h = fnv1a(H->codes, (size_t)H->n_terms * n);
+  h = fnv1a(H->coeffs, sizeof(double) * H->n_terms, h);
+  h = fnv1a(&H->n_terms, sizeof H->n_terms, h);
+  auto it = s->paulis.find(h);
+  if (it != s->paulis.end()) {
+    *out = it->second.get();
+    return QSV_OK;
+  }
+  if (s->paulis.size() >= kMaxCachedPlans) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->paulis.clear();
+  }
+  auto p = std::make_unique<PauliPlan>();
+  // (P psi)_j = i^{nY} (-1)^{popcount((j^x) & z)} psi_{j^x}: x = X|Y positions, z = Z|Y.
+  std::vector<uint64_t> xs;
+  std::vector<std::vector<PauliTerm>> by_group;
+  for (int t = 0; t < H->n_terms; ++t) {
+    uint64_t x = 0, z = 0;
+    int ny = 0;
+    for (int q = 0; q < n; ++q) {
+      const int c = H->codes[(size_t)t * n + q];
+      if (c == 1 || c == 2) x |= 1ull << q;
+      if (c == 3 || c == 2) z |= 1ull << q;
+      if (c == 2) ++ny;
+    }
+    static const double ire[4] = {1, 0, -1, 0}, iim[4] = {0, 1, 0, -1};
+    const double c = H->coeffs[t];
+    PauliTerm term{z, c * ire[ny & 3], c * iim[ny & 3]};
+    size_t g = 0;
+    while (g < xs.size() && xs[g] != x) ++g;
+    if (g == xs.size()) {
+      xs.push_back(x);
+      by_group.emplace_back();
+    }
+    by_group[g].push_back(term);
+  }
+  for (size_t g = 0; g < xs.size(); ++g) {
+    PauliGroup G{xs[g], (int32_t)p->terms.size(), 0};
+    p->terms.insert(p->terms.end(), by_group[g].begin(), by_group[g].end());
+    G.t1 = (int32_t)p->terms.size();
+    p->groups.push_back(G);
+  }
+  const hipStream_t st = s->stream;
+  QSV_TRY(p->d_groups.ensure(sizeof(PauliGroup) * (p->groups.size() + 1), st));
+  QSV_TRY(p->d_terms.ensure(sizeof(PauliTerm) * (p->terms.size() + 1), st));
+  if (!p->groups.empty()) {
+    HIP_TRY(hipMemcpyAsync(p->d_groups.p, p->groups.data(), sizeof(PauliGroup) * p->groups.size(),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->d_terms.p, p->terms.data(), sizeof(PauliTerm) * p->terms.size(),
+                           hipMemcpyHostToDevice, st));
+  }
+  *out = p.get();
+  s->paulis[h] = std::move(p);
+  return QSV_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// handles
+// ------------------------------------------------------------------------------------------------
+template <typename R>
+static hipError_t reset_state(qsv_state* s) {
+  return launch_reset<R>(s->d_state, s->n, s->stream);
+}
+
+static hipError_t dispatch_reset(qsv_state* s) {
+  return s->dt == QSV_C128 ? reset_state<double>(s) : reset_state<float>(s);
+}
+
+extern "C" qsv_status qsv_create(int32_t n, qsv_dtype dt, void* d_state, void* d_work,
+                                 size_t work_bytes, void* stream, qsv_state** out) {
+  if (!out) return fail(QSV_ERR_INVALID_ARG, "out is NULL");
+  if (n < 1 || n > kMaxQubits)
+    return fail(QSV_ERR_INVALID_ARG, "n_qubits = %d outside [1, %d]", n, kMaxQubits);
+  if (dt != QSV_C64 && dt != QSV_C128) return fail(QSV_ERR_INVALID_ARG, "unknown dtype %d", dt);
+  if (!d_state || !d_work) return fail(QSV_ERR_INVALID_ARG, "state or workspace is NULL");
+  if (((uintptr_t)d_state | (uintptr_t)d_work) & 255)
+    return fail(QSV_ERR_INVALID_ARG, "state and workspace must be 256-byte aligned");
+  if (work_bytes < qsv_workspace_bytes(n, dt))
+    return fail(QSV_ERR_INVALID_ARG, "workspace of %zu bytes < %zu needed", work_bytes,
+                qsv_workspace_bytes(n, dt));
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  auto s = std::make_unique<qsv_state>();
+  s->n = n;
+  s->dt = dt;
+  s->d_state = d_state;
+  s->d_work = d_work;
+  s->work_bytes = work_bytes;
+  s->stream = static_cast<hipStream_t>(stream);
+  s->device = dev;
+  s->nb = sweep_blocks(n);
+  HIP_TRY(dispatch_reset(s.get()));
+  *out = s.release();
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_destroy(qsv_state* s) {
+  if (!s) return QSV_OK;
+  (void)hipSetDevice(s->device);
+  (void)hipStreamSynchronize(s->stream);
+  delete s;
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_set_stream(qsv_state* s, void* stream) {
+  QSV_TRY(check_handle(s));
+  // Work already queued on the old stream must finish before the new stream may touch the same
+  // buffers.
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->stream = static_cast<hipStream_t>(stream);
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_reset(qsv_state* s) {
+  QSV_TRY(check_handle(s));
+  HIP_TRY(dispatch_reset(s));
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_sync(qsv_state* s) {
+  QSV_TRY(check_handle(s));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// computations
+// ------------------------------------------------------------------------------------------------
+static qsv_status check_theta(const Plan* p, const double* d_theta) {
+  bool any = false;
+  for (const GateDesc& g : p->gates) any = any || kind_nparams(g.kind) > 0;
+  if (any && !d_theta) return fail(QSV_ERR_INVALID_ARG, "d_theta is NULL");
+  return QSV_OK;
+}
+
+static double state_bytes_d(const qsv_state* s) { return (double)qsv_state_bytes(s->n, s->dt); }
+
+template <typename R>
+static qsv_status forward(qsv_state* s, Plan* p, void* psi) {
+  const double S = state_bytes_d(s);
+  for (size_t k = 0; k < p->gates.size(); ++k) {
+    const GateDesc& g = p->gates[k];
+    QSV_TRY(timed(s, forward_kernel_name(g), forward_bytes(g, S), [&] {
+      return launch_forward_gate<R>(psi, s->n, g, p->d_recs.as<GateRec>() + k, false, s->stream);
+    }));
+  }
+  return QSV_OK;
+}
+
+template <typename R>
+static qsv_status pauli(qsv_state* s, PauliPlan* hp, const void* psi, void* out, double2* ep) {
+  const double S = state_bytes_d(s);
+  return timed(s, "k_pauli", out ? 2 * S : S, [&] {
+    return launch_pauli<R>(psi, out, s->n, hp->d_groups.as<PauliGroup>(), (int)hp->groups.size(),
+                           hp->d_terms.as<PauliTerm>(), ep, s->nb, s->stream);
+  });
+}
+
+template <typename R>
+static qsv_status apply_circuit_t(qsv_state* s, Plan* p, const double* d_theta) {
+  HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
+                      p->d_recs.as<GateRec>(), s->stream));
+  return forward<R>(s, p, s->d_state);
+}
+
+extern "C" qsv_status qsv_apply_circuit(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                                        const double* d_theta, int32_t n_theta) {
+  QSV_TRY(check_handle(s));
+  QSV_TRY(qsv_validate_circuit(s->n, gates, n_gates, n_theta));
+  Plan* p = nullptr;
+  QSV_TRY(get_plan(s, gates, n_gates, n_theta, &p));
+  QSV_TRY(check_theta(p, d_theta));
+  return s->dt == QSV_C128 ? apply_circuit_t<double>(s, p, d_theta)
+                           : apply_circuit_t<float>(s, p, d_theta);
+}
+
+extern "C" qsv_status qsv_expectation_pauli_sum(qsv_state* s, const qsv_pauli_sum* H,
+                                                double* d_energy) {
+  QSV_TRY(check_handle(s));
+  QSV_TRY(qsv_validate_pauli_sum(s->n, H));
+  if (!d_energy) return fail(QSV_ERR_INVALID_ARG, "d_energy is NULL");
+  PauliPlan* hp = nullptr;
+  QSV_TRY(get_pauli(s, H, &hp));
+  QSV_TRY(s->epartials.ensure(sizeof(double2) * s->nb, s->stream));
+  double2* ep = s->epartials.as<double2>();
+  if (s->dt == QSV_C128) QSV_TRY(pauli<double>(s, hp, s->d_state, nullptr, ep));
+  else QSV_TRY(pauli<float>(s, hp, s->d_state, nullptr, ep));
+  HIP_TRY(launch_final_energy(ep, s->nb, d_energy, nullptr, s->stream));
+  return QSV_OK;
+}
+
+template <typename R>
+static qsv_status adjoint_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* d_theta,
+                            double* d_energy, double* d_grad) {
+  const hipStream_t st = s->stream;
+  const int n = s->n, nb = s->nb;
+  const size_t sb = qsv_state_bytes(n, s->dt);
+  void* phi = s->d_work;
+  void* lam = static_cast<char*>(s->d_work) + sb;
+  QSV_TRY(s->partials.ensure(sizeof(double2) * (size_t)(p->n_occ ? p->n_occ : 1) * nb, st));
+  QSV_TRY(s->epartials.ensure(sizeof(double2) * nb, st));
+  double2* part = s->partials.as<double2>();
+  double2* ep = s->epartials.as<double2>();
+
+  HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
+                      p->d_recs.as<GateRec>(), st));
+  // Algorithm 1: the first clone and the forward pass build psi in the phi buffer; lambda is then
+  // written directly as H psi (this also serves as the clone phi := psi), E = <psi|H psi>.
+  const double S = state_bytes_d(s);
+  QSV_TRY(timed(s, "k_copy", 2 * S, [&] { return launch_copy<R>(phi, s->d_state, n, st); }));
+  QSV_TRY(forward<R>(s, p, phi));
+  QSV_TRY(pauli<R>(s, hp, phi, lam, ep));
+  HIP_TRY(launch_final_energy(ep, nb, d_energy, nullptr, st));
+  // reverse sweep
+  for (int k = (int)p->gates.size() - 1; k >= 0; --k) {
+    const int slot = p->slot_of_gate[k];
+    const GateDesc& g = p->gates[k];
+    QSV_TRY(timed(s, backward_kernel_name(g), backward_bytes(g, S, k > 0), [&] {
+      return launch_backward_gate<R>(phi, lam, n, g, p->d_recs.as<GateRec>() + k, k > 0,
+                                     slot >= 0 ? part + (size_t)slot * nb : nullptr, nb, st);
+    }));
+  }
+  HIP_TRY(launch_final_grad(part, nb, p->d_param_ptr.as<int32_t>(), p->d_occ.as<int32_t>(),
+                            p->n_theta, d_grad, nullptr, st));
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_adjoint_gradient(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                                           const double* d_theta, int32_t n_theta,
+                                           const qsv_pauli_sum* H, double* d_energy,
+                                           double* d_grad) {
+  QSV_TRY(check_handle(s));
+  QSV_TRY(qsv_validate_circuit(s->n, gates, n_gates, n_theta));
+  QSV_TRY(qsv_validate_pauli_sum(s->n, H));
+  if (!d_energy) return fail(QSV_ERR_INVALID_ARG, "d_energy is NULL");
+  if (n_theta > 0 && !d_grad) return fail(QSV_ERR_INVALID_ARG, "d_grad is NULL");
+  Plan* p = nullptr;
+  QSV_TRY(get_plan(s, gates, n_gates, n_theta, &p));
+  QSV_TRY(check_theta(p, d_theta));
+  PauliPlan* hp = nullptr;
+  QSV_TRY(get_pauli(s, H, &hp));
+  return s->dt == QSV_C128 ? adjoint_t<double>(s, p, hp, d_theta, d_energy, d_grad)
+                           : adjoint_t<float>(s, p, hp, d_theta, d_energy, d_grad);
+}
+
+// ------------------------------------------------------------------------------------------------
+// GPU parameter-shift baseline
+// ------------------------------------------------------------------------------------------------
+template <typename R>
+static qsv_status param_shift_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* d_theta,
+                                int first, int count, double* d_grad) {
+  const hipStream_t st = s->stream;
+  const int n = s->n, nb = s->nb, nt = p->n_theta;
+  QSV_TRY(s->theta_scratch.ensure(sizeof(double) * (nt ? nt : 1), st));
+  QSV_TRY(s->energies.ensure(sizeof(double) * 2 * (count ? count : 1), st));
+  QSV_TRY(s->epartials.ensure(sizeof(double2) * nb, st));
+  double* th = s->theta_scratch.as<double>();
+  double* e = s->energies.as<double>();
+  double2* ep = s->epartials.as<double2>();
+  void* phi = s->d_work;
+  const double S = state_bytes_d(s);
+  const double half_pi = 1.57079632679489661923;
+  for (int i = 0; i < count; ++i) {
+    for (int side = 0; side < 2; ++side) {
+      HIP_TRY(launch_shift_theta(th, d_theta, nt, first + i, side ? -half_pi : half_pi, st));
+      HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), th,
+                          p->d_recs.as<GateRec>(), st));
+      QSV_TRY(timed(s, "k_copy", 2 * S, [&] { return launch_copy<R>(phi, s->d_state, n, st); }));
+      QSV_TRY(forward<R>(s, p, phi));
+      QSV_TRY(pauli<R>(s, hp, phi, nullptr, ep));
+      HIP_TRY(launch_final_energy(ep, nb, e + 2 * i + side, nullptr, st));
+    }
+  }
+  HIP_TRY(launch_ps_combine(d_grad, e, first, count, st));
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_param_shift_gradient(qsv_state* s, const qsv_gate* gates,
+                                               int32_t n_gates, const double* d_theta,
+                                               int32_t n_theta, const qsv_pauli_sum* H,
+                                               int32_t first, int32_t count, double* d_grad) {
+  QSV_TRY(check_handle(s));
+  QSV_TRY(qsv_validate_circuit(s->n, gates, n_gates, n_theta));
+  QSV_TRY(qsv_validate_pauli_sum(s->n, H));
+  if (first < 0 || count < 0 || (int64_t)first + count > n_theta)
+    return fail(QSV_ERR_INVALID_ARG, "entry range [%d, %d + %d) outside [0, %d)", first, first,
+                count, n_theta);
+  if (count > 0 && !d_grad) return fail(QSV_ERR_INVALID_ARG, "d_grad is NULL");
+  if (count > 0 && !d_theta) return fail(QSV_ERR_INVALID_ARG, "d_theta is NULL");
+  std::vector<int> uses(n_theta, 0);
+  for (int32_t k = 0; k < n_gates; ++k) {
+    const qsv_gate& g = gates[k];
+    if (g.kind == K_CRX || g.kind == K_CRY || g.kind == K_CRZ)
+      return fail(QSV_ERR_UNSUPPORTED, "gate %d: the two-term shift rule is not exact for "
+                  "controlled rotations", k);
+    for (int j = 0; j < kind_nparams(g.kind); ++j)
+      if (++uses[g.param[j]] > 1)
+        return fail(QSV_ERR_UNSUPPORTED, "parameter %d is used by more than one gate",
+                    g.param[j]);
+  }
+  Plan* p = nullptr;
+  QSV_TRY(get_plan(s, gates, n_gates, n_theta, &p));
+  PauliPlan* hp = nullptr;
+  QSV_TRY(get_pauli(s, H, &hp));
+  return s->dt == QSV_C128 ? param_shift_t<double>(s, p, hp, d_theta, first, count, d_grad)
+                           : param_shift_t<float>(s, p, hp, d_theta, first, count, d_grad);
+}
+
+// ------------------------------------------------------------------------------------------------
+// measurement
+// ------------------------------------------------------------------------------------------------
+static qsv_status drain_timer(qsv_state* s) {
+  Timer& t = s->timer;
+  if (t.pending.empty()) return QSV_OK;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (auto& pnd : t.pending) {
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, pnd.a, pnd.b));
+    qsv_kernel_stat& a = t.agg[pnd.name];
+    if (a.launches == 0) {
+      std::memset(&a, 0, sizeof a);
+      std::snprintf(a.name, sizeof a.name, "%s", pnd.name);
+    }
+    a.launches += 1;
+    a.total_ms += ms;
+    a.bytes += pnd.bytes;
+    t.pool.push_back(pnd.a);
+    t.pool.push_back(pnd.b);
+  }
+  t.pending.clear();
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_timing_enable(qsv_state* s, const char* name_filter) {
+  QSV_TRY(check_handle(s));
+  QSV_TRY(drain_timer(s));
+  s->timer.agg.clear();
+  s->timer.on = name_filter != nullptr;
+  s->timer.filter = name_filter ? name_filter : "";
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_timing_read(qsv_state* s, qsv_kernel_stat* out, int32_t max_out,
+                                      int32_t* n_out) {
+  QSV_TRY(check_handle(s));
+  if (max_out < 0 || (max_out > 0 && !out) || !n_out)
+    return fail(QSV_ERR_INVALID_ARG, "bad output array");
+  QSV_TRY(drain_timer(s));
+  std::vector<qsv_kernel_stat> v;
+  for (auto& kv : s->timer.agg) v.push_back(kv.second);
+  std::sort(v.begin(), v.end(), [](const qsv_kernel_stat& a, const qsv_kernel_stat& b) {
+    return a.total_ms > b.total_ms;
+  });
+  const int32_t m = std::min<int32_t>(max_out, (int32_t)v.size());
+  for (int32_t i = 0; i < m; ++i) out[i] = v[i];
+  *n_out = m;
+  return QSV_OK;
+}

@@ -1,0 +1,110 @@
+// Device helpers: complex arithmetic in registers, state loads/stores, index arithmetic and the
+// deterministic FP64 block reduction.
+#pragma once
+
+#include "qsv_internal.h"
+
+namespace qsv {
+
+template <typename R>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using T = double2;
+};
+template <>
+struct Vec2<float> {
+  using T = float2;
+};
+
+template <typename R>
+struct cx {
+  R r, i;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) {
+  return {a.r + b.r, a.i + b.i};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) {
+  return {a.r - b.r, a.i - b.i};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) {
+  return {s * a.r, s * a.i};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> conj(cx<R> a) {
+  return {a.r, -a.i};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> neg(cx<R> a) {
+  return {-a.r, -a.i};
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> load(const typename Vec2<R>::T* p, uint64_t j) {
+  typename Vec2<R>::T v = p[j];
+  return {v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void store(typename Vec2<R>::T* p, uint64_t j, cx<R> a) {
+  typename Vec2<R>::T v;
+  v.x = a.r;
+  v.y = a.i;
+  p[j] = v;
+}
+
+// Matrix entry k of a gate record, narrowed to the storage precision.
+template <typename R>
+__device__ __forceinline__ cx<R> mat(const GateRec* rec, int k) {
+  double2 d = rec->m[k];
+  return {(R)d.x, (R)d.y};
+}
+
+// acc += conj(l) * m, evaluated in FP64 whatever the storage precision.
+template <typename R>
+__device__ __forceinline__ void acc_dot(double2& acc, cx<R> l, cx<R> m) {
+  const double lr = l.r, li = l.i, mr = m.r, mi = m.i;
+  acc.x += lr * mr + li * mi;
+  acc.y += lr * mi - li * mr;
+}
+
+// Index of the g-th element of the set {j : bit q of j is 0}.
+__device__ __forceinline__ uint64_t insert_zero(uint64_t g, int q) {
+  const uint64_t low = g & ((1ull << q) - 1);
+  return ((g >> q) << (q + 1)) | low;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum of a complex FP64 value held by every thread: butterfly within each
+// wave, then the waves in index order. Result written by thread 0 to *out. All threads must call.
+template <int BLOCK>
+__device__ __forceinline__ void block_sum_store(double2 v, double2* out) {
+  __shared__ double2 sm[BLOCK / 64];
+  const double re = wave_sum(v.x), im = wave_sum(v.y);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sm[w] = make_double2(re, im);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 s = sm[0];
+    for (int k = 1; k < BLOCK / 64; ++k) {
+      s.x += sm[k].x;
+      s.y += sm[k].y;
+    }
+    *out = s;
+  }
+  __syncthreads();
+}
+
+}  // namespace qsv

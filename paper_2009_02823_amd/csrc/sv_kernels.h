@@ -1,0 +1,61 @@
+// Launchers of the gate-granular HIP kernels (one HBM pass per gate).
+#pragma once
+
+#include "qsv_internal.h"
+
+namespace qsv {
+
+// Per-gate matrices U and dU/dtheta_j from the device parameter vector (one thread per gate).
+hipError_t launch_prep(const GateDesc* d_gates, int n_gates, const double* d_theta, GateRec* d_rec,
+                       hipStream_t st);
+
+// Blocks used by every gate-granular launch on an n-qubit state (the partials stride).
+int sweep_blocks(int n);
+
+// psi <- U psi (adj = false) or U^dag psi for one gate.
+template <typename R>
+hipError_t launch_forward_gate(void* psi, int n, const GateDesc& g, const GateRec* d_rec, bool adj,
+                               hipStream_t st);
+
+// One step of the reverse sweep for gate g, in one pass over phi and lambda:
+//   phi <- U^dag phi;  for each parameter j of g: partial_j[block] = sum conj(lambda) dU_j phi;
+//   lambda <- U^dag lambda if undo_lam.
+// partial points at slot 0 of the gate's kind_nparams(g.kind) consecutive slots of nb entries.
+template <typename R>
+hipError_t launch_backward_gate(void* phi, void* lam, int n, const GateDesc& g,
+                                const GateRec* d_rec, bool undo_lam, double2* partial, int nb,
+                                hipStream_t st);
+
+// out <- H psi (if out != nullptr) and partial[block] = sum_j conj(psi_j) (H psi)_j.
+template <typename R>
+hipError_t launch_pauli(const void* psi, void* out, int n, const PauliGroup* d_groups, int n_groups,
+                        const PauliTerm* d_terms, double2* partial, int nb, hipStream_t st);
+
+template <typename R>
+hipError_t launch_copy(void* dst, const void* src, int n, hipStream_t st);
+
+template <typename R>
+hipError_t launch_reset(void* psi, int n, hipStream_t st);
+
+// grad[p] = 2 Re sum over the occurrences o of p (occ[ptr[p] .. ptr[p+1])) of
+//           sum_b partials[o * nb + b]; prods[o] = that complex sum if prods != nullptr.
+hipError_t launch_final_grad(const double2* partials, int nb, const int32_t* d_param_ptr,
+                             const int32_t* d_occ, int n_theta, double* d_grad, double2* d_prods,
+                             hipStream_t st);
+
+// *energy = Re sum_b partials[b]; energy_im (optional) = Im.
+hipError_t launch_final_energy(const double2* partials, int nb, double* d_energy,
+                               double* d_energy_im, hipStream_t st);
+
+// Kernel family names (substrings of the symbol names rocprof reports) of the launches above.
+const char* forward_kernel_name(const GateDesc& g);
+const char* backward_kernel_name(const GateDesc& g);
+
+// dst = src with dst[p] += delta (one block; n_theta >= 1).
+hipError_t launch_shift_theta(double* dst, const double* src, int n_theta, int p, double delta,
+                              hipStream_t st);
+
+// grad[first + i] = (e[2i] - e[2i + 1]) / 2 for i < count.
+hipError_t launch_ps_combine(double* grad, const double* e, int first, int count, hipStream_t st);
+
+}  // namespace qsv

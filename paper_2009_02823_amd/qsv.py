@@ -1,0 +1,269 @@
+"""Python binding of the qsv C-ABI (``include/qsv.h``): argument marshalling only.
+
+Device memory and streams come from PyTorch; every step of the computation runs in the HIP
+kernels of ``libqsv.so``. There is no CPU fallback: if the library is not built, or no GPU is
+present, the calls raise.
+
+Gate tables are ``int32`` arrays of shape ``(G, 6)`` with rows ``(kind, q0, q1, p0, p1, p2)`` (see
+``workloads``); Hamiltonians are ``codes`` ``uint8 (h, n)`` plus real ``coeffs`` ``float64 (h,)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqsv.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "qsv.h")
+
+QSV_OK, QSV_ERR_INVALID_ARG, QSV_ERR_UNSUPPORTED, QSV_ERR_OUT_OF_MEMORY, QSV_ERR_HIP, \
+    QSV_ERR_INTERNAL = range(6)
+QSV_C64, QSV_C128 = 0, 1
+DTYPES = {"c64": QSV_C64, "c128": QSV_C128}
+STATUS_NAMES = {0: "QSV_OK", 1: "QSV_ERR_INVALID_ARG", 2: "QSV_ERR_UNSUPPORTED",
+                3: "QSV_ERR_OUT_OF_MEMORY", 4: "QSV_ERR_HIP", 5: "QSV_ERR_INTERNAL"}
+
+
+class QsvError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class PauliSum(ctypes.Structure):
+    _fields_ = [("n_terms", ctypes.c_int32), ("codes", ctypes.c_void_p),
+                ("coeffs", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded ``libqsv.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2009_02823_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sigs = {
+        "qsv_validate_circuit": ([i32, P, i32, i32], i32),
+        "qsv_validate_pauli_sum": ([i32, P], i32),
+        "qsv_workspace_bytes": ([i32, i32], sz),
+        "qsv_state_bytes": ([i32, i32], sz),
+        "qsv_last_error": ([], ctypes.c_char_p),
+        "qsv_create": ([i32, i32, P, P, sz, P, PP], i32),
+        "qsv_destroy": ([P], i32),
+        "qsv_set_stream": ([P, P], i32),
+        "qsv_reset": ([P], i32),
+        "qsv_sync": ([P], i32),
+        "qsv_apply_circuit": ([P, P, i32, P, i32], i32),
+        "qsv_expectation_pauli_sum": ([P, P, P], i32),
+        "qsv_adjoint_gradient": ([P, P, i32, P, i32, P, P, P], i32),
+        "qsv_param_shift_gradient": ([P, P, i32, P, i32, P, i32, i32, P], i32),
+        "qsv_timing_enable": ([P, ctypes.c_char_p], i32),
+        "qsv_timing_read": ([P, P, i32, ctypes.POINTER(i32)], i32),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().qsv_last_error().decode()
+
+
+def check(status: int):
+    if status != QSV_OK:
+        raise QsvError(status, last_error())
+
+
+def as_gate_table(gates) -> np.ndarray:
+    g = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 6))
+    return g
+
+
+def pauli_struct(codes, coeffs, n_qubits):
+    codes = np.ascontiguousarray(np.asarray(codes, dtype=np.uint8).reshape(-1, n_qubits))
+    coeffs = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64).reshape(-1))
+    if codes.shape[0] != coeffs.shape[0]:
+        raise ValueError("codes and coeffs disagree on the number of terms")
+    s = PauliSum(codes.shape[0], codes.ctypes.data, coeffs.ctypes.data)
+    return s, (codes, coeffs)   # keep the arrays alive with the struct
+
+
+def validate_circuit(n_qubits: int, gates, n_theta: int):
+    g = as_gate_table(gates)
+    check(lib().qsv_validate_circuit(n_qubits, g.ctypes.data, g.shape[0], n_theta))
+
+
+def validate_pauli_sum(n_qubits: int, codes, coeffs):
+    s, keep = pauli_struct(codes, coeffs, n_qubits)
+    check(lib().qsv_validate_pauli_sum(n_qubits, ctypes.byref(s)))
+    del keep
+
+
+def state_bytes(n_qubits: int, dtype: str = "c128") -> int:
+    return int(lib().qsv_state_bytes(n_qubits, DTYPES[dtype]))
+
+
+def workspace_bytes(n_qubits: int, dtype: str = "c128") -> int:
+    return int(lib().qsv_workspace_bytes(n_qubits, DTYPES[dtype]))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class StateVector:
+    """A handle: the input state |in> (a torch tensor of 2^n complex amplitudes on the GPU) and a
+    two-state workspace, with all work ordered on one HIP stream."""
+
+    def __init__(self, n_qubits: int, dtype: str = "c128", device=None, stream=None):
+        torch = _torch()
+        L = lib()
+        if not torch.cuda.is_available():
+            raise RuntimeError("qsv needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.n = int(n_qubits)
+        self.dtype = dtype
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        cdt = torch.complex128 if dtype == "c128" else torch.complex64
+        with torch.cuda.device(self.device):
+            self.state = torch.empty(1 << self.n, dtype=cdt, device=self.device)
+            nbytes = workspace_bytes(self.n, dtype)
+            self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self._h = ctypes.c_void_p()
+            check(L.qsv_create(self.n, DTYPES[dtype], self.state.data_ptr(), self.work.data_ptr(),
+                               nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                               ctypes.byref(self._h)))
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().qsv_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- views of the workspace (phi and lambda of Algorithm 1)
+    def workspace_states(self):
+        torch = _torch()
+        cdt = self.state.dtype
+        half = self.work.numel() // 2
+        return (self.work[:half].view(cdt), self.work[half:2 * half].view(cdt))
+
+    def _theta(self, theta):
+        torch = _torch()
+        t = torch.as_tensor(theta, dtype=torch.float64)
+        if t.device != self.device:
+            t = t.to(self.device)
+        t = t.contiguous()
+        self._keep = t   # the enqueued kernels read it after the call returns
+        return t
+
+    # -- calls
+    def sync(self):
+        check(lib().qsv_sync(self._h))
+
+    def set_stream(self, stream):
+        check(lib().qsv_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
+    def reset(self):
+        check(lib().qsv_reset(self._h))
+
+    def apply_circuit(self, gates, theta=()):
+        g = as_gate_table(gates)
+        t = self._theta(theta)
+        check(lib().qsv_apply_circuit(self._h, g.ctypes.data, g.shape[0],
+                                      t.data_ptr() if t.numel() else None, t.numel()))
+        return self
+
+    def expectation(self, codes, coeffs, out=None):
+        torch = _torch()
+        s, keep = pauli_struct(codes, coeffs, self.n)
+        e = out if out is not None else torch.empty(1, dtype=torch.float64, device=self.device)
+        check(lib().qsv_expectation_pauli_sum(self._h, ctypes.byref(s), e.data_ptr()))
+        del keep
+        return e
+
+    def adjoint_gradient(self, gates, theta, codes, coeffs, energy=None, grad=None):
+        """(E, grad) of Algorithm 1 as float64 device tensors (E has shape (1,))."""
+        torch = _torch()
+        g = as_gate_table(gates)
+        t = self._theta(theta)
+        s, keep = pauli_struct(codes, coeffs, self.n)
+        e = energy if energy is not None else torch.empty(1, dtype=torch.float64,
+                                                         device=self.device)
+        gr = grad if grad is not None else torch.empty(t.numel(), dtype=torch.float64,
+                                                      device=self.device)
+        check(lib().qsv_adjoint_gradient(self._h, g.ctypes.data, g.shape[0],
+                                         t.data_ptr() if t.numel() else None, t.numel(),
+                                         ctypes.byref(s), e.data_ptr(),
+                                         gr.data_ptr() if gr.numel() else None))
+        del keep
+        return e, gr
+
+    def param_shift_gradient(self, gates, theta, codes, coeffs, first=0, count=None, grad=None):
+        """GPU parameter-shift entries [first, first + count) (the faithful O(P^2) baseline)."""
+        torch = _torch()
+        g = as_gate_table(gates)
+        t = self._theta(theta)
+        count = t.numel() - first if count is None else count
+        s, keep = pauli_struct(codes, coeffs, self.n)
+        gr = grad if grad is not None else torch.zeros(t.numel(), dtype=torch.float64,
+                                                      device=self.device)
+        check(lib().qsv_param_shift_gradient(self._h, g.ctypes.data, g.shape[0],
+                                             t.data_ptr() if t.numel() else None, t.numel(),
+                                             ctypes.byref(s), first, count,
+                                             gr.data_ptr() if gr.numel() else None))
+        del keep
+        return gr
+
+    def timing_enable(self, name_filter: str | None = ""):
+        check(lib().qsv_timing_enable(self._h, None if name_filter is None
+                                      else name_filter.encode()))
+
+    def timing_read(self, max_out: int = 64):
+        """[{name, launches, total_ms, bytes, avg_us, gbps}] sorted by total time."""
+        arr = (KernelStat * max_out)()
+        n = ctypes.c_int32(0)
+        check(lib().qsv_timing_read(self._h, arr, max_out, ctypes.byref(n)))
+        out = []
+        for k in range(n.value):
+            st = arr[k]
+            avg_ms = st.total_ms / max(st.launches, 1)
+            out.append({"name": st.name.decode(), "launches": int(st.launches),
+                        "total_ms": float(st.total_ms), "bytes": float(st.bytes),
+                        "avg_us": 1e3 * avg_ms,
+                        "bytes_per_launch": float(st.bytes) / max(st.launches, 1),
+                        "gbps": (float(st.bytes) / (st.total_ms * 1e-3) / 1e9)
+                        if st.total_ms > 0 else 0.0})
+        return out

@@ -1,0 +1,122 @@
+"""The C-ABI library loads, exports every function ``include/qsv.h`` declares, and validates its
+arguments on the host (no GPU, no compute calls)."""
+import ctypes
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2009_02823_amd import qsv
+from paper_2009_02823_amd import workloads as W
+
+
+def declared_functions():
+    text = open(qsv.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsv_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_north_star_calls():
+    names = declared_functions()
+    for f in ("qsv_create", "qsv_apply_circuit", "qsv_expectation_pauli_sum",
+              "qsv_adjoint_gradient"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = qsv.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", qsv.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (qsv_\w+)", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, f"declared but not exported: {missing}"
+    for f in declared_functions():
+        getattr(L, f)   # resolvable through the dynamic loader
+
+
+def test_sizes():
+    assert qsv.state_bytes(10, "c128") == 16 << 10
+    assert qsv.state_bytes(10, "c64") == 8 << 10
+    assert qsv.workspace_bytes(20, "c128") == 2 * (16 << 20)
+    assert qsv.state_bytes(0, "c128") == 0
+    assert qsv.state_bytes(35, "c128") == 0
+    assert qsv.lib().qsv_state_bytes(10, 7) == 0
+
+
+def test_valid_inputs_pass():
+    p = W.config1()
+    qsv.validate_circuit(p.n_qubits, p.gates, p.n_params)
+    qsv.validate_pauli_sum(p.n_qubits, p.codes, p.coeffs)
+    rng = np.random.default_rng(0)
+    g, P = W.random_circuit(rng, 5, 60, kinds=list(W.GATE_NAMES))
+    qsv.validate_circuit(5, g, P)
+    qsv.validate_circuit(5, np.zeros((0, 6), np.int32), 0)
+    qsv.validate_pauli_sum(5, np.zeros((0, 5), np.uint8), np.zeros(0))
+
+
+BAD_GATES = [
+    ("unknown kind", (99, 0, -1, -1, -1, -1)),
+    ("negative kind", (-1, 0, -1, -1, -1, -1)),
+    ("qubit out of range", (W.RX, 4, -1, 0, -1, -1)),
+    ("negative qubit", (W.H, -1, -1, -1, -1, -1)),
+    ("q1 on a one-qubit gate", (W.RY, 0, 1, 0, -1, -1)),
+    ("two-qubit gate on one qubit", (W.CNOT, 2, 2, -1, -1, -1)),
+    ("second qubit out of range", (W.CZ, 0, 4, -1, -1, -1)),
+    ("param out of range", (W.RZ, 0, -1, 3, -1, -1)),
+    ("missing param", (W.RZ, 0, -1, -1, -1, -1)),
+    ("param on a fixed gate", (W.X, 0, -1, 0, -1, -1)),
+    ("extra param slot", (W.RX, 0, -1, 0, 1, -1)),
+    ("U3 missing third param", (W.U3, 0, -1, 0, 1, -1)),
+]
+
+
+@pytest.mark.parametrize("name,row", BAD_GATES, ids=[b[0] for b in BAD_GATES])
+def test_invalid_gate_rejected(name, row):
+    good = [(W.H, 0, -1, -1, -1, -1), (W.RY, 1, -1, 0, -1, -1)]
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.validate_circuit(4, good + [row], 3)
+    assert e.value.status == qsv.QSV_ERR_INVALID_ARG
+    assert "gate 2" in str(e.value)
+
+
+def test_invalid_sizes_rejected():
+    L = qsv.lib()
+    assert L.qsv_validate_circuit(0, None, 0, 0) == qsv.QSV_ERR_INVALID_ARG
+    assert L.qsv_validate_circuit(35, None, 0, 0) == qsv.QSV_ERR_INVALID_ARG
+    assert L.qsv_validate_circuit(3, None, 2, 0) == qsv.QSV_ERR_INVALID_ARG
+    assert L.qsv_validate_circuit(3, None, -1, 0) == qsv.QSV_ERR_INVALID_ARG
+    assert L.qsv_validate_pauli_sum(3, None) == qsv.QSV_ERR_INVALID_ARG
+
+
+def test_invalid_pauli_rejected():
+    codes = np.zeros((2, 3), np.uint8)
+    codes[1, 2] = 4
+    with pytest.raises(qsv.QsvError, match="Pauli code 4 at term 1 qubit 2"):
+        qsv.validate_pauli_sum(3, codes, [1.0, 2.0])
+    with pytest.raises(qsv.QsvError, match="not finite"):
+        qsv.validate_pauli_sum(3, np.zeros((2, 3), np.uint8), [1.0, np.nan])
+    with pytest.raises(qsv.QsvError, match="not finite"):
+        qsv.validate_pauli_sum(3, np.zeros((1, 3), np.uint8), [np.inf])
+
+
+def test_create_rejects_bad_arguments_before_touching_the_device():
+    L = qsv.lib()
+    h = ctypes.c_void_p()
+    ws = qsv.workspace_bytes(4, "c128")
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    assert L.qsv_create(4, 1, None, fake, ws, None, ctypes.byref(h)) == qsv.QSV_ERR_INVALID_ARG
+    assert L.qsv_create(0, 1, fake, fake, ws, None, ctypes.byref(h)) == qsv.QSV_ERR_INVALID_ARG
+    assert L.qsv_create(4, 9, fake, fake, ws, None, ctypes.byref(h)) == qsv.QSV_ERR_INVALID_ARG
+    assert L.qsv_create(4, 1, fake, fake, ws - 1, None, ctypes.byref(h)) == \
+        qsv.QSV_ERR_INVALID_ARG
+    assert "workspace" in qsv.last_error()
+    assert L.qsv_create(4, 1, ctypes.c_void_p((1 << 20) + 8), fake, ws, None,
+                        ctypes.byref(h)) == qsv.QSV_ERR_INVALID_ARG
+    assert "aligned" in qsv.last_error()
+    assert L.qsv_create(4, 1, fake, fake, ws, None, None) == qsv.QSV_ERR_INVALID_ARG
+    assert not h.value
+    # calls on a NULL handle are rejected, destroy(NULL) is a no-op
+    assert L.qsv_reset(None) == qsv.QSV_ERR_INVALID_ARG
+    assert L.qsv_sync(None) == qsv.QSV_ERR_INVALID_ARG
+    assert L.qsv_destroy(None) == qsv.QSV_OK

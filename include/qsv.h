@@ -198,6 +198,41 @@ qsv_status qsv_timing_enable(qsv_state* s, const char* name_filter);
    up to max_out of them (sorted by total time, largest first) to out; *n_out = number copied. */
 qsv_status qsv_timing_read(qsv_state* s, qsv_kernel_stat* out, int32_t max_out, int32_t* n_out);
 
+/* ---- fusion ------------------------------------------------------------------------------- */
+
+/* Execution mode of a handle's forward pass and reverse sweep:
+     mode = 0   one HBM pass per gate (gate-granular kernels);
+     mode = 1   fused passes: each pass loads every tile of 2^(reg_qubits + threads_log2)
+                amplitudes once (workgroups of 2^threads_log2 threads, 2^reg_qubits amplitudes of
+                each state per thread), applies a scheduled run of gates in registers and LDS, and
+                stores it once; supported (reg_qubits, threads_log2): (2..3, 8) for complex128,
+                (2..4, 8) for complex64, (2..3, 6) for both;
+     mode = -1  automatic (the default): fused with a size-dependent geometry when the state holds
+                a tile, gate-granular otherwise. */
+qsv_status qsv_set_fusion(qsv_state* s, int32_t mode, int32_t reg_qubits, int32_t threads_log2);
+
+/* The geometry the handle currently runs with: *mode = 1 (fused, with *reg_qubits and
+   *threads_log2) or 0 (gate-granular). */
+qsv_status qsv_get_fusion(qsv_state* s, int32_t* mode, int32_t* reg_qubits, int32_t* threads_log2);
+
+/* Host-only description of the fused schedule of a circuit (no GPU needed): the order gates run
+   in, and for each executed gate its pass and register phase; the physical-qubit masks of every
+   pass's tile and every phase's register qubits. backward != 0 describes the reverse sweep (gates
+   taken from last to first). All arrays are caller-owned with n_gates entries. */
+typedef struct {
+  int32_t n_passes;
+  int32_t n_phases;
+  int32_t* order;
+  int32_t* pass_of;
+  int32_t* phase_of;
+  uint64_t* tile_mask;
+  uint64_t* reg_mask;
+} qsv_schedule_info;
+
+qsv_status qsv_schedule_describe(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates,
+                                 int32_t backward, int32_t reg_qubits, int32_t threads_log2,
+                                 qsv_schedule_info* out);
+
 #ifdef __cplusplus
 }
 #endif

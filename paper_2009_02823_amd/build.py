@@ -24,6 +24,10 @@ CFLAGS = [
     "-Wno-unused-function", "-Wno-unused-result",
     # packed-FP32 instructions stay off on these boxes
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep per-branch register-array code apart: sinking/hoisting the common arithmetic of the
+    # per-register-position branches turns static array indices into address selects, which
+    # forces the thread's amplitude arrays into scratch memory
+    "-mllvm", "-simplifycfg-sink-common=false", "-mllvm", "-simplifycfg-hoist-common=false",
     "-I", CSRC, "-I", INCLUDE,
 ]
 

@@ -1,0 +1,114 @@
+// Fused passes: a run of gates applied to every tile of 2^t amplitudes in one HBM round trip.
+//
+// A pass names t "tile qubits"; a tile is the set of 2^t amplitudes that share the values of all
+// other ("outer") qubits. Tile bit s stands for physical qubit tile[s] (ascending). A workgroup of
+// 2^w threads holds a tile in registers, 2^r amplitudes per thread (t = r + w). In each "phase" r
+// chosen tile bits are register bits (thread-private array index) and the other w bits come from
+// the thread index. Gates whose non-diagonal targets are register bits run entirely in registers;
+// diagonal gates and controls may sit on any tile bit. Between phases the tile is re-laid out
+// through LDS. The direct layout D (thread bits = tile bits 0..w-1, register bits = w..t-1) is the
+// one used for the coalesced loads and stores from HBM.
+#pragma once
+
+#include <vector>
+
+#include "qsv_internal.h"
+
+namespace qsv {
+
+constexpr int kMaxTileBits = 14;
+constexpr int kMaxRegBits = 5;
+constexpr int kMaxSlotsPerPass = 64;
+constexpr int kMaxOpsPerPass = 1024;
+
+enum FusedOpType : uint8_t {
+  // lean op set (every bit location compile-time in registers or constant per thread)
+  FOP_RY = 0,       // exp(-i t Y/2) on register position k0
+  FOP_RX = 1,       // exp(-i t X/2) on register position k0
+  FOP_RZ = 2,       // exp(-i t Z/2) on tile bit s0
+  FOP_CNOT = 3,     // control tile bit s0, target register position k0
+  FOP_CZ = 4,       // tile bits s0, s1
+  FOP_DENSE1 = 5,   // fixed 2x2 on register position k0 (no parameter)
+  FOP_DIAG1 = 6,    // fixed diagonal 2x2 on tile bit s0 (no parameter)
+  // general op set (parameterised matrices with explicit derivatives, controlled and two-qubit)
+  FOP_PDENSE1 = 7,  // 2x2 with 1 or 3 parameters on register position k0 (U3)
+  FOP_PDIAG1 = 8,   // diagonal 2x2 with a parameter on tile bit s0 (PHASE)
+  FOP_CDENSE1 = 9,  // control tile bit s0, 2x2 block (rows/cols 2,3 of the 4x4) on register k0
+  FOP_DIAG2 = 10,   // diagonal 4x4 on tile bits s0 (q0), s1 (q1)
+  FOP_DENSE2 = 11,  // 4x4 on register positions k0 (q0), k1 (q1)
+  FOP_FIRST_GENERAL = FOP_PDENSE1,
+};
+
+// A tile bit referenced by an op (control or diagonal bit) is either a register bit of the phase
+// (flag set, register position in ks0/ks1) or a thread bit (its value is constant per thread).
+enum : uint8_t { FOPF_S0_REG = 1, FOPF_S1_REG = 2 };
+
+struct FusedOp {
+  uint8_t type;
+  uint8_t k0, k1;   // register positions of targets
+  uint8_t s0, s1;   // tile bits (controls, diagonal bits)
+  uint8_t np;       // products (derivative parameters) of this op in the reverse sweep
+  uint8_t lslot;    // local slot of the first product
+  uint8_t flags;    // FOPF_*
+  uint8_t ks0, ks1; // register positions of s0 / s1 when they are register bits
+  uint8_t pad[2];
+  int32_t gate;     // gate record index
+};
+
+struct PhaseDesc {
+  int32_t op_end;                 // ops [previous op_end, op_end) of the pass
+  int8_t regbit[kMaxRegBits];     // tile bit of each register position
+  int8_t pad[3];
+};
+
+struct PassDesc {
+  int32_t nt;                     // tile bits t
+  int32_t n_outer;                // N - t
+  int8_t tile[kMaxTileBits];      // physical qubit of tile bit s (ascending)
+  int8_t pad0[2];
+  int8_t outer[40];               // physical qubits outside the tile (ascending)
+  int32_t phase_begin, phase_end; // into the phase table
+  int32_t op_begin;               // into the op table (phase op_end values are relative)
+  int32_t n_slots;                // products accumulated by this pass
+  int32_t slot_begin;             // into the slot map (local slot -> global reduction slot)
+  int32_t general;                // 1 if any op of the pass is of the general set
+};
+
+// A schedule of one gate sequence (forward order, or the reverse sweep) as host tables ready to
+// be copied to the device.
+struct Schedule {
+  int t = 0, r = 0, w = 0;
+  std::vector<PassDesc> passes;
+  std::vector<PhaseDesc> phases;
+  std::vector<FusedOp> ops;
+  std::vector<int32_t> slot_map;
+  // for inspection: gate order and pass/phase of each executed gate
+  std::vector<int32_t> order, pass_of, phase_of;
+  std::vector<uint64_t> tile_mask, reg_mask;
+};
+
+// Builds the schedule of `gates` taken in order `seq` (gate indices). slot_of_gate[k] is the first
+// global reduction slot of gate k (or -1); it is only used when `backward` is set.
+// Returns false (with msg) if the gates cannot be scheduled with these sizes.
+bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector<int>& seq,
+                    const std::vector<int32_t>& slot_of_gate, bool backward, int t, int r, int w,
+                    Schedule& out, std::string* msg);
+
+// Launchers of the fused pass kernels. Configurations (r, w) available: see fused_kernels.hip.
+bool fused_config_supported(int r, int w, bool c128);
+
+// `general` selects the kernel instance that also handles the general op set.
+template <typename R>
+hipError_t launch_fused_forward(const void* src, void* dst, int n, const PassDesc* d_pass,
+                                const PhaseDesc* d_phases, const FusedOp* d_ops,
+                                const GateRec* d_recs, int r, int w, bool general, int grid,
+                                hipStream_t st);
+
+template <typename R>
+hipError_t launch_fused_backward(void* phi, void* lam, int n, const PassDesc* d_pass,
+                                 const PhaseDesc* d_phases, const FusedOp* d_ops,
+                                 const int32_t* d_slot_map, const GateRec* d_recs,
+                                 double2* partials, int nb, int r, int w, bool general, int grid,
+                                 hipStream_t st);
+
+}  // namespace qsv

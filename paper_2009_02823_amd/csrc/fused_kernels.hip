@@ -1,0 +1,838 @@
+// Fused pass kernels for gfx950 (see fused.h for the tile/phase model).
+//
+// One workgroup of 2^W threads processes tiles of 2^(RB+W) amplitudes; every thread keeps 2^RB
+// amplitudes of each state in registers. Loads and stores use the direct layout (consecutive lanes
+// on consecutive tile bits, the low tile bits being the lowest physical qubits), so every wave
+// reads and writes runs of contiguous amplitudes. Register phases are changed by a transpose
+// through LDS with an XOR swizzle of the element index against bank conflicts.
+//
+// The reverse-sweep kernel applies, per gate, the loop body of Algorithm 1 to both states held in
+// registers: the product of lambda with the gate derivative applied to phi, then
+// phi <- U^dag phi and lambda <- U^dag lambda. For the rotations R = exp(-i t G/2) the product
+// uses dR/dt = -(i/2) G R (paper App. A): Re <lambda|dR phi'> = (1/2) Im <lambda|G|phi> with phi
+// taken before un-applying R; other parameterised gates use their explicit derivative matrices.
+// Per-thread products (FP64) are summed over the wave with DPP row operations, accumulated per
+// wave in LDS over all tiles of the workgroup, and written as one partial per workgroup and
+// product slot; no atomics, fixed order.
+//
+// Two instances per geometry: the lean one handles RX, RY, RZ, CNOT, CZ and fixed one-qubit
+// gates, with every control/diagonal bit resolved either at compile time (register bit) or once
+// per thread (thread bit); the general one adds parameterised dense/diagonal gates with explicit
+// derivatives, controlled rotations and two-qubit rotations.
+#include "fused.h"
+#include "qsv_device.h"
+
+namespace qsv {
+
+template <typename R>
+struct Swz;
+// 64 banks x 4 bytes: fold higher index bits into the bank-selecting bits
+template <>
+struct Swz<double> {  // 16-byte elements, 16 per bank row
+  static __device__ __forceinline__ uint32_t f(uint32_t x) {
+    return x ^ (((x >> 4) ^ (x >> 8) ^ (x >> 12)) & 15u);
+  }
+};
+template <>
+struct Swz<float> {  // 8-byte elements, 32 per bank row
+  static __device__ __forceinline__ uint32_t f(uint32_t x) { return x ^ (((x >> 5) ^ (x >> 10)) & 31u); }
+};
+
+// ---------------------------------------------------------------------------------------------
+// Layouts
+// ---------------------------------------------------------------------------------------------
+template <int T>
+__device__ __forceinline__ uint32_t thread_deposit(uint32_t rmask, uint32_t tid) {
+  uint32_t x = 0;
+  int j = 0;
+#pragma unroll
+  for (int s = 0; s < T; ++s) {
+    if (!((rmask >> s) & 1u)) {
+      x |= ((tid >> j) & 1u) << s;
+      ++j;
+    }
+  }
+  return x;
+}
+
+template <int RB>
+struct Layout {
+  int8_t rb[RB];   // tile bit of each register position
+  uint32_t tdep;   // thread part of the tile index
+};
+
+template <int RB, int T>
+__device__ __forceinline__ void make_layout(Layout<RB>& L, const int8_t* regbit, uint32_t tid) {
+  uint32_t rmask = 0;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    L.rb[k] = regbit[k];
+    rmask |= 1u << regbit[k];
+  }
+  L.tdep = thread_deposit<T>(rmask, tid);
+}
+
+template <int RB>
+__device__ __forceinline__ uint32_t reg_deposit(const Layout<RB>& L, int ri) {
+  uint32_t x = 0;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) x |= (uint32_t)((ri >> k) & 1) << L.rb[k];
+  return x;
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void relayout(cx<R>* a, const Layout<RB>& from, const Layout<RB>& to,
+                                         typename Vec2<R>::T* lds) {
+  constexpr int NA = 1 << RB;
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    typename Vec2<R>::T v;
+    v.x = a[ri].r;
+    v.y = a[ri].i;
+    lds[Swz<R>::f(from.tdep | reg_deposit<RB>(from, ri))] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    const typename Vec2<R>::T v = lds[Swz<R>::f(to.tdep | reg_deposit<RB>(to, ri))];
+    a[ri].r = v.x;
+    a[ri].i = v.y;
+  }
+  __syncthreads();
+}
+
+template <int RB>
+__device__ __forceinline__ bool same_layout(const Layout<RB>& a, const int8_t* rb) {
+  bool s = true;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) s = s && a.rb[k] == rb[k];
+  return s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Lean ops. ADJ selects U^dag (reverse sweep) instead of U.
+// ---------------------------------------------------------------------------------------------
+// cos(t/2), sin(t/2) of a rotation from its record: RY m[2] = s, RX m[1] = -i s, RZ m[0] = c - i s
+template <typename R>
+__device__ __forceinline__ void rot_cs(const GateRec* rec, int type, R& c, R& s) {
+  const double2 m0 = rec->m[0];
+  c = (R)m0.x;
+  if (type == FOP_RY) s = (R)rec->m[2].x;
+  else if (type == FOP_RX) s = (R)(-rec->m[1].y);
+  else s = (R)(-m0.y);
+}
+
+template <typename R, int NA, int K, bool ADJ>
+__device__ __forceinline__ void ry_k(cx<R>* a, R c, R s) {
+  const R sp = ADJ ? -s : s;  // U = [[c, -s], [s, c]]
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    const cx<R> x = a[ri], y = a[rj];
+    a[ri] = {c * x.r - sp * y.r, c * x.i - sp * y.i};
+    a[rj] = {sp * x.r + c * y.r, sp * x.i + c * y.i};
+  }
+}
+
+template <typename R, int NA, int K, bool ADJ>
+__device__ __forceinline__ void rx_k(cx<R>* a, R c, R s) {
+  const R sp = ADJ ? -s : s;  // U = [[c, -i s], [-i s, c]]
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    const cx<R> x = a[ri], y = a[rj];
+    a[ri] = {c * x.r + sp * y.i, c * x.i - sp * y.r};
+    a[rj] = {c * y.r + sp * x.i, c * y.i - sp * x.r};
+  }
+}
+
+// multiply by the phase c + i t
+template <typename R>
+__device__ __forceinline__ cx<R> phase_mul(cx<R> z, R c, R t) {
+  return {c * z.r - t * z.i, c * z.i + t * z.r};
+}
+
+// RZ = diag(c - i s, c + i s): bit b multiplies by c + i (b ? s : -s) (negated for U^dag)
+template <typename R, int NA, int K, bool ADJ>
+__device__ __forceinline__ void rz_k(cx<R>* a, R c, R s) {
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    const bool b = (ri >> K) & 1;
+    const R t = (b != ADJ) ? s : -s;
+    a[ri] = phase_mul(a[ri], c, t);
+  }
+}
+
+template <typename R, int NA, bool ADJ>
+__device__ __forceinline__ void rz_thr(cx<R>* a, R c, R s, bool b) {
+  const R t = (b != ADJ) ? s : -s;
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) a[ri] = phase_mul(a[ri], c, t);
+}
+
+// CNOT with control and target both register positions: swaps chosen at compile time.
+template <typename R, int NA, int KC, int KT>
+__device__ __forceinline__ void cnot_rr(cx<R>* a) {
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if ((ri & (1 << KT)) || !(ri & (1 << KC))) continue;
+    const cx<R> x = a[ri];
+    a[ri] = a[ri | (1 << KT)];
+    a[ri | (1 << KT)] = x;
+  }
+}
+
+// CNOT with the control on a thread bit: swap the target pairs of the threads whose bit is set.
+template <typename R, int NA, int KT>
+__device__ __forceinline__ void cnot_tr(cx<R>* a, bool on) {
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << KT)) continue;
+    const int rj = ri | (1 << KT);
+    const cx<R> x = a[ri], y = a[rj];
+    a[ri] = sel(on, y, x);
+    a[rj] = sel(on, x, y);
+  }
+}
+
+// Negate the amplitudes whose register bits in MASK are all set, when `on`.
+template <typename R, int NA, int MASK>
+__device__ __forceinline__ void neg_where(cx<R>* a, bool on) {
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if ((ri & MASK) != MASK) continue;
+    a[ri] = sel(on, neg(a[ri]), a[ri]);
+  }
+}
+
+template <typename R, int NA, int K>
+__device__ __forceinline__ void dense1_k(cx<R>* a, cx<R> m00, cx<R> m01, cx<R> m10, cx<R> m11) {
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    const cx<R> x = a[ri], y = a[rj];
+    a[ri] = m00 * x + m01 * y;
+    a[rj] = m10 * x + m11 * y;
+  }
+}
+
+template <typename R, int NA, int K>
+__device__ __forceinline__ void diag1_k(cx<R>* a, cx<R> d0, cx<R> d1) {
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) a[ri] = (((ri >> K) & 1) ? d1 : d0) * a[ri];
+}
+
+// ---- runtime register position -> compile-time template instance
+#define QSV_AT_K(NAME, CALL)                                                   \
+  template <typename R, int RB, bool ADJ, int K = 0, typename... Args>        \
+  __device__ __forceinline__ void NAME(int k, cx<R>* a, Args... args) {       \
+    if constexpr (K < RB) {                                                    \
+      if (k == K) CALL;                                                        \
+      else NAME<R, RB, ADJ, K + 1>(k, a, args...);                             \
+    }                                                                          \
+  }
+QSV_AT_K(ry_at, (ry_k<R, 1 << RB, K, ADJ>(a, args...)))
+QSV_AT_K(rx_at, (rx_k<R, 1 << RB, K, ADJ>(a, args...)))
+QSV_AT_K(rz_at, (rz_k<R, 1 << RB, K, ADJ>(a, args...)))
+QSV_AT_K(cnot_tr_at, (cnot_tr<R, 1 << RB, K>(a, args...)))
+QSV_AT_K(dense1_at, (dense1_k<R, 1 << RB, K>(a, args...)))
+QSV_AT_K(diag1_at, (diag1_k<R, 1 << RB, K>(a, args...)))
+#undef QSV_AT_K
+
+template <typename R, int RB, int KC = 0, int KT = 0>
+__device__ __forceinline__ void cnot_rr_at(int kc, int kt, cx<R>* a) {
+  if constexpr (KC < RB) {
+    if constexpr (KT < RB) {
+      if constexpr (KC != KT) {
+        if (kc == KC && kt == KT) {
+          cnot_rr<R, 1 << RB, KC, KT>(a);
+          return;
+        }
+      }
+      cnot_rr_at<R, RB, KC, KT + 1>(kc, kt, a);
+    } else {
+      cnot_rr_at<R, RB, KC + 1, 0>(kc, kt, a);
+    }
+  }
+}
+
+template <typename R, int RB, int KA = 0, int KB = 0>
+__device__ __forceinline__ void neg_rr_at(int ka, int kb, cx<R>* a, bool on) {
+  if constexpr (KA < RB) {
+    if constexpr (KB < RB) {
+      if (ka == KA && kb == KB) {
+        neg_where<R, 1 << RB, (1 << KA) | (1 << KB)>(a, on);
+        return;
+      }
+      neg_rr_at<R, RB, KA, KB + 1>(ka, kb, a, on);
+    } else {
+      neg_rr_at<R, RB, KA + 1, 0>(ka, kb, a, on);
+    }
+  }
+}
+
+__device__ __forceinline__ bool thread_bit(uint32_t tdep, int s) { return (tdep >> s) & 1u; }
+
+// Applies a lean op (or its inverse when ADJ) to one state's registers.
+template <typename R, int RB, bool ADJ>
+__device__ __forceinline__ void apply_lean(const FusedOp& op, const GateRec* rec, cx<R>* a,
+                                           uint32_t tdep) {
+  constexpr int NA = 1 << RB;
+  switch (op.type) {
+    case FOP_RY: {
+      R c, s;
+      rot_cs<R>(rec, FOP_RY, c, s);
+      ry_at<R, RB, ADJ>(op.k0, a, c, s);
+      break;
+    }
+    case FOP_RX: {
+      R c, s;
+      rot_cs<R>(rec, FOP_RX, c, s);
+      rx_at<R, RB, ADJ>(op.k0, a, c, s);
+      break;
+    }
+    case FOP_RZ: {
+      R c, s;
+      rot_cs<R>(rec, FOP_RZ, c, s);
+      if (op.flags & FOPF_S0_REG) rz_at<R, RB, ADJ>(op.ks0, a, c, s);
+      else rz_thr<R, NA, ADJ>(a, c, s, thread_bit(tdep, op.s0));
+      break;
+    }
+    case FOP_CNOT:  // self-inverse
+      if (op.flags & FOPF_S0_REG) cnot_rr_at<R, RB>(op.ks0, op.k0, a);
+      else cnot_tr_at<R, RB, ADJ>(op.k0, a, thread_bit(tdep, op.s0));
+      break;
+    case FOP_CZ: {  // self-inverse
+      const bool r0 = op.flags & FOPF_S0_REG, r1 = op.flags & FOPF_S1_REG;
+      if (r0 && r1) neg_rr_at<R, RB>(op.ks0, op.ks1, a, true);
+      else if (r0) neg_rr_at<R, RB>(op.ks0, op.ks0, a, thread_bit(tdep, op.s1));
+      else if (r1) neg_rr_at<R, RB>(op.ks1, op.ks1, a, thread_bit(tdep, op.s0));
+      else neg_where<R, NA, 0>(a, thread_bit(tdep, op.s0) && thread_bit(tdep, op.s1));
+      break;
+    }
+    case FOP_DENSE1: {
+      cx<R> m00 = mat<R>(rec, 0), m01 = mat<R>(rec, 1), m10 = mat<R>(rec, 2), m11 = mat<R>(rec, 3);
+      if (ADJ) {
+        const cx<R> t = m01;
+        m00 = conj(m00); m11 = conj(m11); m01 = conj(m10); m10 = conj(t);
+      }
+      dense1_at<R, RB, ADJ>(op.k0, a, m00, m01, m10, m11);
+      break;
+    }
+    case FOP_DIAG1: {
+      cx<R> d0 = mat<R>(rec, 0), d1 = mat<R>(rec, 3);
+      if (ADJ) { d0 = conj(d0); d1 = conj(d1); }
+      if (op.flags & FOPF_S0_REG) {
+        diag1_at<R, RB, ADJ>(op.ks0, a, d0, d1);
+      } else {
+        const cx<R> d = sel(thread_bit(tdep, op.s0), d1, d0);
+#pragma unroll
+        for (int ri = 0; ri < NA; ++ri) a[ri] = d * a[ri];
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Products of the lean parameterised ops: Re <lambda|dR phi'> = (1/2) Im <lambda|G|phi>, phi
+// before the un-application.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double im_cm(double lr, double li, double fr, double fi) {
+  return lr * fi - li * fr;  // Im(conj(l) f)
+}
+__device__ __forceinline__ double re_cm(double lr, double li, double fr, double fi) {
+  return lr * fr + li * fi;  // Re(conj(l) f)
+}
+
+template <typename R, int NA, int K>
+__device__ __forceinline__ double prod_ry_k(const cx<R>* f, const cx<R>* l) {
+  double s = 0;  // Y f = (-i f1, i f0)
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    s += re_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i) - re_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i);
+  }
+  return 0.5 * s;
+}
+
+template <typename R, int NA, int K>
+__device__ __forceinline__ double prod_rx_k(const cx<R>* f, const cx<R>* l) {
+  double s = 0;  // X f = (f1, f0)
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    s += im_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i) + im_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i);
+  }
+  return 0.5 * s;
+}
+
+template <typename R, int NA, int K>
+__device__ __forceinline__ double prod_rz_k(const cx<R>* f, const cx<R>* l) {
+  double s = 0;  // Z f = (-1)^bit f
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    const double v = im_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i);
+    s += ((ri >> K) & 1) ? -v : v;
+  }
+  return 0.5 * s;
+}
+
+#define QSV_PROD_AT(NAME, FN)                                                       \
+  template <typename R, int RB, int K = 0>                                          \
+  __device__ __forceinline__ double NAME(int k, const cx<R>* f, const cx<R>* l) {   \
+    if constexpr (K < RB) {                                                         \
+      if (k == K) return FN<R, 1 << RB, K>(f, l);                                    \
+      return NAME<R, RB, K + 1>(k, f, l);                                            \
+    } else {                                                                        \
+      return 0.0;                                                                   \
+    }                                                                               \
+  }
+QSV_PROD_AT(prod_ry_at, prod_ry_k)
+QSV_PROD_AT(prod_rx_at, prod_rx_k)
+QSV_PROD_AT(prod_rz_at, prod_rz_k)
+#undef QSV_PROD_AT
+
+template <typename R, int RB>
+__device__ __forceinline__ double lean_product(const FusedOp& op, const cx<R>* f, const cx<R>* l,
+                                               uint32_t tdep) {
+  constexpr int NA = 1 << RB;
+  if (op.type == FOP_RY) return prod_ry_at<R, RB>(op.k0, f, l);
+  if (op.type == FOP_RX) return prod_rx_at<R, RB>(op.k0, f, l);
+  if (op.flags & FOPF_S0_REG) return prod_rz_at<R, RB>(op.ks0, f, l);
+  double s = 0;
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) s += im_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i);
+  return thread_bit(tdep, op.s0) ? -0.5 * s : 0.5 * s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// General ops (tile bits evaluated per amplitude)
+// ---------------------------------------------------------------------------------------------
+template <int RB>
+__device__ __forceinline__ bool bit_of(int s, const Layout<RB>& L, int ri) {
+  return ((L.tdep | reg_deposit<RB>(L, ri)) >> s) & 1u;
+}
+
+template <typename R, int NA, int K0, int K1>
+__device__ __forceinline__ void dense2_k(cx<R>* a, const GateRec* rec, int off, bool adj) {
+  cx<R> m[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      m[4 * i + j] = sel(adj, conj(mat<R>(rec, off + 4 * j + i)), mat<R>(rec, off + 4 * i + j));
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & ((1 << K0) | (1 << K1))) continue;
+    const int idx[4] = {ri, ri | (1 << K1), ri | (1 << K0), ri | (1 << K0) | (1 << K1)};
+    cx<R> v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = a[idx[k]];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      cx<R> s = {0, 0};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s = s + m[4 * rr + k] * v[k];
+      a[idx[rr]] = s;
+    }
+  }
+}
+
+template <typename R, int RB, int K0 = 0, int K1 = 0>
+__device__ __forceinline__ void dense2_at(int k0, int k1, cx<R>* a, const GateRec* rec, int off,
+                                          bool adj) {
+  if constexpr (K0 < RB) {
+    if constexpr (K1 < RB) {
+      if constexpr (K0 != K1) {
+        if (k0 == K0 && k1 == K1) {
+          dense2_k<R, 1 << RB, K0, K1>(a, rec, off, adj);
+          return;
+        }
+      }
+      dense2_at<R, RB, K0, K1 + 1>(k0, k1, a, rec, off, adj);
+    } else {
+      dense2_at<R, RB, K0 + 1, 0>(k0, k1, a, rec, off, adj);
+    }
+  }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ cx<R> pick_diag4(const cx<R>* d, bool b0, bool b1) {
+  const cx<R> lo = sel(b1, d[1], d[0]);
+  const cx<R> hi = sel(b1, d[3], d[2]);
+  return sel(b0, hi, lo);
+}
+
+template <typename R, int RB, bool ADJ>
+__device__ __forceinline__ void apply_general(const FusedOp& op, const GateRec* rec, cx<R>* a,
+                                              const Layout<RB>& L) {
+  constexpr int NA = 1 << RB;
+  switch (op.type) {
+    case FOP_PDENSE1: case FOP_CDENSE1: {
+      const bool ctl = op.type == FOP_CDENSE1;
+      const int o = ctl ? 10 : 0, st = ctl ? 4 : 2;  // 2x2 block and its row stride
+      cx<R> m00 = mat<R>(rec, o), m01 = mat<R>(rec, o + 1), m10 = mat<R>(rec, o + st),
+            m11 = mat<R>(rec, o + st + 1);
+      if (ADJ) {
+        const cx<R> t = m01;
+        m00 = conj(m00); m11 = conj(m11); m01 = conj(m10); m10 = conj(t);
+      }
+      cx<R> b[NA];
+#pragma unroll
+      for (int ri = 0; ri < NA; ++ri) b[ri] = a[ri];
+      dense1_at<R, RB, ADJ>(op.k0, b, m00, m01, m10, m11);
+#pragma unroll
+      for (int ri = 0; ri < NA; ++ri) a[ri] = sel(!ctl || bit_of<RB>(op.s0, L, ri), b[ri], a[ri]);
+      break;
+    }
+    case FOP_PDIAG1: {
+      cx<R> d0 = mat<R>(rec, 0), d1 = mat<R>(rec, 3);
+      if (ADJ) { d0 = conj(d0); d1 = conj(d1); }
+#pragma unroll
+      for (int ri = 0; ri < NA; ++ri) a[ri] = sel(bit_of<RB>(op.s0, L, ri), d1, d0) * a[ri];
+      break;
+    }
+    case FOP_DIAG2: {
+      cx<R> d[4] = {mat<R>(rec, 0), mat<R>(rec, 5), mat<R>(rec, 10), mat<R>(rec, 15)};
+      if (ADJ) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k] = conj(d[k]);
+      }
+#pragma unroll
+      for (int ri = 0; ri < NA; ++ri)
+        a[ri] = pick_diag4<R, RB>(d, bit_of<RB>(op.s0, L, ri), bit_of<RB>(op.s1, L, ri)) * a[ri];
+      break;
+    }
+    case FOP_DENSE2:
+      dense2_at<R, RB>(op.k0, op.k1, a, rec, 0, ADJ);
+      break;
+    default:
+      break;
+  }
+}
+
+// Re <l|D_j f> for the explicit derivative matrices of a general op (f already un-applied).
+template <typename R, int RB>
+__device__ __forceinline__ void general_products(const FusedOp& op, const GateRec* rec,
+                                                 const cx<R>* f, const cx<R>* l,
+                                                 const Layout<RB>& L, double* out) {
+  constexpr int NA = 1 << RB;
+  cx<R> mu[NA];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (j >= op.np) break;
+#pragma unroll
+    for (int ri = 0; ri < NA; ++ri) mu[ri] = f[ri];
+    switch (op.type) {
+      case FOP_PDENSE1: {
+        const int o = 4 + 4 * j;
+        dense1_at<R, RB, false>(op.k0, mu, mat<R>(rec, o), mat<R>(rec, o + 1),
+                                mat<R>(rec, o + 2), mat<R>(rec, o + 3));
+        break;
+      }
+      case FOP_CDENSE1:
+        // derivative of a controlled gate: dU on the target, amplitudes with control 0 zeroed
+        dense1_at<R, RB, false>(op.k0, mu, mat<R>(rec, 26), mat<R>(rec, 27), mat<R>(rec, 30),
+                                mat<R>(rec, 31));
+#pragma unroll
+        for (int ri = 0; ri < NA; ++ri) mu[ri] = sel(bit_of<RB>(op.s0, L, ri), mu[ri], cx<R>{0, 0});
+        break;
+      case FOP_PDIAG1: {
+        const cx<R> e0 = mat<R>(rec, 4), e1 = mat<R>(rec, 7);
+#pragma unroll
+        for (int ri = 0; ri < NA; ++ri) mu[ri] = sel(bit_of<RB>(op.s0, L, ri), e1, e0) * mu[ri];
+        break;
+      }
+      case FOP_DIAG2: {
+        const cx<R> e[4] = {mat<R>(rec, 16), mat<R>(rec, 21), mat<R>(rec, 26), mat<R>(rec, 31)};
+#pragma unroll
+        for (int ri = 0; ri < NA; ++ri)
+          mu[ri] = pick_diag4<R, RB>(e, bit_of<RB>(op.s0, L, ri), bit_of<RB>(op.s1, L, ri)) * mu[ri];
+        break;
+      }
+      case FOP_DENSE2:
+        dense2_at<R, RB>(op.k0, op.k1, mu, rec, 16, false);
+        break;
+      default:
+        break;
+    }
+    double s = 0;
+#pragma unroll
+    for (int ri = 0; ri < NA; ++ri) s += re_cm(l[ri].r, l[ri].i, mu[ri].r, mu[ri].i);
+    out[j] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Wave sum with DPP row operations (inclusive scan; the total ends in lane 63).
+// ---------------------------------------------------------------------------------------------
+template <int CTRL, int ROWM, int BANKM>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWM, BANKM, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWM, BANKM, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_total_lane63(double v) {
+  double t = v + dpp_f64<0x111, 0xf, 0xf>(v);  // row_shr:1
+  t += dpp_f64<0x112, 0xf, 0xf>(v);             // row_shr:2
+  t += dpp_f64<0x113, 0xf, 0xf>(v);             // row_shr:3
+  t += dpp_f64<0x114, 0xf, 0xe>(t);             // row_shr:4, banks 1-3
+  t += dpp_f64<0x118, 0xf, 0xc>(t);             // row_shr:8, banks 2-3
+  t += dpp_f64<0x142, 0xa, 0xf>(t);             // row_bcast:15, rows 1 and 3
+  t += dpp_f64<0x143, 0xc, 0xf>(t);             // row_bcast:31, rows 2 and 3
+  return t;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------------------------
+template <int RB, int W>
+struct Geometry {
+  static constexpr int NA = 1 << RB;
+  static constexpr int NT = 1 << W;
+  static constexpr int T = RB + W;
+  static constexpr int NW = NT / 64;
+};
+
+__device__ __forceinline__ uint64_t outer_base(const PassDesc* __restrict__ pdp, int n_outer,
+                                               uint64_t tile) {
+  uint64_t b = 0;
+  for (int j = 0; j < n_outer; ++j) b |= ((tile >> j) & 1ull) << pdp->outer[j];
+  return b;
+}
+
+template <int RB, int W>
+__device__ __forceinline__ void direct_offsets(const PassDesc& pd, uint32_t tid, uint64_t& gthr,
+                                               uint64_t* groff) {
+  gthr = 0;
+#pragma unroll
+  for (int s = 0; s < W; ++s) gthr |= (uint64_t)((tid >> s) & 1u) << pd.tile[s];
+#pragma unroll
+  for (int ri = 0; ri < (1 << RB); ++ri) {
+    uint64_t o = 0;
+#pragma unroll
+    for (int k = 0; k < RB; ++k) o |= (uint64_t)((ri >> k) & 1) << pd.tile[W + k];
+    groff[ri] = o;
+  }
+}
+
+template <int RB, int W>
+__device__ __forceinline__ void direct_layout(Layout<RB>& L, uint32_t tid) {
+  int8_t rb[RB];
+#pragma unroll
+  for (int k = 0; k < RB; ++k) rb[k] = (int8_t)(W + k);
+  make_layout<RB, RB + W>(L, rb, tid);
+}
+
+template <typename R, int RB, int W, bool GEN>
+__global__ void __launch_bounds__(1 << W)
+k_pass_fwd(const typename Vec2<R>::T* src, typename Vec2<R>::T* dst,
+           const PassDesc* __restrict__ pdp, const PhaseDesc* __restrict__ phases,
+           const FusedOp* __restrict__ ops, const GateRec* __restrict__ recs) {
+  using G = Geometry<RB, W>;
+  using V = typename Vec2<R>::T;
+  __shared__ V lds[1 << G::T];
+  const PassDesc pd = *pdp;
+  const uint32_t tid = threadIdx.x;
+  uint64_t gthr, groff[G::NA];
+  direct_offsets<RB, W>(pd, tid, gthr, groff);
+  Layout<RB> D;
+  direct_layout<RB, W>(D, tid);
+  const uint64_t n_tiles = 1ull << pd.n_outer;
+  for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const uint64_t ob = outer_base(pdp, pd.n_outer, tile) | gthr;
+    cx<R> a[G::NA];
+#pragma unroll
+    for (int ri = 0; ri < G::NA; ++ri) a[ri] = load<R>(src, ob | groff[ri]);
+    Layout<RB> cur = D;
+    int op_at = pd.op_begin;
+    for (int ph = pd.phase_begin; ph < pd.phase_end; ++ph) {
+      const PhaseDesc P = phases[ph];
+      if (!same_layout<RB>(cur, P.regbit)) {
+        Layout<RB> nxt;
+        make_layout<RB, G::T>(nxt, P.regbit, tid);
+        relayout<R, RB>(a, cur, nxt, lds);
+        cur = nxt;
+      }
+      const int op_end = pd.op_begin + P.op_end;
+      for (; op_at < op_end; ++op_at) {
+        const FusedOp op = ops[op_at];
+        const GateRec* rec = recs + op.gate;
+        if (GEN && op.type >= FOP_FIRST_GENERAL) apply_general<R, RB, false>(op, rec, a, cur);
+        else apply_lean<R, RB, false>(op, rec, a, cur.tdep);
+      }
+    }
+    if (!same_layout<RB>(cur, D.rb)) relayout<R, RB>(a, cur, D, lds);
+#pragma unroll
+    for (int ri = 0; ri < G::NA; ++ri) store<R>(dst, ob | groff[ri], a[ri]);
+  }
+}
+
+template <typename R, int RB, int W, bool GEN>
+__global__ void __launch_bounds__(1 << W)
+k_pass_bwd(typename Vec2<R>::T* __restrict__ phi, typename Vec2<R>::T* __restrict__ lam,
+           const PassDesc* __restrict__ pdp, const PhaseDesc* __restrict__ phases,
+           const FusedOp* __restrict__ ops, const int32_t* __restrict__ slot_map,
+           const GateRec* __restrict__ recs, double2* __restrict__ partials, int nb) {
+  using G = Geometry<RB, W>;
+  using V = typename Vec2<R>::T;
+  __shared__ V lds[1 << G::T];
+  __shared__ double wacc[kMaxSlotsPerPass][G::NW];
+  const PassDesc pd = *pdp;
+  const uint32_t tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < kMaxSlotsPerPass * G::NW; i += G::NT) (&wacc[0][0])[i] = 0.0;
+  __syncthreads();
+  uint64_t gthr, groff[G::NA];
+  direct_offsets<RB, W>(pd, tid, gthr, groff);
+  Layout<RB> D;
+  direct_layout<RB, W>(D, tid);
+  const uint64_t n_tiles = 1ull << pd.n_outer;
+  for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const uint64_t ob = outer_base(pdp, pd.n_outer, tile) | gthr;
+    cx<R> f[G::NA], l[G::NA];
+#pragma unroll
+    for (int ri = 0; ri < G::NA; ++ri) {
+      f[ri] = load<R>(phi, ob | groff[ri]);
+      l[ri] = load<R>(lam, ob | groff[ri]);
+    }
+    Layout<RB> cur = D;
+    int op_at = pd.op_begin;
+    for (int ph = pd.phase_begin; ph < pd.phase_end; ++ph) {
+      const PhaseDesc P = phases[ph];
+      if (!same_layout<RB>(cur, P.regbit)) {
+        Layout<RB> nxt;
+        make_layout<RB, G::T>(nxt, P.regbit, tid);
+        relayout<R, RB>(f, cur, nxt, lds);
+        relayout<R, RB>(l, cur, nxt, lds);
+        cur = nxt;
+      }
+      const int op_end = pd.op_begin + P.op_end;
+      for (; op_at < op_end; ++op_at) {
+        const FusedOp op = ops[op_at];
+        const GateRec* rec = recs + op.gate;
+        double prod[3] = {0, 0, 0};
+        if (GEN && op.type >= FOP_FIRST_GENERAL) {
+          apply_general<R, RB, true>(op, rec, f, cur);
+          if (op.np) general_products<R, RB>(op, rec, f, l, cur, prod);
+          apply_general<R, RB, true>(op, rec, l, cur);
+        } else {
+          if (op.np) prod[0] = lean_product<R, RB>(op, f, l, cur.tdep);
+          apply_lean<R, RB, true>(op, rec, f, cur.tdep);
+          apply_lean<R, RB, true>(op, rec, l, cur.tdep);
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          if (j >= op.np) break;
+          const double s = wave_total_lane63(prod[j]);
+          if (lane == 63) wacc[op.lslot + j][wave] += s;
+        }
+      }
+    }
+    if (!same_layout<RB>(cur, D.rb)) {
+      relayout<R, RB>(f, cur, D, lds);
+      relayout<R, RB>(l, cur, D, lds);
+    }
+#pragma unroll
+    for (int ri = 0; ri < G::NA; ++ri) {
+      store<R>(phi, ob | groff[ri], f[ri]);
+      store<R>(lam, ob | groff[ri], l[ri]);
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < pd.n_slots; j += G::NT) {
+    double s = 0;
+    for (int w = 0; w < G::NW; ++w) s += wacc[j][w];
+    partials[(size_t)slot_map[pd.slot_begin + j] * nb + blockIdx.x] = make_double2(s, 0.0);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------------------------
+// Geometries with a kernel instance whose amplitude registers do not spill (reverse sweep: two
+// states per thread).
+bool fused_config_supported(int r, int w, bool c128) {
+  if (w == 8) return r >= 2 && r <= (c128 ? 3 : 4);
+  if (w == 6) return r >= 2 && r <= 3;
+  return false;
+}
+
+#define QSV_FUSED_CASES(X, R) X(R, 2, 8) X(R, 3, 8) X(R, 2, 6) X(R, 3, 6)
+
+template <typename R>
+hipError_t launch_fused_forward(const void* src, void* dst, int n, const PassDesc* d_pass,
+                                const PhaseDesc* d_phases, const FusedOp* d_ops,
+                                const GateRec* d_recs, int r, int w, bool general, int grid,
+                                hipStream_t st) {
+  using V = typename Vec2<R>::T;
+  (void)n;
+#define X(RR, RB, WW)                                                                           \
+  if (r == RB && w == WW) {                                                                     \
+    if (general)                                                                                \
+      hipLaunchKernelGGL((k_pass_fwd<RR, RB, WW, true>), dim3(grid), dim3(1 << WW), 0, st,      \
+                         static_cast<const V*>(src), static_cast<V*>(dst), d_pass, d_phases,    \
+                         d_ops, d_recs);                                                        \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_pass_fwd<RR, RB, WW, false>), dim3(grid), dim3(1 << WW), 0, st,     \
+                         static_cast<const V*>(src), static_cast<V*>(dst), d_pass, d_phases,    \
+                         d_ops, d_recs);                                                        \
+    return hipGetLastError();                                                                   \
+  }
+  QSV_FUSED_CASES(X, R)
+  if constexpr (sizeof(R) == 4) { X(R, 4, 8) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_fused_backward(void* phi, void* lam, int n, const PassDesc* d_pass,
+                                 const PhaseDesc* d_phases, const FusedOp* d_ops,
+                                 const int32_t* d_slot_map, const GateRec* d_recs,
+                                 double2* partials, int nb, int r, int w, bool general, int grid,
+                                 hipStream_t st) {
+  using V = typename Vec2<R>::T;
+  (void)n;
+#define X(RR, RB, WW)                                                                           \
+  if (r == RB && w == WW) {                                                                     \
+    if (general)                                                                                \
+      hipLaunchKernelGGL((k_pass_bwd<RR, RB, WW, true>), dim3(grid), dim3(1 << WW), 0, st,      \
+                         static_cast<V*>(phi), static_cast<V*>(lam), d_pass, d_phases, d_ops,   \
+                         d_slot_map, d_recs, partials, nb);                                     \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_pass_bwd<RR, RB, WW, false>), dim3(grid), dim3(1 << WW), 0, st,     \
+                         static_cast<V*>(phi), static_cast<V*>(lam), d_pass, d_phases, d_ops,   \
+                         d_slot_map, d_recs, partials, nb);                                     \
+    return hipGetLastError();                                                                   \
+  }
+  QSV_FUSED_CASES(X, R)
+  if constexpr (sizeof(R) == 4) { X(R, 4, 8) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_fused_forward<double>(const void*, void*, int, const PassDesc*,
+                                                 const PhaseDesc*, const FusedOp*, const GateRec*,
+                                                 int, int, bool, int, hipStream_t);
+template hipError_t launch_fused_forward<float>(const void*, void*, int, const PassDesc*,
+                                                const PhaseDesc*, const FusedOp*, const GateRec*,
+                                                int, int, bool, int, hipStream_t);
+template hipError_t launch_fused_backward<double>(void*, void*, int, const PassDesc*,
+                                                  const PhaseDesc*, const FusedOp*,
+                                                  const int32_t*, const GateRec*, double2*, int,
+                                                  int, int, bool, int, hipStream_t);
+template hipError_t launch_fused_backward<float>(void*, void*, int, const PassDesc*,
+                                                 const PhaseDesc*, const FusedOp*, const int32_t*,
+                                                 const GateRec*, double2*, int, int, int, bool,
+                                                 int, hipStream_t);
+
+}  // namespace qsv

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/qsv.h"
+#include "fused.h"
 #include "qsv_internal.h"
 #include "sv_kernels.h"
 
@@ -156,6 +157,16 @@ static uint64_t fnv1a(const void* data, size_t len, uint64_t h = 146959810393466
   return h;
 }
 
+// The fused schedules of one circuit for one tile geometry, with their device copies.
+struct FusedSchedule {
+  Schedule sched;
+  DevBuf d_passes, d_phases, d_ops, d_slot_map;
+};
+struct FusedPlan {
+  int r = 0, w = 0;
+  FusedSchedule fwd, bwd;
+};
+
 // A circuit lowered for the device: gate table, matrix records, and the map from parameters to
 // the reduction slots of their occurrences (in sweep order, last gate first).
 struct Plan {
@@ -165,6 +176,7 @@ struct Plan {
   std::vector<int32_t> slot_of_gate;  // first reduction slot of gate k (-1 if none)
   std::vector<int32_t> param_ptr, occ;
   DevBuf d_gates, d_recs, d_param_ptr, d_occ;
+  std::map<int, std::unique_ptr<FusedPlan>> fused;  // key r * 16 + w
 };
 
 struct PauliPlan {
@@ -214,6 +226,8 @@ struct qsv_state {
   hipStream_t stream = nullptr;
   int device = 0;
   int nb = 1;
+  int fusion_mode = -1;  // -1 automatic, 0 gate-granular, 1 fused with (fr, fw)
+  int fr = 0, fw = 0;
   std::unordered_map<uint64_t, std::unique_ptr<Plan>> plans;
   std::unordered_map<uint64_t, std::unique_ptr<PauliPlan>> paulis;
   DevBuf partials, epartials, theta_scratch, energies;
@@ -456,15 +470,164 @@ static qsv_status check_theta(const Plan* p, const double* d_theta) {
 
 static double state_bytes_d(const qsv_state* s) { return (double)qsv_state_bytes(s->n, s->dt); }
 
+// ------------------------------------------------------------------------------------------------
+// fusion geometry and schedules
+// ------------------------------------------------------------------------------------------------
+static constexpr int kFusedGridCap = 1024;
+
+// Tile geometry for the handle: (r, w) with t = r + w tile qubits, or false for the gate-granular
+// path (states too small for a tile, or fusion switched off).
+static bool fusion_geometry(const qsv_state* s, int* r, int* w) {
+  const bool c128 = s->dt == QSV_C128;
+  if (s->fusion_mode == 0) return false;
+  if (s->fusion_mode == 1) {
+    *r = s->fr;
+    *w = s->fw;
+    return true;
+  }
+  const int rmax = c128 ? 3 : 4;
+  for (int rr = rmax; rr >= 2; --rr)
+    if (rr + 8 <= s->n) {
+      *r = rr;
+      *w = 8;
+      return true;
+    }
+  for (int rr = 3; rr >= 2; --rr)
+    if (rr + 6 <= s->n) {
+      *r = rr;
+      *w = 6;
+      return true;
+    }
+  return false;
+}
+
+static qsv_status upload_schedule(FusedSchedule& fs, hipStream_t st) {
+  const Schedule& sc = fs.sched;
+  QSV_TRY(fs.d_passes.ensure(sizeof(PassDesc) * (sc.passes.size() + 1), st));
+  QSV_TRY(fs.d_phases.ensure(sizeof(PhaseDesc) * (sc.phases.size() + 1), st));
+  QSV_TRY(fs.d_ops.ensure(sizeof(FusedOp) * (sc.ops.size() + 1), st));
+  QSV_TRY(fs.d_slot_map.ensure(sizeof(int32_t) * (sc.slot_map.size() + 1), st));
+  if (!sc.passes.empty())
+    HIP_TRY(hipMemcpyAsync(fs.d_passes.p, sc.passes.data(), sizeof(PassDesc) * sc.passes.size(),
+                           hipMemcpyHostToDevice, st));
+  if (!sc.phases.empty())
+    HIP_TRY(hipMemcpyAsync(fs.d_phases.p, sc.phases.data(), sizeof(PhaseDesc) * sc.phases.size(),
+                           hipMemcpyHostToDevice, st));
+  if (!sc.ops.empty())
+    HIP_TRY(hipMemcpyAsync(fs.d_ops.p, sc.ops.data(), sizeof(FusedOp) * sc.ops.size(),
+                           hipMemcpyHostToDevice, st));
+  if (!sc.slot_map.empty())
+    HIP_TRY(hipMemcpyAsync(fs.d_slot_map.p, sc.slot_map.data(),
+                           sizeof(int32_t) * sc.slot_map.size(), hipMemcpyHostToDevice, st));
+  return QSV_OK;
+}
+
+static qsv_status get_fused(qsv_state* s, Plan* p, int r, int w, FusedPlan** out) {
+  const int key = r * 16 + w;
+  auto it = p->fused.find(key);
+  if (it != p->fused.end()) {
+    *out = it->second.get();
+    return QSV_OK;
+  }
+  if (!fused_config_supported(r, w, s->dt == QSV_C128) || r + w > s->n)
+    return fail(QSV_ERR_UNSUPPORTED, "fused geometry r=%d w=%d not available for n=%d", r, w, s->n);
+  auto fp = std::make_unique<FusedPlan>();
+  fp->r = r;
+  fp->w = w;
+  const int G = (int)p->gates.size();
+  std::vector<int> seq(G);
+  std::string msg;
+  for (int k = 0; k < G; ++k) seq[k] = k;
+  if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, false, r + w, r, w, fp->fwd.sched, &msg))
+    return fail(QSV_ERR_INTERNAL, "forward schedule: %s", msg.c_str());
+  for (int k = 0; k < G; ++k) seq[k] = G - 1 - k;
+  if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, true, r + w, r, w, fp->bwd.sched, &msg))
+    return fail(QSV_ERR_INTERNAL, "backward schedule: %s", msg.c_str());
+  QSV_TRY(upload_schedule(fp->fwd, s->stream));
+  QSV_TRY(upload_schedule(fp->bwd, s->stream));
+  *out = fp.get();
+  p->fused[key] = std::move(fp);
+  return QSV_OK;
+}
+
+static int fused_grid(int n, int t) {
+  const uint64_t tiles = 1ull << (n - t);
+  return (int)std::min<uint64_t>(tiles, (uint64_t)kFusedGridCap);
+}
+
+// psi_dst <- U psi_src (src may equal dst).
 template <typename R>
-static qsv_status forward(qsv_state* s, Plan* p, void* psi) {
+static qsv_status forward(qsv_state* s, Plan* p, const void* src, void* dst) {
   const double S = state_bytes_d(s);
+  const hipStream_t st = s->stream;
+  int r = 0, w = 0;
+  if (fusion_geometry(s, &r, &w) && !p->gates.empty()) {
+    FusedPlan* fp = nullptr;
+    QSV_TRY(get_fused(s, p, r, w, &fp));
+    const Schedule& sc = fp->fwd.sched;
+    const int grid = fused_grid(s->n, r + w);
+    for (size_t i = 0; i < sc.passes.size(); ++i) {
+      const void* from = i == 0 ? src : dst;
+      QSV_TRY(timed(s, "k_pass_fwd", 2 * S, [&] {
+        return launch_fused_forward<R>(from, dst, s->n, fp->fwd.d_passes.as<PassDesc>() + i,
+                                       fp->fwd.d_phases.as<PhaseDesc>(),
+                                       fp->fwd.d_ops.as<FusedOp>(), p->d_recs.as<GateRec>(), r,
+                                       w, sc.passes[i].general != 0, grid, st);
+      }));
+    }
+    return QSV_OK;
+  }
+  if (src != dst)
+    QSV_TRY(timed(s, "k_copy", 2 * S, [&] { return launch_copy<R>(dst, src, s->n, st); }));
   for (size_t k = 0; k < p->gates.size(); ++k) {
     const GateDesc& g = p->gates[k];
     QSV_TRY(timed(s, forward_kernel_name(g), forward_bytes(g, S), [&] {
-      return launch_forward_gate<R>(psi, s->n, g, p->d_recs.as<GateRec>() + k, false, s->stream);
+      return launch_forward_gate<R>(dst, s->n, g, p->d_recs.as<GateRec>() + k, false, st);
     }));
   }
+  return QSV_OK;
+}
+
+// The reverse sweep of Algorithm 1 over (phi, lambda); per-slot partials of Re <lambda|mu> are
+// written with stride *nb_out.
+template <typename R>
+static qsv_status backward(qsv_state* s, Plan* p, void* phi, void* lam, int* nb_out) {
+  const double S = state_bytes_d(s);
+  const hipStream_t st = s->stream;
+  const int n = s->n;
+  int r = 0, w = 0;
+  if (fusion_geometry(s, &r, &w) && !p->gates.empty()) {
+    FusedPlan* fp = nullptr;
+    QSV_TRY(get_fused(s, p, r, w, &fp));
+    const Schedule& sc = fp->bwd.sched;
+    const int nb = fused_grid(n, r + w);
+    QSV_TRY(s->partials.ensure(sizeof(double2) * (size_t)(p->n_occ ? p->n_occ : 1) * nb, st));
+    double2* part = s->partials.as<double2>();
+    for (size_t i = 0; i < sc.passes.size(); ++i) {
+      QSV_TRY(timed(s, "k_pass_bwd", 4 * S, [&] {
+        return launch_fused_backward<R>(phi, lam, n, fp->bwd.d_passes.as<PassDesc>() + i,
+                                        fp->bwd.d_phases.as<PhaseDesc>(),
+                                        fp->bwd.d_ops.as<FusedOp>(),
+                                        fp->bwd.d_slot_map.as<int32_t>(),
+                                        p->d_recs.as<GateRec>(), part, nb, r, w,
+                                        sc.passes[i].general != 0, nb, st);
+      }));
+    }
+    *nb_out = nb;
+    return QSV_OK;
+  }
+  const int nb = s->nb;
+  QSV_TRY(s->partials.ensure(sizeof(double2) * (size_t)(p->n_occ ? p->n_occ : 1) * nb, st));
+  double2* part = s->partials.as<double2>();
+  for (int k = (int)p->gates.size() - 1; k >= 0; --k) {
+    const int slot = p->slot_of_gate[k];
+    const GateDesc& g = p->gates[k];
+    QSV_TRY(timed(s, backward_kernel_name(g), backward_bytes(g, S, k > 0), [&] {
+      return launch_backward_gate<R>(phi, lam, n, g, p->d_recs.as<GateRec>() + k, k > 0,
+                                     slot >= 0 ? part + (size_t)slot * nb : nullptr, nb, st);
+    }));
+  }
+  *nb_out = nb;
   return QSV_OK;
 }
 
@@ -481,7 +644,7 @@ template <typename R>
 static qsv_status apply_circuit_t(qsv_state* s, Plan* p, const double* d_theta) {
   HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
                       p->d_recs.as<GateRec>(), s->stream));
-  return forward<R>(s, p, s->d_state);
+  return forward<R>(s, p, s->d_state, s->d_state);
 }
 
 extern "C" qsv_status qsv_apply_circuit(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
@@ -518,31 +681,21 @@ static qsv_status adjoint_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* 
   const size_t sb = qsv_state_bytes(n, s->dt);
   void* phi = s->d_work;
   void* lam = static_cast<char*>(s->d_work) + sb;
-  QSV_TRY(s->partials.ensure(sizeof(double2) * (size_t)(p->n_occ ? p->n_occ : 1) * nb, st));
   QSV_TRY(s->epartials.ensure(sizeof(double2) * nb, st));
-  double2* part = s->partials.as<double2>();
   double2* ep = s->epartials.as<double2>();
 
   HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
                       p->d_recs.as<GateRec>(), st));
-  // Algorithm 1: the first clone and the forward pass build psi in the phi buffer; lambda is then
-  // written directly as H psi (this also serves as the clone phi := psi), E = <psi|H psi>.
-  const double S = state_bytes_d(s);
-  QSV_TRY(timed(s, "k_copy", 2 * S, [&] { return launch_copy<R>(phi, s->d_state, n, st); }));
-  QSV_TRY(forward<R>(s, p, phi));
+  // Algorithm 1: the clone lambda := |in> and the forward pass build psi in the phi buffer (the
+  // first pass reads |in> and writes phi); lambda is then written directly as H psi, which also
+  // stands for the clone phi := psi. E = <psi|H psi>.
+  QSV_TRY(forward<R>(s, p, s->d_state, phi));
   QSV_TRY(pauli<R>(s, hp, phi, lam, ep));
   HIP_TRY(launch_final_energy(ep, nb, d_energy, nullptr, st));
-  // reverse sweep
-  for (int k = (int)p->gates.size() - 1; k >= 0; --k) {
-    const int slot = p->slot_of_gate[k];
-    const GateDesc& g = p->gates[k];
-    QSV_TRY(timed(s, backward_kernel_name(g), backward_bytes(g, S, k > 0), [&] {
-      return launch_backward_gate<R>(phi, lam, n, g, p->d_recs.as<GateRec>() + k, k > 0,
-                                     slot >= 0 ? part + (size_t)slot * nb : nullptr, nb, st);
-    }));
-  }
-  HIP_TRY(launch_final_grad(part, nb, p->d_param_ptr.as<int32_t>(), p->d_occ.as<int32_t>(),
-                            p->n_theta, d_grad, nullptr, st));
+  int nbp = 1;
+  QSV_TRY(backward<R>(s, p, phi, lam, &nbp));
+  HIP_TRY(launch_final_grad(s->partials.as<double2>(), nbp, p->d_param_ptr.as<int32_t>(),
+                            p->d_occ.as<int32_t>(), p->n_theta, d_grad, nullptr, st));
   return QSV_OK;
 }
 
@@ -579,15 +732,13 @@ static qsv_status param_shift_t(qsv_state* s, Plan* p, PauliPlan* hp, const doub
   double* e = s->energies.as<double>();
   double2* ep = s->epartials.as<double2>();
   void* phi = s->d_work;
-  const double S = state_bytes_d(s);
   const double half_pi = 1.57079632679489661923;
   for (int i = 0; i < count; ++i) {
     for (int side = 0; side < 2; ++side) {
       HIP_TRY(launch_shift_theta(th, d_theta, nt, first + i, side ? -half_pi : half_pi, st));
       HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), th,
                           p->d_recs.as<GateRec>(), st));
-      QSV_TRY(timed(s, "k_copy", 2 * S, [&] { return launch_copy<R>(phi, s->d_state, n, st); }));
-      QSV_TRY(forward<R>(s, p, phi));
+      QSV_TRY(forward<R>(s, p, s->d_state, phi));
       QSV_TRY(pauli<R>(s, hp, phi, nullptr, ep));
       HIP_TRY(launch_final_energy(ep, nb, e + 2 * i + side, nullptr, st));
     }
@@ -675,5 +826,77 @@ extern "C" qsv_status qsv_timing_read(qsv_state* s, qsv_kernel_stat* out, int32_
   const int32_t m = std::min<int32_t>(max_out, (int32_t)v.size());
   for (int32_t i = 0; i < m; ++i) out[i] = v[i];
   *n_out = m;
+  return QSV_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// fusion control and schedule inspection
+// ------------------------------------------------------------------------------------------------
+extern "C" qsv_status qsv_set_fusion(qsv_state* s, int32_t mode, int32_t reg_qubits,
+                                     int32_t threads_log2) {
+  QSV_TRY(check_handle(s));
+  if (mode < -1 || mode > 1) return fail(QSV_ERR_INVALID_ARG, "fusion mode %d", mode);
+  if (mode == 1) {
+    if (!fused_config_supported(reg_qubits, threads_log2, s->dt == QSV_C128))
+      return fail(QSV_ERR_UNSUPPORTED, "no fused kernel for reg_qubits=%d threads_log2=%d",
+                  reg_qubits, threads_log2);
+    if (reg_qubits + threads_log2 > s->n)
+      return fail(QSV_ERR_INVALID_ARG, "tile of %d qubits exceeds the %d-qubit state",
+                  reg_qubits + threads_log2, s->n);
+  }
+  s->fusion_mode = mode;
+  s->fr = mode == 1 ? reg_qubits : 0;
+  s->fw = mode == 1 ? threads_log2 : 0;
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_get_fusion(qsv_state* s, int32_t* mode, int32_t* reg_qubits,
+                                     int32_t* threads_log2) {
+  QSV_TRY(check_handle(s));
+  if (!mode || !reg_qubits || !threads_log2) return fail(QSV_ERR_INVALID_ARG, "NULL output");
+  int r = 0, w = 0;
+  const bool f = fusion_geometry(s, &r, &w);
+  *mode = f ? 1 : 0;
+  *reg_qubits = r;
+  *threads_log2 = w;
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_schedule_describe(int32_t n, const qsv_gate* gates, int32_t n_gates,
+                                            int32_t backward, int32_t reg_qubits,
+                                            int32_t threads_log2, qsv_schedule_info* out) {
+  QSV_TRY(qsv_validate_circuit(n, gates, n_gates, 1 << 30));
+  if (!out || (n_gates > 0 && (!out->order || !out->pass_of || !out->phase_of ||
+                               !out->tile_mask || !out->reg_mask)))
+    return fail(QSV_ERR_INVALID_ARG, "NULL output array");
+  if (reg_qubits < 1 || reg_qubits > kMaxRegBits || threads_log2 < 1 ||
+      reg_qubits + threads_log2 > n || reg_qubits + threads_log2 > kMaxTileBits)
+    return fail(QSV_ERR_INVALID_ARG, "tile geometry r=%d w=%d invalid for n=%d", reg_qubits,
+                threads_log2, n);
+  std::vector<GateDesc> g(reinterpret_cast<const GateDesc*>(gates),
+                          reinterpret_cast<const GateDesc*>(gates) + n_gates);
+  std::vector<int32_t> slot(n_gates, -1);
+  int sl = 0;
+  for (int k = n_gates - 1; k >= 0; --k)
+    if (kind_nparams(g[k].kind)) {
+      slot[k] = sl;
+      sl += kind_nparams(g[k].kind);
+    }
+  std::vector<int> seq(n_gates);
+  for (int k = 0; k < n_gates; ++k) seq[k] = backward ? n_gates - 1 - k : k;
+  Schedule sc;
+  std::string msg;
+  if (!build_schedule(n, g, seq, slot, backward != 0, reg_qubits + threads_log2, reg_qubits,
+                      threads_log2, sc, &msg))
+    return fail(QSV_ERR_INTERNAL, "schedule: %s", msg.c_str());
+  out->n_passes = (int32_t)sc.passes.size();
+  out->n_phases = (int32_t)sc.phases.size();
+  for (int i = 0; i < n_gates; ++i) {
+    out->order[i] = sc.order[i];
+    out->pass_of[i] = sc.pass_of[i];
+    out->phase_of[i] = sc.phase_of[i];
+  }
+  for (size_t i = 0; i < sc.passes.size(); ++i) out->tile_mask[i] = sc.tile_mask[i];
+  for (size_t i = 0; i < sc.phases.size(); ++i) out->reg_mask[i] = sc.reg_mask[i];
   return QSV_OK;
 }

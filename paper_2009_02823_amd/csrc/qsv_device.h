@@ -46,6 +46,12 @@ template <typename R>
 __device__ __forceinline__ cx<R> neg(cx<R> a) {
   return {-a.r, -a.i};
 }
+// c ? a : b, selected per component (a select of whole structs would make the compiler pick
+// between their addresses and keep them in scratch memory).
+template <typename R>
+__device__ __forceinline__ cx<R> sel(bool c, cx<R> a, cx<R> b) {
+  return {c ? a.r : b.r, c ? a.i : b.i};
+}
 
 template <typename R>
 __device__ __forceinline__ cx<R> load(const typename Vec2<R>::T* p, uint64_t j) {

@@ -1,0 +1,287 @@
+// Fusion scheduler (host code): partitions a gate sequence into fused passes (tile qubit sets) and
+// each pass into register phases, preserving the order of the gates on every qubit.
+//
+// Both partitions use the same "blocked scan": walk the remaining gates in order; a gate is taken
+// when all of its qubits are admissible and none of them is blocked, otherwise its qubits become
+// blocked for the rest of the scan. Every taken gate therefore only follows gates it commutes with
+// (disjoint qubits) or gates taken before it, so the executed order is a valid reordering.
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "fused.h"
+
+namespace qsv {
+
+static uint64_t qmask(const GateDesc& g) {
+  uint64_t m = 1ull << g.q0;
+  if (kind_nqubits(g.kind) == 2) m |= 1ull << g.q1;
+  return m;
+}
+
+// Physical qubits that must be register bits for the gate (its non-diagonal targets).
+static uint64_t regneed(const GateDesc& g) {
+  switch (g.kind) {
+    case K_RZ: case K_Z: case K_S: case K_T: case K_SDG: case K_PHASE: case K_CZ: case K_RZZ:
+    case K_CRZ:
+      return 0;
+    case K_CNOT: case K_CRX: case K_CRY:
+      return 1ull << g.q1;
+    case K_RXX: case K_RYY:
+      return (1ull << g.q0) | (1ull << g.q1);
+    default:
+      return 1ull << g.q0;
+  }
+}
+
+static int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+// Gates taken by a blocked scan of `rem` with admissible qubits `allowed`, at most `max_slots`
+// products (backward) and `max_ops` gates.
+static void scan(const std::vector<int>& rem, const std::vector<GateDesc>& g, uint64_t allowed,
+                 bool backward, int max_slots, int max_ops, std::vector<int>* taken, int* count) {
+  uint64_t blocked = 0;
+  int slots = 0, ops = 0, cnt = 0;
+  for (int k : rem) {
+    const uint64_t m = qmask(g[k]);
+    const int np = backward ? kind_nparams(g[k].kind) : 0;
+    if ((m & blocked) || (m & ~allowed) || slots + np > max_slots || ops + 1 > max_ops) {
+      blocked |= m;
+      continue;
+    }
+    slots += np;
+    ++ops;
+    ++cnt;
+    if (taken) taken->push_back(k);
+  }
+  *count = cnt;
+}
+
+// Greedy tile growth along the gate order, starting from `seed`.
+static uint64_t grow_tile(const std::vector<int>& rem, const std::vector<GateDesc>& g,
+                          uint64_t seed, int t) {
+  uint64_t T = seed, blocked = 0;
+  for (int k : rem) {
+    const uint64_t m = qmask(g[k]);
+    if (m & blocked) {
+      blocked |= m;
+      continue;
+    }
+    if (popc(T | m) <= t) T |= m;
+    else blocked |= m;
+  }
+  return T;
+}
+
+static uint64_t fill_tile(uint64_t T, int n, int t) {
+  for (int q = 0; q < n && popc(T) < t; ++q) T |= 1ull << q;
+  return T;
+}
+
+bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector<int>& seq,
+                    const std::vector<int32_t>& slot_of_gate, bool backward, int t, int r, int w,
+                    Schedule& out, std::string* msg) {
+  out = Schedule();
+  out.t = t;
+  out.r = r;
+  out.w = w;
+  if (t != r + w || t > n || t > kMaxTileBits || r > kMaxRegBits || r < 1) {
+    if (msg) *msg = "tile/register sizes do not fit the state";
+    return false;
+  }
+  const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  // low qubits always in the tile: contiguous runs of 2^c amplitudes per load
+  const int c = std::min(4, std::min(w, n));
+  const uint64_t low = (1ull << c) - 1;
+
+  std::vector<int> rem(seq);
+  while (!rem.empty()) {
+    // ---- choose the tile: best of several candidates by gates taken
+    std::vector<uint64_t> cands;
+    cands.push_back(fill_tile(grow_tile(rem, gates, low, t), n, t));
+    cands.push_back(fill_tile(grow_tile(rem, gates, low | qmask(gates[rem[0]]), t), n, t));
+    for (int a = c; a + (t - c) <= n; ++a) {
+      uint64_t win = (((1ull << (t - c)) - 1) << a) | low;
+      cands.push_back(win & all);
+    }
+    uint64_t bestT = 0;
+    int best = -1;
+    for (uint64_t T : cands) {
+      if (popc(T) != t) continue;
+      int cnt = 0;
+      scan(rem, gates, T, backward, kMaxSlotsPerPass, kMaxOpsPerPass, nullptr, &cnt);
+      if (cnt > best) {
+        best = cnt;
+        bestT = T;
+      }
+    }
+    if (best <= 0) {
+      if (msg) *msg = "a gate does not fit any tile";
+      return false;
+    }
+    std::vector<int> taken;
+    int cnt = 0;
+    scan(rem, gates, bestT, backward, kMaxSlotsPerPass, kMaxOpsPerPass, &taken, &cnt);
+
+    PassDesc pd;
+    std::memset(&pd, 0, sizeof pd);
+    pd.nt = t;
+    int tb_of[64];
+    for (int q = 0; q < 64; ++q) tb_of[q] = -1;
+    int s = 0, o = 0;
+    for (int q = 0; q < n; ++q) {
+      if ((bestT >> q) & 1) {
+        tb_of[q] = s;
+        pd.tile[s++] = (int8_t)q;
+      } else {
+        pd.outer[o++] = (int8_t)q;
+      }
+    }
+    pd.n_outer = o;
+    pd.phase_begin = (int32_t)out.phases.size();
+    pd.op_begin = (int32_t)out.ops.size();
+    pd.slot_begin = (int32_t)out.slot_map.size();
+    const int pass_id = (int32_t)out.passes.size();
+    out.tile_mask.push_back(bestT);
+
+    // ---- register phases inside the pass
+    const uint32_t dmask = ((1u << t) - 1) & ~((1u << w) - 1);  // layout D register bits
+    std::vector<int> prem(taken);
+    int lslot = 0;
+    while (!prem.empty()) {
+      uint32_t R = 0;
+      uint64_t blocked = 0;
+      std::vector<int> ph;
+      std::vector<int> left;
+      // prefer the direct layout if the first gate that needs registers fits in it
+      for (int k : prem) {
+        const uint64_t m = qmask(gates[k]);
+        if (m & blocked) {
+          blocked |= m;
+          left.push_back(k);
+          continue;
+        }
+        uint32_t need = 0;
+        for (uint64_t rn = regneed(gates[k]); rn; rn &= rn - 1) need |= 1u << tb_of[__builtin_ctzll(rn)];
+        if (popc(R | need) <= r) {
+          R |= need;
+          ph.push_back(k);
+        } else {
+          blocked |= m;
+          left.push_back(k);
+        }
+      }
+      // complete the register set: direct-layout bits first, then the lowest free bits
+      for (uint32_t d = dmask & ~R; d && popc(R) < r; d &= d - 1) R |= d & (~d + 1);
+      for (int b = 0; b < t && popc(R) < r; ++b) R |= 1u << b;
+
+      PhaseDesc P;
+      std::memset(&P, 0, sizeof P);
+      int regpos[kMaxTileBits];
+      int kk = 0;
+      for (int b = 0; b < t; ++b)
+        if ((R >> b) & 1) {
+          regpos[b] = kk;
+          P.regbit[kk++] = (int8_t)b;
+        } else {
+          regpos[b] = -1;
+        }
+      const int phase_id = (int32_t)out.phases.size();
+      uint64_t rphys = 0;
+      for (int k2 = 0; k2 < r; ++k2) rphys |= 1ull << pd.tile[P.regbit[k2]];
+      out.reg_mask.push_back(rphys);
+      for (int k : ph) {
+        const GateDesc& g = gates[k];
+        FusedOp op;
+        std::memset(&op, 0, sizeof op);
+        op.gate = k;
+        const int b0 = tb_of[g.q0], b1 = kind_nqubits(g.kind) == 2 ? tb_of[g.q1] : 0;
+        const int np = backward ? kind_nparams(g.kind) : 0;
+        op.np = (uint8_t)np;
+        auto locate0 = [&](int b) {
+          op.s0 = (uint8_t)b;
+          if (regpos[b] >= 0) {
+            op.flags |= FOPF_S0_REG;
+            op.ks0 = (uint8_t)regpos[b];
+          }
+        };
+        auto locate1 = [&](int b) {
+          op.s1 = (uint8_t)b;
+          if (regpos[b] >= 0) {
+            op.flags |= FOPF_S1_REG;
+            op.ks1 = (uint8_t)regpos[b];
+          }
+        };
+        switch (g.kind) {
+          case K_RY:
+            op.type = FOP_RY; op.k0 = (uint8_t)regpos[b0];
+            break;
+          case K_RX:
+            op.type = FOP_RX; op.k0 = (uint8_t)regpos[b0];
+            break;
+          case K_H: case K_X: case K_Y:
+            op.type = FOP_DENSE1; op.k0 = (uint8_t)regpos[b0];
+            break;
+          case K_U3:
+            op.type = FOP_PDENSE1; op.k0 = (uint8_t)regpos[b0];
+            break;
+          case K_RZ:
+            op.type = FOP_RZ; locate0(b0);
+            break;
+          case K_Z: case K_S: case K_T: case K_SDG:
+            op.type = FOP_DIAG1; locate0(b0);
+            break;
+          case K_PHASE:
+            op.type = FOP_PDIAG1; locate0(b0);
+            break;
+          case K_CNOT:
+            op.type = FOP_CNOT; locate0(b0); op.k0 = (uint8_t)regpos[b1];
+            break;
+          case K_CZ:
+            op.type = FOP_CZ; locate0(b0); locate1(b1);
+            break;
+          case K_CRX: case K_CRY:
+            op.type = FOP_CDENSE1; locate0(b0); op.k0 = (uint8_t)regpos[b1];
+            break;
+          case K_CRZ: case K_RZZ:
+            op.type = FOP_DIAG2; locate0(b0); locate1(b1);
+            break;
+          case K_RXX: case K_RYY:
+            op.type = FOP_DENSE2; op.k0 = (uint8_t)regpos[b0]; op.k1 = (uint8_t)regpos[b1];
+            break;
+          default:
+            if (msg) *msg = "unknown gate kind";
+            return false;
+        }
+        if (op.type >= FOP_FIRST_GENERAL) pd.general = 1;
+        if (np) {
+          op.lslot = (uint8_t)lslot;
+          for (int j = 0; j < np; ++j) out.slot_map.push_back(slot_of_gate[k] + j);
+          lslot += np;
+        }
+        out.ops.push_back(op);
+        out.order.push_back(k);
+        out.pass_of.push_back(pass_id);
+        out.phase_of.push_back(phase_id);
+      }
+      P.op_end = (int32_t)out.ops.size() - pd.op_begin;
+      out.phases.push_back(P);
+      prem.swap(left);
+    }
+    pd.phase_end = (int32_t)out.phases.size();
+    pd.n_slots = lslot;
+    out.passes.push_back(pd);
+
+    // drop the taken gates from the remaining sequence
+    std::vector<char> done(gates.size(), 0);
+    for (int k : taken) done[k] = 1;
+    std::vector<int> nrem;
+    nrem.reserve(rem.size());
+    for (int k : rem)
+      if (!done[k]) nrem.push_back(k);
+    rem.swap(nrem);
+  }
+  return true;
+}
+
+}  // namespace qsv

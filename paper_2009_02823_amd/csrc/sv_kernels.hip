@@ -174,7 +174,7 @@ k_fwd_diag1(typename Vec2<R>::T* psi, int n, int q, const GateRec* rec, int adj)
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < dim;
        j += (uint64_t)gridDim.x * blockDim.x) {
     const cx<R> a = load<R>(psi, j);
-    store<R>(psi, j, ((j >> q) & 1) ? d1 * a : d0 * a);
+    store<R>(psi, j, sel(((j >> q) & 1) != 0, d1, d0) * a);
   }
 }
 
@@ -227,7 +227,7 @@ __device__ __forceinline__ void matvec4(const GateRec* rec, int off, bool adj, c
     cx<R> s = {0, 0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const cx<R> m = adj ? conj(mat<R>(rec, off + 4 * k + r)) : mat<R>(rec, off + 4 * r + k);
+      const cx<R> m = sel(adj, conj(mat<R>(rec, off + 4 * k + r)), mat<R>(rec, off + 4 * r + k));
       s = s + m * v[k];
     }
     w[r] = s;
@@ -345,12 +345,12 @@ k_bwd_diag1(typename Vec2<R>::T* phi, typename Vec2<R>::T* lam, int n, int q, co
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < dim;
        j += (uint64_t)gridDim.x * blockDim.x) {
     const bool b = (j >> q) & 1;
-    const cx<R> f = (b ? d1 : d0) * load<R>(phi, j);
+    const cx<R> f = sel(b, d1, d0) * load<R>(phi, j);
     store<R>(phi, j, f);
     if (NP > 0 || undo_lam) {
       const cx<R> l = load<R>(lam, j);
-      if (NP > 0) acc_dot<R>(acc, l, (b ? e1 : e0) * f);
-      if (undo_lam) store<R>(lam, j, (b ? d1 : d0) * l);
+      if (NP > 0) acc_dot<R>(acc, l, sel(b, e1, e0) * f);
+      if (undo_lam) store<R>(lam, j, sel(b, d1, d0) * l);
     }
   }
   if (NP > 0) block_sum_store<kBlock>(acc, partial + blockIdx.x);

@@ -37,6 +37,13 @@ class KernelStat(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class ScheduleInfo(ctypes.Structure):
+    _fields_ = [("n_passes", ctypes.c_int32), ("n_phases", ctypes.c_int32),
+                ("order", ctypes.c_void_p), ("pass_of", ctypes.c_void_p),
+                ("phase_of", ctypes.c_void_p), ("tile_mask", ctypes.c_void_p),
+                ("reg_mask", ctypes.c_void_p)]
+
+
 class PauliSum(ctypes.Structure):
     _fields_ = [("n_terms", ctypes.c_int32), ("codes", ctypes.c_void_p),
                 ("coeffs", ctypes.c_void_p)]
@@ -73,6 +80,10 @@ def lib() -> ctypes.CDLL:
         "qsv_param_shift_gradient": ([P, P, i32, P, i32, P, i32, i32, P], i32),
         "qsv_timing_enable": ([P, ctypes.c_char_p], i32),
         "qsv_timing_read": ([P, P, i32, ctypes.POINTER(i32)], i32),
+        "qsv_set_fusion": ([P, i32, i32, i32], i32),
+        "qsv_get_fusion": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
+                           i32),
+        "qsv_schedule_describe": ([i32, P, i32, i32, i32, i32, P], i32),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -114,6 +125,24 @@ def validate_pauli_sum(n_qubits: int, codes, coeffs):
     s, keep = pauli_struct(codes, coeffs, n_qubits)
     check(lib().qsv_validate_pauli_sum(n_qubits, ctypes.byref(s)))
     del keep
+
+
+def schedule_describe(n_qubits: int, gates, backward: bool, reg_qubits: int, threads_log2: int):
+    """Host-only: the fused schedule of a circuit as numpy arrays (see qsv_schedule_describe)."""
+    g = as_gate_table(gates)
+    G = g.shape[0]
+    order = np.zeros(max(G, 1), np.int32)
+    pass_of = np.zeros(max(G, 1), np.int32)
+    phase_of = np.zeros(max(G, 1), np.int32)
+    tile = np.zeros(max(G, 1), np.uint64)
+    reg = np.zeros(max(G, 1), np.uint64)
+    info = ScheduleInfo(0, 0, order.ctypes.data, pass_of.ctypes.data, phase_of.ctypes.data,
+                        tile.ctypes.data, reg.ctypes.data)
+    check(lib().qsv_schedule_describe(n_qubits, g.ctypes.data, G, 1 if backward else 0,
+                                      reg_qubits, threads_log2, ctypes.byref(info)))
+    return {"n_passes": info.n_passes, "n_phases": info.n_phases, "order": order[:G],
+            "pass_of": pass_of[:G], "phase_of": phase_of[:G],
+            "tile_mask": tile[:info.n_passes], "reg_mask": reg[:info.n_phases]}
 
 
 def state_bytes(n_qubits: int, dtype: str = "c128") -> int:
@@ -246,6 +275,15 @@ class StateVector:
                                              gr.data_ptr() if gr.numel() else None))
         del keep
         return gr
+
+    def set_fusion(self, mode: int, reg_qubits: int = 0, threads_log2: int = 0):
+        """mode 0: gate-granular; 1: fused with the given geometry; -1: automatic."""
+        check(lib().qsv_set_fusion(self._h, mode, reg_qubits, threads_log2))
+
+    def get_fusion(self):
+        m, r, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().qsv_get_fusion(self._h, ctypes.byref(m), ctypes.byref(r), ctypes.byref(w)))
+        return m.value, r.value, w.value
 
     def timing_enable(self, name_filter: str | None = ""):
         check(lib().qsv_timing_enable(self._h, None if name_filter is None

@@ -1,0 +1,124 @@
+"""GPU parity of the fused pass kernels in every tile geometry, against the CPU oracle.
+
+Covers: every gate kind in random order (so passes mix dense, diagonal, controlled and two-qubit
+ops on register and thread bits), a single tile (no outer qubits), more tiles than workgroups
+(grid-stride over tiles), register phases that change layout, and agreement between the fused
+and the gate-granular paths.
+"""
+import numpy as np
+import pytest
+
+from paper_2009_02823_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GEOMS = {"c128": [(2, 8), (3, 8), (2, 6), (3, 6)], "c64": [(2, 8), (3, 8), (4, 8), (2, 6), (3, 6)]}
+ALL_KINDS = list(W.GATE_NAMES)
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_02823_amd import qsv
+    qsv.lib()
+    return qsv
+
+
+def run(Q, n, gates, theta, codes, coeffs, dtype, geom):
+    with Q.StateVector(n, dtype) as sv:
+        if geom is None:
+            sv.set_fusion(0)
+        else:
+            sv.set_fusion(1, *geom)
+        e, g = sv.adjoint_gradient(gates, theta, codes, coeffs)
+        sv.reset()
+        sv.apply_circuit(gates, theta)
+        sv.sync()
+        return float(e.cpu()[0]), g.cpu().numpy(), sv.state.cpu().numpy().astype(np.complex128)
+
+
+def tol_check(dtype, e, g, psi, e_ref, g_ref, psi_ref, coeffs):
+    if dtype == "c128":
+        scale = max(1.0, float(np.abs(coeffs).sum()))
+        assert abs(e - e_ref.real) <= 1e-10 * scale
+        assert np.max(np.abs(g - g_ref)) <= 1e-10 * scale
+        assert np.max(np.abs(psi - psi_ref)) <= 1e-12
+    else:
+        assert abs(e - e_ref.real) <= 2e-4 * max(abs(e_ref), 1.0)
+        assert np.max(np.abs(g - g_ref)) <= 2e-4 * max(np.max(np.abs(g_ref)), 1e-300)
+        assert np.max(np.abs(psi - psi_ref)) <= 2e-5
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("seed", range(3))
+def test_random_circuits_every_geometry(Q, orc, dtype, seed):
+    rng = np.random.default_rng(2000 + seed)
+    for r, w in GEOMS[dtype]:
+        n = r + w + int(rng.integers(0, 3))      # single tile up to 4 tiles
+        gates, P = W.random_circuit(rng, n, 160, ALL_KINDS, n_params=None if seed != 1 else 40)
+        theta = W.uniform_angles(rng, P)
+        codes = W.random_pauli_strings(rng, n, 9)
+        coeffs = rng.standard_normal(9)
+        e_ref, g_ref = orc.adjoint_gradient(n, gates, theta, codes, coeffs)
+        psi_ref = orc.statevector(n, gates, theta)
+        e, g, psi = run(Q, n, gates, theta, codes, coeffs, dtype, (r, w))
+        tol_check(dtype, e, g, psi, e_ref, g_ref, psi_ref, coeffs)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_hea_many_tiles(Q, orc, dtype):
+    """16 qubits with 10/11-qubit tiles: 32..64 tiles, CZ brickwork, random Pauli strings."""
+    n = 16
+    rng = np.random.default_rng(9)
+    gates = W.hea_circuit(n, 6, cz_brickwork=True)
+    theta = W.uniform_angles(rng, 12 * n)
+    codes = W.random_weight_pauli_strings(rng, n, 30)
+    coeffs = rng.standard_normal(30)
+    e_ref, g_ref = orc.adjoint_gradient(n, gates, theta, codes, coeffs)
+    psi_ref = orc.statevector(n, gates, theta)
+    for geom in GEOMS[dtype][:3]:
+        e, g, psi = run(Q, n, gates, theta, codes, coeffs, dtype, geom)
+        tol_check(dtype, e, g, psi, e_ref, g_ref, psi_ref, coeffs)
+
+
+def test_fused_matches_gate_granular(Q):
+    p = W.config2(n=18, layers=8)
+    e0, g0, s0 = run(Q, p.n_qubits, p.gates, p.theta, p.codes, p.coeffs, "c128", None)
+    e1, g1, s1 = run(Q, p.n_qubits, p.gates, p.theta, p.codes, p.coeffs, "c128", (3, 8))
+    assert abs(e0 - e1) < 1e-13 and np.max(np.abs(g0 - g1)) < 1e-13
+    assert np.max(np.abs(s0 - s1)) < 1e-13
+
+
+def test_more_tiles_than_workgroups(Q):
+    """22 qubits, 11-qubit tiles: 2048 tiles over at most 1024 workgroups; closed form."""
+    import test_oracle_pins as pins
+    n = 22
+    gates, theta, codes, coeffs, E, G = pins.tfim_product_layer(n, np.random.default_rng(1))
+    with Q.StateVector(n) as sv:
+        sv.set_fusion(1, 3, 8)
+        e, g = sv.adjoint_gradient(gates, theta, codes, coeffs)
+        sv.sync()
+    assert abs(float(e.cpu()[0]) - E) < 1e-11
+    assert np.max(np.abs(g.cpu().numpy() - G)) < 1e-11
+
+
+def test_fused_deterministic(Q):
+    p = W.config2(n=16, layers=6)
+    outs = [run(Q, p.n_qubits, p.gates, p.theta, p.codes, p.coeffs, "c128", (3, 8))[:2]
+            for _ in range(3)]
+    for e, g in outs[1:]:
+        assert e == outs[0][0] and np.array_equal(g, outs[0][1])
+
+
+def test_set_fusion_validation(Q):
+    with Q.StateVector(9) as sv:
+        with pytest.raises(Q.QsvError):
+            sv.set_fusion(1, 3, 8)      # tile of 11 qubits > 9
+        with pytest.raises(Q.QsvError):
+            sv.set_fusion(1, 7, 8)      # no kernel for 7 register qubits
+        sv.set_fusion(1, 3, 6)
+        assert sv.get_fusion() == (1, 3, 6)
+        sv.set_fusion(0)
+        assert sv.get_fusion()[0] == 0

@@ -1,0 +1,109 @@
+"""Fusion scheduler (host logic, no GPU): the fused schedule is a valid execution of the circuit.
+
+For every schedule: each gate runs exactly once; the gates on every qubit keep their order
+(forward) or reversed order (reverse sweep); each gate's qubits lie in its pass's tile; each
+gate's non-diagonal targets are register qubits of its phase; passes and phases appear in
+increasing order. Executing the gates in the scheduled order on the CPU oracle gives the same
+state as the original order.
+"""
+import numpy as np
+import pytest
+
+from paper_2009_02823_amd import qsv
+from paper_2009_02823_amd import workloads as W
+
+DIAG = {W.RZ, W.Z, W.S, W.T, W.SDG, W.PHASE, W.CZ, W.RZZ, W.CRZ}
+
+
+def reg_need(row):
+    k, q0, q1 = int(row[0]), int(row[1]), int(row[2])
+    if k in DIAG:
+        return 0
+    if k in (W.CNOT, W.CRX, W.CRY):
+        return 1 << q1
+    if k in (W.RXX, W.RYY):
+        return (1 << q0) | (1 << q1)
+    return 1 << q0
+
+
+def qubits(row):
+    return [int(row[1])] + ([int(row[2])] if W.N_QUBITS[int(row[0])] == 2 else [])
+
+
+def check_schedule(n, gates, backward, r, w):
+    info = qsv.schedule_describe(n, gates, backward, r, w)
+    G = gates.shape[0]
+    order = info["order"]
+    assert sorted(order.tolist()) == list(range(G))
+    assert np.all(np.diff(info["pass_of"]) >= 0) and np.all(np.diff(info["phase_of"]) >= 0)
+    # per-qubit order
+    seq = list(range(G))[::-1] if backward else list(range(G))
+    for q in range(n):
+        want = [k for k in seq if q in qubits(gates[k])]
+        got = [int(k) for k in order if q in qubits(gates[k])]
+        assert got == want, f"qubit {q} order changed"
+    t = r + w
+    for i, k in enumerate(order):
+        tile = int(info["tile_mask"][info["pass_of"][i]])
+        assert bin(tile).count("1") == t
+        for q in qubits(gates[k]):
+            assert (tile >> q) & 1, "gate outside its pass's tile"
+        regm = int(info["reg_mask"][info["phase_of"][i]])
+        assert bin(regm).count("1") == r and (regm & ~tile) == 0
+        assert (reg_need(gates[k]) & ~regm) == 0, "non-diagonal target not in registers"
+    return info
+
+
+@pytest.mark.parametrize("n,L,cz", [(10, 4, False), (12, 3, True), (16, 5, False),
+                                    (20, 20, False), (26, 30, True), (30, 10, False)])
+@pytest.mark.parametrize("backward", [False, True])
+@pytest.mark.parametrize("r,w", [(3, 8), (4, 8), (2, 6)])
+def test_hea_schedules_valid(n, L, cz, backward, r, w):
+    if r + w > n:
+        pytest.skip("tile larger than the state")
+    gates = W.hea_circuit(n, L, cz_brickwork=cz)
+    info = check_schedule(n, gates, backward, r, w)
+    # fusion must cut the number of HBM passes well below one per gate
+    assert info["n_passes"] < gates.shape[0] / 4
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_schedules_valid_and_equivalent(seed, orc):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(8, 13))
+    gates, P = W.random_circuit(rng, n, 150, list(W.GATE_NAMES))
+    theta = W.uniform_angles(rng, P)
+    r, w = (2, 6) if seed % 2 else (3, 6)
+    for backward in (False, True):
+        info = check_schedule(n, gates, backward, r, w)
+        order = info["order"]
+        if backward:
+            # the reverse sweep applies U^dag in the scheduled order: compare U^dag... products
+            psi0 = orc.statevector(n, gates, theta)
+            a = orc.statevector(n, gates, theta, psi_in=psi0, inverse=True)
+            b = psi0.copy()
+            for k in order:
+                b = orc.statevector(n, gates[k:k + 1], theta, psi_in=b, inverse=True)
+            assert np.max(np.abs(a - b)) < 1e-12
+        else:
+            a = orc.statevector(n, gates, theta)
+            b = orc.statevector(n, gates[order], theta)
+            assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_schedule_rejects_bad_geometry():
+    gates = W.hea_circuit(8, 1)
+    with pytest.raises(qsv.QsvError):
+        qsv.schedule_describe(8, gates, False, 4, 8)      # tile of 12 > 8 qubits
+    with pytest.raises(qsv.QsvError):
+        qsv.schedule_describe(8, gates, False, 0, 6)
+
+
+def test_pass_counts_reported():
+    """Pass counts for the measured workloads (printed with -s)."""
+    for n, L, cz, r in [(20, 20, False, 3), (26, 30, True, 4), (30, 10, False, 3)]:
+        gates = W.hea_circuit(n, L, cz_brickwork=cz)
+        f = qsv.schedule_describe(n, gates, False, r, 8)
+        b = qsv.schedule_describe(n, gates, True, r, 8)
+        print(f"n={n} L={L} G={gates.shape[0]} t={r + 8}: forward {f['n_passes']} passes "
+              f"{f['n_phases']} phases, backward {b['n_passes']} passes {b['n_phases']} phases")

@@ -158,6 +158,11 @@ qsv_status qsv_apply_circuit(qsv_state* s, const qsv_gate* gates, int32_t n_gate
    workspace). d_energy: device float64[1]. (Sec. 2.2, the energy functional.) */
 qsv_status qsv_expectation_pauli_sum(qsv_state* s, const qsv_pauli_sum* H, double* d_energy);
 
+/* *d_energy <- <psi|H|psi> with psi = U(theta)|in>, computed in the workspace (the handle's state
+   |in> is left unchanged): the forward pass and expectation of Sec. 2.2 without the sweep. */
+qsv_status qsv_energy(qsv_state* s, const qsv_gate* gates, int32_t n_gates, const double* d_theta,
+                      int32_t n_theta, const qsv_pauli_sum* H, double* d_energy);
+
 /* Reverse-mode gradient (Algorithm 1) with the handle's state as |in> (left unchanged):
      psi = U |in>,  lambda = H psi,  E = <psi|lambda>;
      for i = G..1:  phi <- U_i^dag phi;  grad[param_i] += 2 Re <lambda| dU_i/dtheta |phi>;
@@ -167,6 +172,23 @@ qsv_status qsv_expectation_pauli_sum(qsv_state* s, const qsv_pauli_sum* H, doubl
 qsv_status qsv_adjoint_gradient(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
                                 const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
                                 double* d_energy, double* d_grad);
+
+/* Algorithm 1 for a batch of independent circuits, one handle each (their states are the inputs
+   |in>, left unchanged; every handle uses its own workspace).
+   gates[b], n_gates[b], n_theta[b], H[b]: circuit b (host arrays, as for qsv_adjoint_gradient).
+   d_theta_flat: device float64; circuit b reads theta_off[b] .. theta_off[b] + n_theta[b] - 1.
+   d_energy: device float64[n_batch] <- E_b.  d_grad_flat: device float64, circuit b's gradient
+   is written at theta_off[b] ..; segments must not overlap.
+   All handles must be distinct, on one device, with one dtype; all work is ordered on the stream
+   of states[0] (the other handles must have no work pending on other streams). When every
+   circuit holds a tile of the common geometry, the k-th fused pass of all circuits runs as one
+   launch (levels of the forward pass and of the reverse sweep), else circuits run one after the
+   other. */
+qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* const* states,
+                                        const qsv_gate* const* gates, const int32_t* n_gates,
+                                        const double* d_theta_flat, const int64_t* theta_off,
+                                        const int32_t* n_theta, const qsv_pauli_sum* H,
+                                        double* d_energy, double* d_grad_flat);
 
 /* Faithful O(P^2) baseline on the same GPU (the re-simulation the paper's introduction calls
    "faithful" emulation, here in its parameter-shift form): for p in [first, first + count),

@@ -74,6 +74,27 @@ struct PassDesc {
   int32_t general;                // 1 if any op of the pass is of the general set
 };
 
+// One unit of work of a fused launch: one pass of one circuit over all of its tiles. A launch
+// takes a table of items (several circuits of a batch, or one pass of one circuit) and splits the
+// concatenated tiles into contiguous chunks, one per workgroup. Items are built on the host and
+// hold device pointers only.
+struct PassItem {
+  const PassDesc* pass;
+  const PhaseDesc* phases;
+  const FusedOp* ops;
+  const GateRec* recs;
+  const int32_t* slot_map;
+  const void* src;      // forward: state read by the pass
+  void* dst;            // forward: state written (may equal src); backward: phi
+  void* lam;            // backward: lambda
+  double2* partials;    // backward: this item's block of partials, [local slot][workgroup]
+  int64_t tile_begin;   // first tile of the item in the launch's concatenated tile range
+  int32_t n_outer;      // log2 of the item's tile count
+  int32_t first_wg;     // first workgroup whose chunk reaches into the item
+  int32_t nb;           // workgroups whose chunks reach into the item (partials stride)
+  int32_t pad;
+};
+
 // A schedule of one gate sequence (forward order, or the reverse sweep) as host tables ready to
 // be copied to the device.
 struct Schedule {
@@ -97,18 +118,16 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
 // Launchers of the fused pass kernels. Configurations (r, w) available: see fused_kernels.hip.
 bool fused_config_supported(int r, int w, bool c128);
 
-// `general` selects the kernel instance that also handles the general op set.
+// Launch over `n_items` items whose tiles total `total`; workgroup w takes tiles
+// [w * chunk, (w + 1) * chunk). `general` selects the kernel instance that also handles the
+// general op set.
 template <typename R>
-hipError_t launch_fused_forward(const void* src, void* dst, int n, const PassDesc* d_pass,
-                                const PhaseDesc* d_phases, const FusedOp* d_ops,
-                                const GateRec* d_recs, int r, int w, bool general, int grid,
-                                hipStream_t st);
+hipError_t launch_fused_forward(const PassItem* d_items, int n_items, int64_t total, int64_t chunk,
+                                int r, int w, bool general, int grid, hipStream_t st);
 
 template <typename R>
-hipError_t launch_fused_backward(void* phi, void* lam, int n, const PassDesc* d_pass,
-                                 const PhaseDesc* d_phases, const FusedOp* d_ops,
-                                 const int32_t* d_slot_map, const GateRec* d_recs,
-                                 double2* partials, int nb, int r, int w, bool general, int grid,
+hipError_t launch_fused_backward(const PassItem* d_items, int n_items, int64_t total,
+                                 int64_t chunk, int r, int w, bool general, int grid,
                                  hipStream_t st);
 
 }  // namespace qsv

@@ -101,6 +101,36 @@ __device__ __forceinline__ void relayout(cx<R>* a, const Layout<RB>& from, const
   __syncthreads();
 }
 
+// Both states of the reverse sweep through one pair of barriers (two LDS halves).
+template <typename R, int RB>
+__device__ __forceinline__ void relayout2(cx<R>* a, cx<R>* b, const Layout<RB>& from,
+                                          const Layout<RB>& to, typename Vec2<R>::T* lds,
+                                          int half) {
+  constexpr int NA = 1 << RB;
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    const uint32_t x = Swz<R>::f(from.tdep | reg_deposit<RB>(from, ri));
+    typename Vec2<R>::T v, w;
+    v.x = a[ri].r;
+    v.y = a[ri].i;
+    w.x = b[ri].r;
+    w.y = b[ri].i;
+    lds[x] = v;
+    lds[half + x] = w;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    const uint32_t x = Swz<R>::f(to.tdep | reg_deposit<RB>(to, ri));
+    const typename Vec2<R>::T v = lds[x], w = lds[half + x];
+    a[ri].r = v.x;
+    a[ri].i = v.y;
+    b[ri].r = w.x;
+    b[ri].i = w.y;
+  }
+  __syncthreads();
+}
+
 template <int RB>
 __device__ __forceinline__ bool same_layout(const Layout<RB>& a, const int8_t* rb) {
   bool s = true;
@@ -633,126 +663,152 @@ __device__ __forceinline__ void direct_layout(Layout<RB>& L, uint32_t tid) {
   make_layout<RB, RB + W>(L, rb, tid);
 }
 
+// Item of the chunk-local tile g: the last item whose first tile is <= g (binary search).
+__device__ __forceinline__ int find_item(const PassItem* __restrict__ items, int n_items, int64_t g) {
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tile_begin <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 template <typename R, int RB, int W, bool GEN>
 __global__ void __launch_bounds__(1 << W)
-k_pass_fwd(const typename Vec2<R>::T* src, typename Vec2<R>::T* dst,
-           const PassDesc* __restrict__ pdp, const PhaseDesc* __restrict__ phases,
-           const FusedOp* __restrict__ ops, const GateRec* __restrict__ recs) {
+k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64_t chunk) {
   using G = Geometry<RB, W>;
   using V = typename Vec2<R>::T;
   __shared__ V lds[1 << G::T];
-  const PassDesc pd = *pdp;
   const uint32_t tid = threadIdx.x;
-  uint64_t gthr, groff[G::NA];
-  direct_offsets<RB, W>(pd, tid, gthr, groff);
+  int64_t g0 = (int64_t)blockIdx.x * chunk;
+  const int64_t g1 = g0 + chunk < total ? g0 + chunk : total;
+  if (g0 >= g1) return;
+  int it = find_item(items, n_items, g0);
   Layout<RB> D;
   direct_layout<RB, W>(D, tid);
-  const uint64_t n_tiles = 1ull << pd.n_outer;
-  for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const uint64_t ob = outer_base(pdp, pd.n_outer, tile) | gthr;
-    cx<R> a[G::NA];
+  while (g0 < g1) {
+    const PassItem I = items[it];
+    const PassDesc pd = *I.pass;
+    const int64_t stop = I.tile_begin + (1ll << I.n_outer) < g1 ? I.tile_begin + (1ll << I.n_outer) : g1;
+    const V* src = static_cast<const V*>(I.src);
+    V* dst = static_cast<V*>(I.dst);
+    uint64_t gthr, groff[G::NA];
+    direct_offsets<RB, W>(pd, tid, gthr, groff);
+    for (int64_t g = g0; g < stop; ++g) {
+      const uint64_t ob = outer_base(I.pass, pd.n_outer, (uint64_t)(g - I.tile_begin)) | gthr;
+      cx<R> a[G::NA];
 #pragma unroll
-    for (int ri = 0; ri < G::NA; ++ri) a[ri] = load<R>(src, ob | groff[ri]);
-    Layout<RB> cur = D;
-    int op_at = pd.op_begin;
-    for (int ph = pd.phase_begin; ph < pd.phase_end; ++ph) {
-      const PhaseDesc P = phases[ph];
-      if (!same_layout<RB>(cur, P.regbit)) {
-        Layout<RB> nxt;
-        make_layout<RB, G::T>(nxt, P.regbit, tid);
-        relayout<R, RB>(a, cur, nxt, lds);
-        cur = nxt;
+      for (int ri = 0; ri < G::NA; ++ri) a[ri] = load<R>(src, ob | groff[ri]);
+      Layout<RB> cur = D;
+      int op_at = pd.op_begin;
+      for (int ph = pd.phase_begin; ph < pd.phase_end; ++ph) {
+        const PhaseDesc P = I.phases[ph];
+        if (!same_layout<RB>(cur, P.regbit)) {
+          Layout<RB> nxt;
+          make_layout<RB, G::T>(nxt, P.regbit, tid);
+          relayout<R, RB>(a, cur, nxt, lds);
+          cur = nxt;
+        }
+        const int op_end = pd.op_begin + P.op_end;
+        for (; op_at < op_end; ++op_at) {
+          const FusedOp op = I.ops[op_at];
+          const GateRec* rec = I.recs + op.gate;
+          if (GEN && op.type >= FOP_FIRST_GENERAL) apply_general<R, RB, false>(op, rec, a, cur);
+          else apply_lean<R, RB, false>(op, rec, a, cur.tdep);
+        }
       }
-      const int op_end = pd.op_begin + P.op_end;
-      for (; op_at < op_end; ++op_at) {
-        const FusedOp op = ops[op_at];
-        const GateRec* rec = recs + op.gate;
-        if (GEN && op.type >= FOP_FIRST_GENERAL) apply_general<R, RB, false>(op, rec, a, cur);
-        else apply_lean<R, RB, false>(op, rec, a, cur.tdep);
-      }
+      if (!same_layout<RB>(cur, D.rb)) relayout<R, RB>(a, cur, D, lds);
+#pragma unroll
+      for (int ri = 0; ri < G::NA; ++ri) store<R>(dst, ob | groff[ri], a[ri]);
     }
-    if (!same_layout<RB>(cur, D.rb)) relayout<R, RB>(a, cur, D, lds);
-#pragma unroll
-    for (int ri = 0; ri < G::NA; ++ri) store<R>(dst, ob | groff[ri], a[ri]);
+    g0 = stop;
+    ++it;
   }
 }
 
 template <typename R, int RB, int W, bool GEN>
 __global__ void __launch_bounds__(1 << W)
-k_pass_bwd(typename Vec2<R>::T* __restrict__ phi, typename Vec2<R>::T* __restrict__ lam,
-           const PassDesc* __restrict__ pdp, const PhaseDesc* __restrict__ phases,
-           const FusedOp* __restrict__ ops, const int32_t* __restrict__ slot_map,
-           const GateRec* __restrict__ recs, double2* __restrict__ partials, int nb) {
+k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64_t chunk) {
   using G = Geometry<RB, W>;
   using V = typename Vec2<R>::T;
-  __shared__ V lds[1 << G::T];
+  __shared__ V lds[2 << G::T];
   __shared__ double wacc[kMaxSlotsPerPass][G::NW];
-  const PassDesc pd = *pdp;
   const uint32_t tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < kMaxSlotsPerPass * G::NW; i += G::NT) (&wacc[0][0])[i] = 0.0;
-  __syncthreads();
-  uint64_t gthr, groff[G::NA];
-  direct_offsets<RB, W>(pd, tid, gthr, groff);
+  int64_t g0 = (int64_t)blockIdx.x * chunk;
+  const int64_t g1 = g0 + chunk < total ? g0 + chunk : total;
+  if (g0 >= g1) return;
+  int it = find_item(items, n_items, g0);
   Layout<RB> D;
   direct_layout<RB, W>(D, tid);
-  const uint64_t n_tiles = 1ull << pd.n_outer;
-  for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const uint64_t ob = outer_base(pdp, pd.n_outer, tile) | gthr;
-    cx<R> f[G::NA], l[G::NA];
+  while (g0 < g1) {
+    const PassItem I = items[it];
+    const PassDesc pd = *I.pass;
+    const int64_t stop = I.tile_begin + (1ll << I.n_outer) < g1 ? I.tile_begin + (1ll << I.n_outer) : g1;
+    V* phi = static_cast<V*>(I.dst);
+    V* lam = static_cast<V*>(I.lam);
+    for (int i = tid; i < kMaxSlotsPerPass * G::NW; i += G::NT) (&wacc[0][0])[i] = 0.0;
+    __syncthreads();
+    uint64_t gthr, groff[G::NA];
+    direct_offsets<RB, W>(pd, tid, gthr, groff);
+    for (int64_t g = g0; g < stop; ++g) {
+      const uint64_t ob = outer_base(I.pass, pd.n_outer, (uint64_t)(g - I.tile_begin)) | gthr;
+      cx<R> f[G::NA], l[G::NA];
 #pragma unroll
-    for (int ri = 0; ri < G::NA; ++ri) {
-      f[ri] = load<R>(phi, ob | groff[ri]);
-      l[ri] = load<R>(lam, ob | groff[ri]);
-    }
-    Layout<RB> cur = D;
-    int op_at = pd.op_begin;
-    for (int ph = pd.phase_begin; ph < pd.phase_end; ++ph) {
-      const PhaseDesc P = phases[ph];
-      if (!same_layout<RB>(cur, P.regbit)) {
-        Layout<RB> nxt;
-        make_layout<RB, G::T>(nxt, P.regbit, tid);
-        relayout<R, RB>(f, cur, nxt, lds);
-        relayout<R, RB>(l, cur, nxt, lds);
-        cur = nxt;
+      for (int ri = 0; ri < G::NA; ++ri) {
+        f[ri] = load<R>(phi, ob | groff[ri]);
+        l[ri] = load<R>(lam, ob | groff[ri]);
       }
-      const int op_end = pd.op_begin + P.op_end;
-      for (; op_at < op_end; ++op_at) {
-        const FusedOp op = ops[op_at];
-        const GateRec* rec = recs + op.gate;
-        double prod[3] = {0, 0, 0};
-        if (GEN && op.type >= FOP_FIRST_GENERAL) {
-          apply_general<R, RB, true>(op, rec, f, cur);
-          if (op.np) general_products<R, RB>(op, rec, f, l, cur, prod);
-          apply_general<R, RB, true>(op, rec, l, cur);
-        } else {
-          if (op.np) prod[0] = lean_product<R, RB>(op, f, l, cur.tdep);
-          apply_lean<R, RB, true>(op, rec, f, cur.tdep);
-          apply_lean<R, RB, true>(op, rec, l, cur.tdep);
+      Layout<RB> cur = D;
+      int op_at = pd.op_begin;
+      for (int ph = pd.phase_begin; ph < pd.phase_end; ++ph) {
+        const PhaseDesc P = I.phases[ph];
+        if (!same_layout<RB>(cur, P.regbit)) {
+          Layout<RB> nxt;
+          make_layout<RB, G::T>(nxt, P.regbit, tid);
+          relayout2<R, RB>(f, l, cur, nxt, lds, 1 << G::T);
+          cur = nxt;
         }
+        const int op_end = pd.op_begin + P.op_end;
+        for (; op_at < op_end; ++op_at) {
+          const FusedOp op = I.ops[op_at];
+          const GateRec* rec = I.recs + op.gate;
+          double prod[3] = {0, 0, 0};
+          if (GEN && op.type >= FOP_FIRST_GENERAL) {
+            apply_general<R, RB, true>(op, rec, f, cur);
+            if (op.np) general_products<R, RB>(op, rec, f, l, cur, prod);
+            apply_general<R, RB, true>(op, rec, l, cur);
+          } else {
+            if (op.np) prod[0] = lean_product<R, RB>(op, f, l, cur.tdep);
+            apply_lean<R, RB, true>(op, rec, f, cur.tdep);
+            apply_lean<R, RB, true>(op, rec, l, cur.tdep);
+          }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          if (j >= op.np) break;
-          const double s = wave_total_lane63(prod[j]);
-          if (lane == 63) wacc[op.lslot + j][wave] += s;
+          for (int j = 0; j < 3; ++j) {
+            if (j >= op.np) break;
+            const double s = wave_total_lane63(prod[j]);
+            if (lane == 63) wacc[op.lslot + j][wave] += s;
+          }
         }
       }
-    }
-    if (!same_layout<RB>(cur, D.rb)) {
-      relayout<R, RB>(f, cur, D, lds);
-      relayout<R, RB>(l, cur, D, lds);
-    }
+      if (!same_layout<RB>(cur, D.rb)) relayout2<R, RB>(f, l, cur, D, lds, 1 << G::T);
 #pragma unroll
-    for (int ri = 0; ri < G::NA; ++ri) {
-      store<R>(phi, ob | groff[ri], f[ri]);
-      store<R>(lam, ob | groff[ri], l[ri]);
+      for (int ri = 0; ri < G::NA; ++ri) {
+        store<R>(phi, ob | groff[ri], f[ri]);
+        store<R>(lam, ob | groff[ri], l[ri]);
+      }
     }
-  }
-  __syncthreads();
-  for (int j = tid; j < pd.n_slots; j += G::NT) {
-    double s = 0;
-    for (int w = 0; w < G::NW; ++w) s += wacc[j][w];
-    partials[(size_t)slot_map[pd.slot_begin + j] * nb + blockIdx.x] = make_double2(s, 0.0);
+    __syncthreads();
+    const int col = (int)blockIdx.x - I.first_wg;
+    for (int j = tid; j < pd.n_slots; j += G::NT) {
+      double s = 0;
+      for (int w = 0; w < G::NW; ++w) s += wacc[j][w];
+      I.partials[(size_t)j * I.nb + col] = make_double2(s, 0.0);
+    }
+    __syncthreads();
+    g0 = stop;
+    ++it;
   }
 }
 
@@ -770,23 +826,17 @@ bool fused_config_supported(int r, int w, bool c128) {
 #define QSV_FUSED_CASES(X, R) X(R, 2, 8) X(R, 3, 8) X(R, 2, 6) X(R, 3, 6)
 
 template <typename R>
-hipError_t launch_fused_forward(const void* src, void* dst, int n, const PassDesc* d_pass,
-                                const PhaseDesc* d_phases, const FusedOp* d_ops,
-                                const GateRec* d_recs, int r, int w, bool general, int grid,
-                                hipStream_t st) {
-  using V = typename Vec2<R>::T;
-  (void)n;
-#define X(RR, RB, WW)                                                                           \
-  if (r == RB && w == WW) {                                                                     \
-    if (general)                                                                                \
-      hipLaunchKernelGGL((k_pass_fwd<RR, RB, WW, true>), dim3(grid), dim3(1 << WW), 0, st,      \
-                         static_cast<const V*>(src), static_cast<V*>(dst), d_pass, d_phases,    \
-                         d_ops, d_recs);                                                        \
-    else                                                                                        \
-      hipLaunchKernelGGL((k_pass_fwd<RR, RB, WW, false>), dim3(grid), dim3(1 << WW), 0, st,     \
-                         static_cast<const V*>(src), static_cast<V*>(dst), d_pass, d_phases,    \
-                         d_ops, d_recs);                                                        \
-    return hipGetLastError();                                                                   \
+hipError_t launch_fused_forward(const PassItem* d_items, int n_items, int64_t total, int64_t chunk,
+                                int r, int w, bool general, int grid, hipStream_t st) {
+#define X(RR, RB, WW)                                                                          \
+  if (r == RB && w == WW) {                                                                    \
+    if (general)                                                                               \
+      hipLaunchKernelGGL((k_pass_fwd<RR, RB, WW, true>), dim3(grid), dim3(1 << WW), 0, st,     \
+                         d_items, n_items, total, chunk);                                      \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_pass_fwd<RR, RB, WW, false>), dim3(grid), dim3(1 << WW), 0, st,    \
+                         d_items, n_items, total, chunk);                                      \
+    return hipGetLastError();                                                                  \
   }
   QSV_FUSED_CASES(X, R)
   if constexpr (sizeof(R) == 4) { X(R, 4, 8) }
@@ -795,24 +845,18 @@ hipError_t launch_fused_forward(const void* src, void* dst, int n, const PassDes
 }
 
 template <typename R>
-hipError_t launch_fused_backward(void* phi, void* lam, int n, const PassDesc* d_pass,
-                                 const PhaseDesc* d_phases, const FusedOp* d_ops,
-                                 const int32_t* d_slot_map, const GateRec* d_recs,
-                                 double2* partials, int nb, int r, int w, bool general, int grid,
+hipError_t launch_fused_backward(const PassItem* d_items, int n_items, int64_t total,
+                                 int64_t chunk, int r, int w, bool general, int grid,
                                  hipStream_t st) {
-  using V = typename Vec2<R>::T;
-  (void)n;
-#define X(RR, RB, WW)                                                                           \
-  if (r == RB && w == WW) {                                                                     \
-    if (general)                                                                                \
-      hipLaunchKernelGGL((k_pass_bwd<RR, RB, WW, true>), dim3(grid), dim3(1 << WW), 0, st,      \
-                         static_cast<V*>(phi), static_cast<V*>(lam), d_pass, d_phases, d_ops,   \
-                         d_slot_map, d_recs, partials, nb);                                     \
-    else                                                                                        \
-      hipLaunchKernelGGL((k_pass_bwd<RR, RB, WW, false>), dim3(grid), dim3(1 << WW), 0, st,     \
-                         static_cast<V*>(phi), static_cast<V*>(lam), d_pass, d_phases, d_ops,   \
-                         d_slot_map, d_recs, partials, nb);                                     \
-    return hipGetLastError();                                                                   \
+#define X(RR, RB, WW)                                                                          \
+  if (r == RB && w == WW) {                                                                    \
+    if (general)                                                                               \
+      hipLaunchKernelGGL((k_pass_bwd<RR, RB, WW, true>), dim3(grid), dim3(1 << WW), 0, st,     \
+                         d_items, n_items, total, chunk);                                      \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_pass_bwd<RR, RB, WW, false>), dim3(grid), dim3(1 << WW), 0, st,    \
+                         d_items, n_items, total, chunk);                                      \
+    return hipGetLastError();                                                                  \
   }
   QSV_FUSED_CASES(X, R)
   if constexpr (sizeof(R) == 4) { X(R, 4, 8) }
@@ -820,19 +864,13 @@ hipError_t launch_fused_backward(void* phi, void* lam, int n, const PassDesc* d_
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_fused_forward<double>(const void*, void*, int, const PassDesc*,
-                                                 const PhaseDesc*, const FusedOp*, const GateRec*,
-                                                 int, int, bool, int, hipStream_t);
-template hipError_t launch_fused_forward<float>(const void*, void*, int, const PassDesc*,
-                                                const PhaseDesc*, const FusedOp*, const GateRec*,
-                                                int, int, bool, int, hipStream_t);
-template hipError_t launch_fused_backward<double>(void*, void*, int, const PassDesc*,
-                                                  const PhaseDesc*, const FusedOp*,
-                                                  const int32_t*, const GateRec*, double2*, int,
-                                                  int, int, bool, int, hipStream_t);
-template hipError_t launch_fused_backward<float>(void*, void*, int, const PassDesc*,
-                                                 const PhaseDesc*, const FusedOp*, const int32_t*,
-                                                 const GateRec*, double2*, int, int, int, bool,
-                                                 int, hipStream_t);
+template hipError_t launch_fused_forward<double>(const PassItem*, int, int64_t, int64_t, int, int,
+                                                 bool, int, hipStream_t);
+template hipError_t launch_fused_forward<float>(const PassItem*, int, int64_t, int64_t, int, int,
+                                                bool, int, hipStream_t);
+template hipError_t launch_fused_backward<double>(const PassItem*, int, int64_t, int64_t, int,
+                                                  int, bool, int, hipStream_t);
+template hipError_t launch_fused_backward<float>(const PassItem*, int, int64_t, int64_t, int, int,
+                                                 bool, int, hipStream_t);
 
 }  // namespace qsv

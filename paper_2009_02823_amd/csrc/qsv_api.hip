@@ -162,9 +162,20 @@ struct FusedSchedule {
   Schedule sched;
   DevBuf d_passes, d_phases, d_ops, d_slot_map;
 };
+
+// A circuit's fused schedules bound to one handle's buffers: one launch item per pass (forward
+// into phi, forward in place on the state, reverse sweep), the reverse sweep's partials and the
+// descriptors the final reduction reads them with.
 struct FusedPlan {
-  int r = 0, w = 0;
+  int r = 0, w = 0, t = 0;
   FusedSchedule fwd, bwd;
+  int64_t tiles = 0, chunk = 1;
+  int grid = 1, nb = 1;
+  std::vector<PassItem> items_fwd_phi, items_fwd_state, items_bwd;
+  std::vector<int64_t> occ_base;  // per global slot, relative to the partials buffer
+  std::vector<int32_t> occ_nb;
+  DevBuf d_items_fwd_phi, d_items_fwd_state, d_items_bwd, partials, d_occ_base, d_occ_nb,
+      d_final;
 };
 
 // A circuit lowered for the device: gate table, matrix records, and the map from parameters to
@@ -177,6 +188,9 @@ struct Plan {
   std::vector<int32_t> param_ptr, occ;
   DevBuf d_gates, d_recs, d_param_ptr, d_occ;
   std::map<int, std::unique_ptr<FusedPlan>> fused;  // key r * 16 + w
+  // gate-granular reverse sweep: partials [slot][block] and their descriptors
+  bool gg_ready = false;
+  DevBuf gg_partials, d_gg_occ_base, d_gg_occ_nb, d_gg_final;
 };
 
 struct PauliPlan {
@@ -217,6 +231,24 @@ struct Timer {
   }
 };
 
+// A batch of circuits (one handle each) run level by level: level k of the forward pass (or of
+// the reverse sweep) is one launch over the k-th pass of every circuit that has one.
+struct BatchLevel {
+  DevBuf d_items;
+  int n_items = 0;
+  int64_t total = 0, chunk = 1;
+  int grid = 1;
+  bool general = false;
+};
+struct BatchPlan {
+  std::vector<qsv_state*> states;
+  std::vector<Plan*> plans;
+  int r = 0, w = 0;
+  std::vector<std::unique_ptr<BatchLevel>> fwd, bwd;
+  DevBuf partials, d_occ_base, d_occ_nb, d_final;
+  int64_t total_params = 0;
+};
+
 struct qsv_state {
   int n = 0;
   qsv_dtype dt = QSV_C128;
@@ -230,8 +262,9 @@ struct qsv_state {
   int fr = 0, fw = 0;
   std::unordered_map<uint64_t, std::unique_ptr<Plan>> plans;
   std::unordered_map<uint64_t, std::unique_ptr<PauliPlan>> paulis;
-  DevBuf partials, epartials, theta_scratch, energies;
+  DevBuf epartials, theta_scratch, energies;
   Timer timer;
+  std::unordered_map<uint64_t, std::unique_ptr<BatchPlan>> batches;
 };
 
 static constexpr size_t kMaxCachedPlans = 64;
@@ -522,6 +555,60 @@ static qsv_status upload_schedule(FusedSchedule& fs, hipStream_t st) {
   return QSV_OK;
 }
 
+template <typename T>
+static qsv_status upload_vec(DevBuf& b, const std::vector<T>& v, hipStream_t st) {
+  QSV_TRY(b.ensure(sizeof(T) * (v.size() ? v.size() : 1), st));
+  if (!v.empty())
+    HIP_TRY(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+  return QSV_OK;
+}
+
+// Launch geometry of `total` tiles: workgroups, tiles per workgroup, and for an item occupying
+// tiles [begin, begin + count) the first workgroup reaching into it and how many do.
+static void launch_shape(int64_t total, int* grid, int64_t* chunk) {
+  const int64_t g = std::min<int64_t>(total, kFusedGridCap);
+  *grid = (int)(g < 1 ? 1 : g);
+  *chunk = (total + *grid - 1) / *grid;
+  if (*chunk < 1) *chunk = 1;
+}
+static void item_span(int64_t begin, int64_t count, int64_t chunk, int32_t* first, int32_t* nb) {
+  const int64_t f = begin / chunk, l = (begin + count - 1) / chunk;
+  *first = (int32_t)f;
+  *nb = (int32_t)(l - f + 1);
+}
+
+static PassItem make_item(const FusedSchedule& fs, size_t i, const Plan* p, const void* src,
+                          void* dst, void* lam, int n_outer) {
+  PassItem it;
+  std::memset(&it, 0, sizeof it);
+  it.pass = fs.d_passes.as<PassDesc>() + i;
+  it.phases = fs.d_phases.as<PhaseDesc>();
+  it.ops = fs.d_ops.as<FusedOp>();
+  it.recs = p->d_recs.as<GateRec>();
+  it.slot_map = fs.d_slot_map.as<int32_t>();
+  it.src = src;
+  it.dst = dst;
+  it.lam = lam;
+  it.n_outer = n_outer;
+  return it;
+}
+
+static qsv_status upload_final(DevBuf& d_final, const DevBuf& partials, const DevBuf& occ_base,
+                               const DevBuf& occ_nb, const Plan* p, hipStream_t st) {
+  FinalDesc fd;
+  std::memset(&fd, 0, sizeof fd);
+  fd.partials = partials.as<double2>();
+  fd.occ_base = occ_base.as<int64_t>();
+  fd.occ_nb = occ_nb.as<int32_t>();
+  fd.param_ptr = p->d_param_ptr.as<int32_t>();
+  fd.occ = p->d_occ.as<int32_t>();
+  fd.grad_off = 0;
+  fd.p_begin = 0;
+  fd.n_theta = p->n_theta;
+  std::vector<FinalDesc> v(1, fd);
+  return upload_vec(d_final, v, st);
+}
+
 static qsv_status get_fused(qsv_state* s, Plan* p, int r, int w, FusedPlan** out) {
   const int key = r * 16 + w;
   auto it = p->fused.find(key);
@@ -531,9 +618,11 @@ static qsv_status get_fused(qsv_state* s, Plan* p, int r, int w, FusedPlan** out
   }
   if (!fused_config_supported(r, w, s->dt == QSV_C128) || r + w > s->n)
     return fail(QSV_ERR_UNSUPPORTED, "fused geometry r=%d w=%d not available for n=%d", r, w, s->n);
+  const hipStream_t st = s->stream;
   auto fp = std::make_unique<FusedPlan>();
   fp->r = r;
   fp->w = w;
+  fp->t = r + w;
   const int G = (int)p->gates.size();
   std::vector<int> seq(G);
   std::string msg;
@@ -543,36 +632,89 @@ static qsv_status get_fused(qsv_state* s, Plan* p, int r, int w, FusedPlan** out
   for (int k = 0; k < G; ++k) seq[k] = G - 1 - k;
   if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, true, r + w, r, w, fp->bwd.sched, &msg))
     return fail(QSV_ERR_INTERNAL, "backward schedule: %s", msg.c_str());
-  QSV_TRY(upload_schedule(fp->fwd, s->stream));
-  QSV_TRY(upload_schedule(fp->bwd, s->stream));
+  QSV_TRY(upload_schedule(fp->fwd, st));
+  QSV_TRY(upload_schedule(fp->bwd, st));
+
+  // single-circuit launch items
+  const int n_outer = s->n - fp->t;
+  fp->tiles = 1ll << n_outer;
+  launch_shape(fp->tiles, &fp->grid, &fp->chunk);
+  int32_t first = 0, nb = 1;
+  item_span(0, fp->tiles, fp->chunk, &first, &nb);
+  fp->nb = nb;
+  void* phi = s->d_work;
+  void* lam = static_cast<char*>(s->d_work) + qsv_state_bytes(s->n, s->dt);
+  for (size_t i = 0; i < fp->fwd.sched.passes.size(); ++i) {
+    PassItem a = make_item(fp->fwd, i, p, i == 0 ? s->d_state : phi, phi, nullptr, n_outer);
+    a.nb = nb;
+    fp->items_fwd_phi.push_back(a);
+    PassItem b = make_item(fp->fwd, i, p, s->d_state, s->d_state, nullptr, n_outer);
+    b.nb = nb;
+    fp->items_fwd_state.push_back(b);
+  }
+  const Schedule& bs = fp->bwd.sched;
+  int64_t total_partials = 0;
+  for (const PassDesc& pd : bs.passes) total_partials += (int64_t)pd.n_slots * nb;
+  QSV_TRY(fp->partials.ensure(sizeof(double2) * (total_partials ? total_partials : 1), st));
+  fp->occ_base.assign(p->n_occ ? p->n_occ : 1, 0);
+  fp->occ_nb.assign(p->n_occ ? p->n_occ : 1, 0);
+  int64_t off = 0;
+  for (size_t i = 0; i < bs.passes.size(); ++i) {
+    const PassDesc& pd = bs.passes[i];
+    PassItem b = make_item(fp->bwd, i, p, nullptr, phi, lam, n_outer);
+    b.nb = nb;
+    b.partials = fp->partials.as<double2>() + off;
+    fp->items_bwd.push_back(b);
+    for (int j = 0; j < pd.n_slots; ++j) {
+      const int gs = bs.slot_map[pd.slot_begin + j];
+      fp->occ_base[gs] = off + (int64_t)j * nb;
+      fp->occ_nb[gs] = nb;
+    }
+    off += (int64_t)pd.n_slots * nb;
+  }
+  QSV_TRY(upload_vec(fp->d_items_fwd_phi, fp->items_fwd_phi, st));
+  QSV_TRY(upload_vec(fp->d_items_fwd_state, fp->items_fwd_state, st));
+  QSV_TRY(upload_vec(fp->d_items_bwd, fp->items_bwd, st));
+  QSV_TRY(upload_vec(fp->d_occ_base, fp->occ_base, st));
+  QSV_TRY(upload_vec(fp->d_occ_nb, fp->occ_nb, st));
+  QSV_TRY(upload_final(fp->d_final, fp->partials, fp->d_occ_base, fp->d_occ_nb, p, st));
   *out = fp.get();
   p->fused[key] = std::move(fp);
   return QSV_OK;
 }
 
-static int fused_grid(int n, int t) {
-  const uint64_t tiles = 1ull << (n - t);
-  return (int)std::min<uint64_t>(tiles, (uint64_t)kFusedGridCap);
+// Gate-granular reverse-sweep partials: slot o has nb consecutive block partials at o * nb.
+static qsv_status get_gate_granular(qsv_state* s, Plan* p) {
+  if (p->gg_ready) return QSV_OK;
+  const hipStream_t st = s->stream;
+  const int nb = s->nb, no = p->n_occ ? p->n_occ : 1;
+  QSV_TRY(p->gg_partials.ensure(sizeof(double2) * (size_t)no * nb, st));
+  std::vector<int64_t> base(no);
+  std::vector<int32_t> cnt(no, nb);
+  for (int o = 0; o < no; ++o) base[o] = (int64_t)o * nb;
+  QSV_TRY(upload_vec(p->d_gg_occ_base, base, st));
+  QSV_TRY(upload_vec(p->d_gg_occ_nb, cnt, st));
+  QSV_TRY(upload_final(p->d_gg_final, p->gg_partials, p->d_gg_occ_base, p->d_gg_occ_nb, p, st));
+  p->gg_ready = true;
+  return QSV_OK;
 }
 
-// psi_dst <- U psi_src (src may equal dst).
+// dst <- U src (fused: into phi or in place on the state; gate-granular: any pair of buffers).
 template <typename R>
 static qsv_status forward(qsv_state* s, Plan* p, const void* src, void* dst) {
   const double S = state_bytes_d(s);
   const hipStream_t st = s->stream;
   int r = 0, w = 0;
-  if (fusion_geometry(s, &r, &w) && !p->gates.empty()) {
+  if (fusion_geometry(s, &r, &w) && !p->gates.empty() &&
+      (src == dst ? dst == s->d_state : (src == s->d_state && dst == s->d_work))) {
     FusedPlan* fp = nullptr;
     QSV_TRY(get_fused(s, p, r, w, &fp));
     const Schedule& sc = fp->fwd.sched;
-    const int grid = fused_grid(s->n, r + w);
+    const PassItem* items = (src == dst ? fp->d_items_fwd_state : fp->d_items_fwd_phi).as<PassItem>();
     for (size_t i = 0; i < sc.passes.size(); ++i) {
-      const void* from = i == 0 ? src : dst;
       QSV_TRY(timed(s, "k_pass_fwd", 2 * S, [&] {
-        return launch_fused_forward<R>(from, dst, s->n, fp->fwd.d_passes.as<PassDesc>() + i,
-                                       fp->fwd.d_phases.as<PhaseDesc>(),
-                                       fp->fwd.d_ops.as<FusedOp>(), p->d_recs.as<GateRec>(), r,
-                                       w, sc.passes[i].general != 0, grid, st);
+        return launch_fused_forward<R>(items + i, 1, fp->tiles, fp->chunk, r, w,
+                                       sc.passes[i].general != 0, fp->grid, st);
       }));
     }
     return QSV_OK;
@@ -588,37 +730,33 @@ static qsv_status forward(qsv_state* s, Plan* p, const void* src, void* dst) {
   return QSV_OK;
 }
 
-// The reverse sweep of Algorithm 1 over (phi, lambda); per-slot partials of Re <lambda|mu> are
-// written with stride *nb_out.
+// The reverse sweep of Algorithm 1 over (phi, lambda) = the workspace; *final_desc receives the
+// descriptor table the final reduction reads the partials with.
 template <typename R>
-static qsv_status backward(qsv_state* s, Plan* p, void* phi, void* lam, int* nb_out) {
+static qsv_status backward(qsv_state* s, Plan* p, const FinalDesc** final_desc) {
   const double S = state_bytes_d(s);
   const hipStream_t st = s->stream;
   const int n = s->n;
+  void* phi = s->d_work;
+  void* lam = static_cast<char*>(s->d_work) + qsv_state_bytes(n, s->dt);
   int r = 0, w = 0;
   if (fusion_geometry(s, &r, &w) && !p->gates.empty()) {
     FusedPlan* fp = nullptr;
     QSV_TRY(get_fused(s, p, r, w, &fp));
     const Schedule& sc = fp->bwd.sched;
-    const int nb = fused_grid(n, r + w);
-    QSV_TRY(s->partials.ensure(sizeof(double2) * (size_t)(p->n_occ ? p->n_occ : 1) * nb, st));
-    double2* part = s->partials.as<double2>();
+    const PassItem* items = fp->d_items_bwd.as<PassItem>();
     for (size_t i = 0; i < sc.passes.size(); ++i) {
       QSV_TRY(timed(s, "k_pass_bwd", 4 * S, [&] {
-        return launch_fused_backward<R>(phi, lam, n, fp->bwd.d_passes.as<PassDesc>() + i,
-                                        fp->bwd.d_phases.as<PhaseDesc>(),
-                                        fp->bwd.d_ops.as<FusedOp>(),
-                                        fp->bwd.d_slot_map.as<int32_t>(),
-                                        p->d_recs.as<GateRec>(), part, nb, r, w,
-                                        sc.passes[i].general != 0, nb, st);
+        return launch_fused_backward<R>(items + i, 1, fp->tiles, fp->chunk, r, w,
+                                        sc.passes[i].general != 0, fp->grid, st);
       }));
     }
-    *nb_out = nb;
+    *final_desc = fp->d_final.as<FinalDesc>();
     return QSV_OK;
   }
+  QSV_TRY(get_gate_granular(s, p));
   const int nb = s->nb;
-  QSV_TRY(s->partials.ensure(sizeof(double2) * (size_t)(p->n_occ ? p->n_occ : 1) * nb, st));
-  double2* part = s->partials.as<double2>();
+  double2* part = p->gg_partials.as<double2>();
   for (int k = (int)p->gates.size() - 1; k >= 0; --k) {
     const int slot = p->slot_of_gate[k];
     const GateDesc& g = p->gates[k];
@@ -627,7 +765,7 @@ static qsv_status backward(qsv_state* s, Plan* p, void* phi, void* lam, int* nb_
                                      slot >= 0 ? part + (size_t)slot * nb : nullptr, nb, st);
     }));
   }
-  *nb_out = nb;
+  *final_desc = p->d_gg_final.as<FinalDesc>();
   return QSV_OK;
 }
 
@@ -674,16 +812,44 @@ extern "C" qsv_status qsv_expectation_pauli_sum(qsv_state* s, const qsv_pauli_su
 }
 
 template <typename R>
+static qsv_status energy_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* d_theta,
+                           double* d_energy) {
+  QSV_TRY(s->epartials.ensure(sizeof(double2) * s->nb, s->stream));
+  double2* ep = s->epartials.as<double2>();
+  HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
+                      p->d_recs.as<GateRec>(), s->stream));
+  void* phi = s->d_work;
+  QSV_TRY(forward<R>(s, p, s->d_state, phi));
+  QSV_TRY(pauli<R>(s, hp, phi, nullptr, ep));
+  HIP_TRY(launch_final_energy(ep, s->nb, d_energy, nullptr, s->stream));
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_energy(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                                 const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
+                                 double* d_energy) {
+  QSV_TRY(check_handle(s));
+  QSV_TRY(qsv_validate_circuit(s->n, gates, n_gates, n_theta));
+  QSV_TRY(qsv_validate_pauli_sum(s->n, H));
+  if (!d_energy) return fail(QSV_ERR_INVALID_ARG, "d_energy is NULL");
+  Plan* p = nullptr;
+  QSV_TRY(get_plan(s, gates, n_gates, n_theta, &p));
+  QSV_TRY(check_theta(p, d_theta));
+  PauliPlan* hp = nullptr;
+  QSV_TRY(get_pauli(s, H, &hp));
+  return s->dt == QSV_C128 ? energy_t<double>(s, p, hp, d_theta, d_energy)
+                           : energy_t<float>(s, p, hp, d_theta, d_energy);
+}
+
+template <typename R>
 static qsv_status adjoint_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* d_theta,
                             double* d_energy, double* d_grad) {
   const hipStream_t st = s->stream;
-  const int n = s->n, nb = s->nb;
-  const size_t sb = qsv_state_bytes(n, s->dt);
+  const int nb = s->nb;
   void* phi = s->d_work;
-  void* lam = static_cast<char*>(s->d_work) + sb;
+  void* lam = static_cast<char*>(s->d_work) + qsv_state_bytes(s->n, s->dt);
   QSV_TRY(s->epartials.ensure(sizeof(double2) * nb, st));
   double2* ep = s->epartials.as<double2>();
-
   HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
                       p->d_recs.as<GateRec>(), st));
   // Algorithm 1: the clone lambda := |in> and the forward pass build psi in the phi buffer (the
@@ -692,10 +858,9 @@ static qsv_status adjoint_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* 
   QSV_TRY(forward<R>(s, p, s->d_state, phi));
   QSV_TRY(pauli<R>(s, hp, phi, lam, ep));
   HIP_TRY(launch_final_energy(ep, nb, d_energy, nullptr, st));
-  int nbp = 1;
-  QSV_TRY(backward<R>(s, p, phi, lam, &nbp));
-  HIP_TRY(launch_final_grad(s->partials.as<double2>(), nbp, p->d_param_ptr.as<int32_t>(),
-                            p->d_occ.as<int32_t>(), p->n_theta, d_grad, nullptr, st));
+  const FinalDesc* fd = nullptr;
+  QSV_TRY(backward<R>(s, p, &fd));
+  HIP_TRY(launch_final_grad(fd, 1, p->n_theta, d_grad, st));
   return QSV_OK;
 }
 
@@ -715,6 +880,250 @@ extern "C" qsv_status qsv_adjoint_gradient(qsv_state* s, const qsv_gate* gates, 
   QSV_TRY(get_pauli(s, H, &hp));
   return s->dt == QSV_C128 ? adjoint_t<double>(s, p, hp, d_theta, d_energy, d_grad)
                            : adjoint_t<float>(s, p, hp, d_theta, d_energy, d_grad);
+}
+// ------------------------------------------------------------------------------------------------
+// batches of independent circuits
+// ------------------------------------------------------------------------------------------------
+static constexpr size_t kMaxCachedBatches = 8;
+
+// Routes the per-circuit helper launches of a batch onto one stream for the duration of a call.
+struct StreamOverride {
+  std::vector<std::pair<qsv_state*, hipStream_t>> saved;
+  StreamOverride(qsv_state* const* states, int n, hipStream_t st) {
+    for (int b = 0; b < n; ++b) {
+      saved.push_back({states[b], states[b]->stream});
+      states[b]->stream = st;
+    }
+  }
+  ~StreamOverride() {
+    for (auto& kv : saved) kv.first->stream = kv.second;
+  }
+};
+
+static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>& plans, int B,
+                              const int64_t* theta_off, int r, int w, BatchPlan* bp) {
+  qsv_state* s0 = states[0];
+  const hipStream_t st = s0->stream;
+  bp->r = r;
+  bp->w = w;
+  std::vector<FusedPlan*> fps(B);
+  size_t lf = 0, lb = 0;
+  for (int b = 0; b < B; ++b) {
+    QSV_TRY(get_fused(states[b], plans[b], r, w, &fps[b]));
+    lf = std::max(lf, fps[b]->fwd.sched.passes.size());
+    lb = std::max(lb, fps[b]->bwd.sched.passes.size());
+  }
+  // forward levels
+  for (size_t k = 0; k < lf; ++k) {
+    auto L = std::make_unique<BatchLevel>();
+    std::vector<PassItem> items;
+    for (int b = 0; b < B; ++b) {
+      if (k >= fps[b]->fwd.sched.passes.size()) continue;
+      PassItem it = fps[b]->items_fwd_phi[k];
+      it.tile_begin = L->total;
+      L->total += fps[b]->tiles;
+      L->general = L->general || fps[b]->fwd.sched.passes[k].general;
+      items.push_back(it);
+    }
+    launch_shape(L->total, &L->grid, &L->chunk);
+    for (PassItem& it : items) item_span(it.tile_begin, 1ll << it.n_outer, L->chunk, &it.first_wg, &it.nb);
+    L->n_items = (int)items.size();
+    QSV_TRY(upload_vec(L->d_items, items, st));
+    bp->fwd.push_back(std::move(L));
+  }
+  // reverse-sweep levels: partial blocks [local slot][workgroup] per (level, circuit)
+  std::vector<std::vector<PassItem>> level_items(lb);
+  std::vector<std::vector<int>> level_owner(lb);
+  int64_t total_partials = 0;
+  for (size_t k = 0; k < lb; ++k) {
+    auto L = std::make_unique<BatchLevel>();
+    for (int b = 0; b < B; ++b) {
+      if (k >= fps[b]->bwd.sched.passes.size()) continue;
+      PassItem it = fps[b]->items_bwd[k];
+      it.tile_begin = L->total;
+      L->total += fps[b]->tiles;
+      L->general = L->general || fps[b]->bwd.sched.passes[k].general;
+      level_items[k].push_back(it);
+      level_owner[k].push_back(b);
+    }
+    launch_shape(L->total, &L->grid, &L->chunk);
+    for (PassItem& it : level_items[k])
+      item_span(it.tile_begin, 1ll << it.n_outer, L->chunk, &it.first_wg, &it.nb);
+    L->n_items = (int)level_items[k].size();
+    bp->bwd.push_back(std::move(L));
+  }
+  std::vector<int64_t> occ_base;
+  std::vector<int32_t> occ_nb;
+  std::vector<int64_t> occ_off(B);
+  for (int b = 0; b < B; ++b) {
+    occ_off[b] = (int64_t)occ_base.size();
+    const int no = plans[b]->n_occ ? plans[b]->n_occ : 1;
+    occ_base.resize(occ_base.size() + no, 0);
+    occ_nb.resize(occ_nb.size() + no, 0);
+  }
+  int64_t off = 0;
+  std::vector<std::vector<int64_t>> item_off(lb);
+  for (size_t k = 0; k < lb; ++k) {
+    for (size_t i = 0; i < level_items[k].size(); ++i) {
+      const int b = level_owner[k][i];
+      const Schedule& bs = fps[b]->bwd.sched;
+      const PassDesc& pd = bs.passes[k];
+      const PassItem& it = level_items[k][i];
+      item_off[k].push_back(off);
+      for (int j = 0; j < pd.n_slots; ++j) {
+        const int gs = bs.slot_map[pd.slot_begin + j];
+        occ_base[occ_off[b] + gs] = off + (int64_t)j * it.nb;
+        occ_nb[occ_off[b] + gs] = it.nb;
+      }
+      off += (int64_t)pd.n_slots * it.nb;
+    }
+  }
+  total_partials = off;
+  QSV_TRY(bp->partials.ensure(sizeof(double2) * (total_partials ? total_partials : 1), st));
+  for (size_t k = 0; k < lb; ++k) {
+    for (size_t i = 0; i < level_items[k].size(); ++i)
+      level_items[k][i].partials = bp->partials.as<double2>() + item_off[k][i];
+    QSV_TRY(upload_vec(bp->bwd[k]->d_items, level_items[k], st));
+  }
+  QSV_TRY(upload_vec(bp->d_occ_base, occ_base, st));
+  QSV_TRY(upload_vec(bp->d_occ_nb, occ_nb, st));
+  std::vector<FinalDesc> fds(B);
+  int64_t pb = 0;
+  for (int b = 0; b < B; ++b) {
+    FinalDesc& fd = fds[b];
+    std::memset(&fd, 0, sizeof fd);
+    fd.partials = bp->partials.as<double2>();
+    fd.occ_base = bp->d_occ_base.as<int64_t>() + occ_off[b];
+    fd.occ_nb = bp->d_occ_nb.as<int32_t>() + occ_off[b];
+    fd.param_ptr = plans[b]->d_param_ptr.as<int32_t>();
+    fd.occ = plans[b]->d_occ.as<int32_t>();
+    fd.grad_off = theta_off[b];
+    fd.p_begin = pb;
+    fd.n_theta = plans[b]->n_theta;
+    pb += plans[b]->n_theta;
+  }
+  bp->total_params = pb;
+  QSV_TRY(upload_vec(bp->d_final, fds, st));
+  bp->plans = plans;
+  bp->states.assign(states, states + B);
+  return QSV_OK;
+}
+
+template <typename R>
+static qsv_status batched_t(qsv_state* const* states, int B, const std::vector<Plan*>& plans,
+                            const std::vector<PauliPlan*>& hps, BatchPlan* bp,
+                            const double* d_theta_flat, const int64_t* theta_off,
+                            double* d_energy, double* d_grad_flat) {
+  qsv_state* s0 = states[0];
+  const hipStream_t st = s0->stream;
+  const double S0 = state_bytes_d(s0);
+  for (int b = 0; b < B; ++b)
+    HIP_TRY(launch_prep(plans[b]->d_gates.as<GateDesc>(), (int)plans[b]->gates.size(),
+                        d_theta_flat + theta_off[b], plans[b]->d_recs.as<GateRec>(), st));
+  for (auto& L : bp->fwd)
+    QSV_TRY(timed(s0, "k_pass_fwd", 2 * S0, [&] {
+      return launch_fused_forward<R>(L->d_items.as<PassItem>(), L->n_items, L->total, L->chunk,
+                                     bp->r, bp->w, L->general, L->grid, st);
+    }));
+  for (int b = 0; b < B; ++b) {
+    qsv_state* s = states[b];
+    QSV_TRY(s->epartials.ensure(sizeof(double2) * s->nb, st));
+    void* phi = s->d_work;
+    void* lam = static_cast<char*>(s->d_work) + qsv_state_bytes(s->n, s->dt);
+    QSV_TRY(pauli<R>(s, hps[b], phi, lam, s->epartials.as<double2>()));
+    HIP_TRY(launch_final_energy(s->epartials.as<double2>(), s->nb, d_energy + b, nullptr, st));
+  }
+  for (auto& L : bp->bwd)
+    QSV_TRY(timed(s0, "k_pass_bwd", 4 * S0, [&] {
+      return launch_fused_backward<R>(L->d_items.as<PassItem>(), L->n_items, L->total, L->chunk,
+                                      bp->r, bp->w, L->general, L->grid, st);
+    }));
+  HIP_TRY(launch_final_grad(bp->d_final.as<FinalDesc>(), B, bp->total_params, d_grad_flat, st));
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* const* states,
+                                                   const qsv_gate* const* gates,
+                                                   const int32_t* n_gates,
+                                                   const double* d_theta_flat,
+                                                   const int64_t* theta_off,
+                                                   const int32_t* n_theta,
+                                                   const qsv_pauli_sum* H, double* d_energy,
+                                                   double* d_grad_flat) {
+  if (n_batch < 1) return fail(QSV_ERR_INVALID_ARG, "n_batch = %d < 1", n_batch);
+  if (!states || !gates || !n_gates || !theta_off || !n_theta || !H)
+    return fail(QSV_ERR_INVALID_ARG, "NULL batch array");
+  if (!d_energy) return fail(QSV_ERR_INVALID_ARG, "d_energy is NULL");
+  qsv_state* s0 = states[0];
+  QSV_TRY(check_handle(s0));
+  bool any_theta = false;
+  for (int b = 0; b < n_batch; ++b) {
+    qsv_state* s = states[b];
+    if (!s) return fail(QSV_ERR_INVALID_ARG, "states[%d] is NULL", b);
+    if (s->device != s0->device || s->dt != s0->dt)
+      return fail(QSV_ERR_INVALID_ARG, "states[%d]: device or dtype differs from states[0]", b);
+    for (int c = 0; c < b; ++c)
+      if (states[c] == s) return fail(QSV_ERR_INVALID_ARG, "states[%d] repeats states[%d]", b, c);
+    QSV_TRY(qsv_validate_circuit(s->n, gates[b], n_gates[b], n_theta[b]));
+    QSV_TRY(qsv_validate_pauli_sum(s->n, &H[b]));
+    if (theta_off[b] < 0) return fail(QSV_ERR_INVALID_ARG, "theta_off[%d] < 0", b);
+    any_theta = any_theta || n_theta[b] > 0;
+  }
+  if (any_theta && (!d_theta_flat || !d_grad_flat))
+    return fail(QSV_ERR_INVALID_ARG, "d_theta_flat or d_grad_flat is NULL");
+  StreamOverride so(states, n_batch, s0->stream);
+  std::vector<Plan*> plans(n_batch);
+  std::vector<PauliPlan*> hps(n_batch);
+  for (int b = 0; b < n_batch; ++b) {
+    QSV_TRY(get_plan(states[b], gates[b], n_gates[b], n_theta[b], &plans[b]));
+    QSV_TRY(check_theta(plans[b], d_theta_flat));
+    QSV_TRY(get_pauli(states[b], &H[b], &hps[b]));
+  }
+  // a common tile geometry that fits every circuit; otherwise one circuit after the other
+  int r = 0, w = 0;
+  bool fused = fusion_geometry(s0, &r, &w);
+  for (int b = 0; b < n_batch && fused; ++b) {
+    int rb = 0, wb = 0;
+    fused = fusion_geometry(states[b], &rb, &wb) && r + w <= states[b]->n &&
+            !plans[b]->gates.empty();
+  }
+  if (!fused) {
+    for (int b = 0; b < n_batch; ++b) {
+      qsv_state* s = states[b];
+      double* g = d_grad_flat ? d_grad_flat + theta_off[b] : nullptr;
+      if (s->dt == QSV_C128)
+        QSV_TRY(adjoint_t<double>(s, plans[b], hps[b], d_theta_flat + theta_off[b], d_energy + b, g));
+      else
+        QSV_TRY(adjoint_t<float>(s, plans[b], hps[b], d_theta_flat + theta_off[b], d_energy + b, g));
+    }
+    return QSV_OK;
+  }
+  uint64_t key = fnv1a(&n_batch, sizeof n_batch);
+  key = fnv1a(states, sizeof(qsv_state*) * n_batch, key);
+  key = fnv1a(plans.data(), sizeof(Plan*) * n_batch, key);
+  key = fnv1a(theta_off, sizeof(int64_t) * n_batch, key);
+  key = fnv1a(&r, sizeof r, key);
+  key = fnv1a(&w, sizeof w, key);
+  BatchPlan* bp = nullptr;
+  auto it = s0->batches.find(key);
+  if (it != s0->batches.end() && it->second->plans == plans &&
+      std::equal(it->second->states.begin(), it->second->states.end(), states)) {
+    bp = it->second.get();
+  } else {
+    if (s0->batches.size() >= kMaxCachedBatches) {
+      HIP_TRY(hipStreamSynchronize(s0->stream));
+      s0->batches.clear();
+    }
+    auto nbp = std::make_unique<BatchPlan>();
+    QSV_TRY(build_batch(states, plans, n_batch, theta_off, r, w, nbp.get()));
+    bp = nbp.get();
+    s0->batches[key] = std::move(nbp);
+  }
+  return s0->dt == QSV_C128
+             ? batched_t<double>(states, n_batch, plans, hps, bp, d_theta_flat, theta_off,
+                                 d_energy, d_grad_flat)
+             : batched_t<float>(states, n_batch, plans, hps, bp, d_theta_flat, theta_off,
+                                d_energy, d_grad_flat);
 }
 
 // ------------------------------------------------------------------------------------------------

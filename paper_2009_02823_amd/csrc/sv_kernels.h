@@ -37,11 +37,26 @@ hipError_t launch_copy(void* dst, const void* src, int n, hipStream_t st);
 template <typename R>
 hipError_t launch_reset(void* psi, int n, hipStream_t st);
 
-// grad[p] = 2 Re sum over the occurrences o of p (occ[ptr[p] .. ptr[p+1])) of
-//           sum_b partials[o * nb + b]; prods[o] = that complex sum if prods != nullptr.
-hipError_t launch_final_grad(const double2* partials, int nb, const int32_t* d_param_ptr,
-                             const int32_t* d_occ, int n_theta, double* d_grad, double2* d_prods,
-                             hipStream_t st);
+// Where the partial sums of one circuit's products live: occurrence o (a reduction slot) has
+// occ_nb[o] consecutive partials starting at partials[occ_base[o]]; parameter p owns the
+// occurrences occ[param_ptr[p] .. param_ptr[p+1]) (in sweep order). Gradient entries are written
+// to grad[grad_off + p].
+struct FinalDesc {
+  const double2* partials;
+  const int64_t* occ_base;
+  const int32_t* occ_nb;
+  const int32_t* param_ptr;
+  const int32_t* occ;
+  int64_t grad_off;
+  int64_t p_begin;   // first block of this circuit in the launch
+  int32_t n_theta;
+  int32_t pad;
+};
+
+// One block per gradient entry over n_desc circuits (total_params = sum of n_theta):
+// grad[grad_off + p] = 2 Re sum over the occurrences of p of their partials, in a fixed order.
+hipError_t launch_final_grad(const FinalDesc* d_desc, int n_desc, int64_t total_params,
+                             double* d_grad, hipStream_t st);
 
 // *energy = Re sum_b partials[b]; energy_im (optional) = Im.
 hipError_t launch_final_energy(const double2* partials, int nb, double* d_energy,

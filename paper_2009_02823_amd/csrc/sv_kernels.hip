@@ -565,17 +565,23 @@ __device__ double2 block_sum_range(const double2* p, int count) {
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_final_grad(const double2* partials, int nb, const int32_t* ptr, const int32_t* occ, double* grad,
-             double2* prods) {
-  const int p = blockIdx.x;
-  double total = 0;
-  for (int k = ptr[p]; k < ptr[p + 1]; ++k) {
-    const int o = occ[k];
-    const double2 s = block_sum_range(partials + (size_t)o * nb, nb);
-    total += s.x;
-    if (prods && threadIdx.x == 0) prods[o] = s;
+k_final_grad(const FinalDesc* __restrict__ descs, int n_desc, double* grad) {
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = n_desc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].p_begin <= blk) lo = mid;
+    else hi = mid - 1;
   }
-  if (threadIdx.x == 0) grad[p] = 2.0 * total;
+  const FinalDesc d = descs[lo];
+  const int p = (int)(blk - d.p_begin);
+  double total = 0;
+  for (int k = d.param_ptr[p]; k < d.param_ptr[p + 1]; ++k) {
+    const int o = d.occ[k];
+    const double2 s = block_sum_range(d.partials + d.occ_base[o], d.occ_nb[o]);
+    total += s.x;
+  }
+  if (threadIdx.x == 0) grad[d.grad_off + p] = 2.0 * total;
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -587,12 +593,11 @@ k_final_energy(const double2* partials, int nb, double* energy, double* energy_i
   }
 }
 
-hipError_t launch_final_grad(const double2* partials, int nb, const int32_t* d_param_ptr,
-                             const int32_t* d_occ, int n_theta, double* d_grad, double2* d_prods,
-                             hipStream_t st) {
-  if (n_theta <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_final_grad, dim3(n_theta), dim3(kBlock), 0, st, partials, nb, d_param_ptr,
-                     d_occ, d_grad, d_prods);
+hipError_t launch_final_grad(const FinalDesc* d_desc, int n_desc, int64_t total_params,
+                             double* d_grad, hipStream_t st) {
+  if (total_params <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_final_grad, dim3((unsigned)total_params), dim3(kBlock), 0, st, d_desc,
+                     n_desc, d_grad);
   return hipGetLastError();
 }
 

@@ -77,6 +77,8 @@ def lib() -> ctypes.CDLL:
         "qsv_apply_circuit": ([P, P, i32, P, i32], i32),
         "qsv_expectation_pauli_sum": ([P, P, P], i32),
         "qsv_adjoint_gradient": ([P, P, i32, P, i32, P, P, P], i32),
+        "qsv_energy": ([P, P, i32, P, i32, P, P], i32),
+        "qsv_adjoint_gradient_batched": ([i32, P, P, P, P, P, P, P, P, P], i32),
         "qsv_param_shift_gradient": ([P, P, i32, P, i32, P, i32, i32, P], i32),
         "qsv_timing_enable": ([P, ctypes.c_char_p], i32),
         "qsv_timing_read": ([P, P, i32, ctypes.POINTER(i32)], i32),
@@ -243,6 +245,19 @@ class StateVector:
         del keep
         return e
 
+    def energy(self, gates, theta, codes, coeffs, out=None):
+        """<psi|H|psi> with psi = U(theta)|in> as a float64 device tensor of shape (1,)."""
+        torch = _torch()
+        g = as_gate_table(gates)
+        t = self._theta(theta)
+        s, keep = pauli_struct(codes, coeffs, self.n)
+        e = out if out is not None else torch.empty(1, dtype=torch.float64, device=self.device)
+        check(lib().qsv_energy(self._h, g.ctypes.data, g.shape[0],
+                               t.data_ptr() if t.numel() else None, t.numel(), ctypes.byref(s),
+                               e.data_ptr()))
+        del keep
+        return e
+
     def adjoint_gradient(self, gates, theta, codes, coeffs, energy=None, grad=None):
         """(E, grad) of Algorithm 1 as float64 device tensors (E has shape (1,))."""
         torch = _torch()
@@ -305,3 +320,69 @@ class StateVector:
                         "gbps": (float(st.bytes) / (st.total_ms * 1e-3) / 1e9)
                         if st.total_ms > 0 else 0.0})
         return out
+
+
+class Batch:
+    """Independent circuits (one handle each) whose energies and gradients are computed by one
+    qsv_adjoint_gradient_batched call from a flat parameter vector.
+
+    problems: objects with n_qubits, gates, codes, coeffs and n_params (workloads.Problem)."""
+
+    def __init__(self, problems, dtype: str = "c128", device=None):
+        torch = _torch()
+        self.problems = list(problems)
+        B = len(self.problems)
+        self.handles = [StateVector(p.n_qubits, dtype, device=device) for p in self.problems]
+        self.device = self.handles[0].device
+        self.gates = [as_gate_table(p.gates) for p in self.problems]
+        self._paulis = [pauli_struct(p.codes, p.coeffs, p.n_qubits) for p in self.problems]
+        self.n_theta = [int(p.n_params) for p in self.problems]
+        off = np.zeros(B + 1, dtype=np.int64)
+        off[1:] = np.cumsum(self.n_theta)
+        self.theta_off = off[:-1]
+        self.n_params = int(off[-1])
+        self._states = (ctypes.c_void_p * B)(*[h._h.value for h in self.handles])
+        self._gates = (ctypes.c_void_p * B)(*[g.ctypes.data for g in self.gates])
+        self._n_gates = (ctypes.c_int32 * B)(*[g.shape[0] for g in self.gates])
+        self._theta_off = (ctypes.c_int64 * B)(*self.theta_off.tolist())
+        self._n_theta = (ctypes.c_int32 * B)(*self.n_theta)
+        self._H = (PauliSum * B)(*[ps for ps, _ in self._paulis])
+        self._seg = None
+        del torch
+
+    def theta_flat(self):
+        """The problems' parameter vectors concatenated (float64, on the device)."""
+        torch = _torch()
+        return torch.as_tensor(np.concatenate([p.theta for p in self.problems]),
+                               dtype=torch.float64, device=self.device)
+
+    def segment_ids(self, device=None):
+        torch = _torch()
+        if self._seg is None:
+            self._seg = torch.as_tensor(np.repeat(np.arange(len(self.n_theta)), self.n_theta),
+                                        device=self.device)
+        return self._seg
+
+    def adjoint_gradient(self, theta_flat, energy=None, grad=None):
+        torch = _torch()
+        t = torch.as_tensor(theta_flat, dtype=torch.float64)
+        if t.device != self.device:
+            t = t.to(self.device)
+        t = t.contiguous()
+        self._keep = t
+        B = len(self.handles)
+        e = energy if energy is not None else torch.empty(B, dtype=torch.float64,
+                                                         device=self.device)
+        g = grad if grad is not None else torch.empty(self.n_params, dtype=torch.float64,
+                                                     device=self.device)
+        check(lib().qsv_adjoint_gradient_batched(B, self._states, self._gates, self._n_gates,
+                                                 t.data_ptr(), self._theta_off, self._n_theta,
+                                                 self._H, e.data_ptr(), g.data_ptr()))
+        return e, g
+
+    def sync(self):
+        self.handles[0].sync()
+
+    def close(self):
+        for h in self.handles:
+            h.close()

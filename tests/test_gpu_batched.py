@@ -1,0 +1,144 @@
+"""Batched reverse-mode gradients (one launch per pass level over all circuits) and the autograd
+layer, against the CPU oracle."""
+import numpy as np
+import pytest
+
+from paper_2009_02823_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_02823_amd import qsv
+    qsv.lib()
+    return qsv
+
+
+def small_batch(seed, B=7):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for b in range(B):
+        n = int(rng.integers(11, 15))
+        if b % 2:
+            L = int(rng.integers(2, 5))
+            gates = W.hea_circuit(n, L, cz_brickwork=bool(b % 3 == 0))
+            P = 2 * n * L
+            codes, coeffs = W.heisenberg_chain(n)
+        else:
+            gates, P = W.random_circuit(rng, n, 60, list(W.GATE_NAMES))
+            codes = W.random_pauli_strings(rng, n, 6)
+            coeffs = rng.standard_normal(6)
+        theta = W.uniform_angles(rng, P)
+        probs.append(W.Problem(f"b{b}", n, gates, theta, codes, coeffs))
+    return probs
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_vs_oracle(Q, orc, dtype):
+    probs = small_batch(3)
+    batch = Q.Batch(probs, dtype)
+    e, g = batch.adjoint_gradient(batch.theta_flat())
+    batch.sync()
+    e = e.cpu().numpy()
+    g = g.cpu().numpy()
+    for b, p in enumerate(probs):
+        e_ref, g_ref = orc.adjoint_gradient(p.n_qubits, p.gates, p.theta, p.codes, p.coeffs)
+        gb = g[batch.theta_off[b]: batch.theta_off[b] + p.n_params]
+        if dtype == "c128":
+            scale = max(1.0, np.abs(p.coeffs).sum())
+            assert abs(e[b] - e_ref.real) < 1e-10 * scale
+            assert np.max(np.abs(gb - g_ref)) < 1e-10 * scale
+        else:
+            assert abs(e[b] - e_ref.real) < 2e-4 * max(abs(e_ref), 1)
+            scale = max(np.max(np.abs(g_ref)), 1e-6 * np.abs(p.coeffs).sum())
+            assert np.max(np.abs(gb - g_ref)) < 2e-4 * scale
+    batch.close()
+
+
+def test_batch_equals_single_calls_and_repeats(Q):
+    import torch
+    probs = small_batch(5, B=5)
+    batch = Q.Batch(probs)
+    th = batch.theta_flat()
+    e1, g1 = batch.adjoint_gradient(th)
+    e2, g2 = batch.adjoint_gradient(th)
+    batch.sync()
+    assert torch.equal(e1, e2) and torch.equal(g1, g2)
+    for b, p in enumerate(probs):
+        with Q.StateVector(p.n_qubits) as sv:
+            e, g = sv.adjoint_gradient(p.gates, p.theta, p.codes, p.coeffs)
+            sv.sync()
+        o = batch.theta_off[b]
+        assert abs(float(e.cpu()[0]) - float(e1[b].cpu())) < 1e-13
+        assert float((g - g1[o:o + p.n_params]).abs().max()) < 1e-13
+    batch.close()
+
+
+def test_config4_batch_sampled_vs_oracle(Q, orc):
+    """The 512-circuit batch (12..18 qubits, 5..15 layers, Heisenberg chains): four circuits
+    checked entry by entry against the oracle."""
+    probs = W.config4()
+    batch = Q.Batch(probs)
+    e, g = batch.adjoint_gradient(batch.theta_flat())
+    batch.sync()
+    e = e.cpu().numpy()
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(0)
+    for b in rng.choice(len(probs), size=4, replace=False):
+        p = probs[b]
+        e_ref, g_ref = orc.adjoint_gradient(p.n_qubits, p.gates, p.theta, p.codes, p.coeffs)
+        gb = g[batch.theta_off[b]: batch.theta_off[b] + p.n_params]
+        assert abs(e[b] - e_ref.real) < 1e-10 * np.abs(p.coeffs).sum()
+        assert np.max(np.abs(gb - g_ref)) < 1e-10 * np.abs(p.coeffs).sum()
+    batch.close()
+
+
+def test_autograd_energy_and_gradcheck(Q, orc):
+    import torch
+    from paper_2009_02823_amd.autograd import AdjointEnergy
+    n = 6
+    rng = np.random.default_rng(2)
+    gates = W.hea_circuit(n, 2)
+    theta0 = W.uniform_angles(rng, 4 * n)
+    codes = W.random_pauli_strings(rng, n, 8)
+    coeffs = rng.standard_normal(8)
+    f = AdjointEnergy(n, gates, codes, coeffs, device="cuda:0")
+    theta = torch.tensor(theta0, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    e = f(theta)
+    e.backward()
+    e_ref, g_ref = orc.adjoint_gradient(n, gates, theta0, codes, coeffs)
+    assert abs(float(e.detach()) - e_ref.real) < 1e-12
+    assert float((theta.grad.cpu() - torch.tensor(g_ref)).abs().max()) < 1e-12
+    # no-grad path computes E alone
+    with torch.no_grad():
+        assert abs(float(f(theta.detach())) - e_ref.real) < 1e-12
+    # finite differences of the forward against backward
+    th = torch.tensor(theta0[: 4 * n], dtype=torch.float64, device="cuda:0", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda t: f(t), (th,), eps=1e-6, atol=1e-7, rtol=1e-5)
+    # chain rule through a scalar function of E
+    theta.grad = None
+    (3.0 * f(theta) ** 2).backward()
+    assert float((theta.grad.cpu() - torch.tensor(6.0 * e_ref.real * g_ref)).abs().max()) < 1e-11
+    f.sim.close()
+
+
+def test_autograd_batched(Q, orc):
+    import torch
+    from paper_2009_02823_amd.autograd import QsvEnergyBatch
+    probs = small_batch(8, B=4)
+    batch = Q.Batch(probs)
+    th = batch.theta_flat().requires_grad_(True)
+    e = QsvEnergyBatch.apply(th, batch)
+    w = torch.arange(1, len(probs) + 1, dtype=torch.float64, device=th.device)
+    (w * e).sum().backward()
+    grad = th.grad.cpu().numpy()
+    for b, p in enumerate(probs):
+        _, g_ref = orc.adjoint_gradient(p.n_qubits, p.gates, p.theta, p.codes, p.coeffs)
+        o = batch.theta_off[b]
+        assert np.max(np.abs(grad[o:o + p.n_params] - (b + 1) * g_ref)) < 1e-10 * (b + 1) * \
+            max(1.0, np.abs(p.coeffs).sum())
+    batch.close()

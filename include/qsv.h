@@ -201,6 +201,27 @@ qsv_status qsv_param_shift_gradient(qsv_state* s, const qsv_gate* gates, int32_t
                                     const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
                                     int32_t first, int32_t count, double* d_grad);
 
+/* ---- graphs and tuning ------------------------------------------------------------------- */
+
+/* on != 0: qsv_adjoint_gradient and qsv_adjoint_gradient_batched capture their launch sequence
+   into a hipGraph on the second call with the same circuit, Hamiltonian, geometry and device
+   pointers (the first call builds every plan eagerly) and replay it on every later such call.
+   Capture happens on a library-owned stream after the handle's stream has drained; replays are
+   ordered on the handle's stream. Graphs are bypassed while kernel timing is on. on = 0 frees
+   them. */
+qsv_status qsv_set_graphs(qsv_state* s, int32_t on);
+
+/* Times qsv_adjoint_gradient `repeats` times for every available execution mode (gate-granular
+   for states up to 20 qubits, every fused geometry that fits the state), keeps the fastest as
+   the handle's mode and caches the choice per (qubit count, storage type, gate kinds and qubits)
+   for the process; later calls with the same structure reuse it without timing. Writes the
+   chosen mode and geometry (and the measured ms per gradient, -1 when taken from the cache).
+   Uses the workspace; outputs may be NULL. */
+qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                        const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
+                        int32_t repeats, int32_t* out_mode, int32_t* out_reg_qubits,
+                        int32_t* out_threads_log2, double* out_ms);
+
 /* ---- measurement -------------------------------------------------------------------------- */
 
 /* Per-kernel-family statistics gathered from HIP events recorded on the handle's stream right

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -249,6 +250,29 @@ struct BatchPlan {
   int64_t total_params = 0;
 };
 
+// Captured launch sequences, replayed with hipGraphLaunch when the same call repeats.
+struct GraphCache {
+  bool on = false;
+  hipStream_t capture_stream = nullptr;  // library-owned, default priority
+  struct Entry {
+    int seen = 0;                // eager runs so far (capture on the second)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::unordered_map<uint64_t, Entry> entries;
+  void clear() {
+    for (auto& kv : entries) {
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+      if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    entries.clear();
+  }
+  ~GraphCache() {
+    clear();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
+};
+
 struct qsv_state {
   int n = 0;
   qsv_dtype dt = QSV_C128;
@@ -265,6 +289,7 @@ struct qsv_state {
   DevBuf epartials, theta_scratch, energies;
   Timer timer;
   std::unordered_map<uint64_t, std::unique_ptr<BatchPlan>> batches;
+  GraphCache graphs;
 };
 
 static constexpr size_t kMaxCachedPlans = 64;
@@ -488,6 +513,69 @@ extern "C" qsv_status qsv_reset(qsv_state* s) {
 extern "C" qsv_status qsv_sync(qsv_state* s) {
   QSV_TRY(check_handle(s));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// hipGraph capture and replay
+// ------------------------------------------------------------------------------------------------
+static constexpr size_t kMaxGraphs = 16;
+
+// Runs `enqueue` (which puts a call's whole launch sequence on s->stream). With graphs on and no
+// timing active, the first run with a given key is eager (it builds and allocates every plan), the
+// second is captured on the library's capture stream into a graph, and every later run with that
+// key replays the graph on s->stream. `key` must cover everything the launches bake in (plans,
+// device pointers, geometry). `extra` lists further handles whose stream must follow during the
+// capture (batches).
+template <typename F>
+static qsv_status run_graph(qsv_state* s, uint64_t key, F&& enqueue,
+                            qsv_state* const* extra = nullptr, int n_extra = 0) {
+  GraphCache& gc = s->graphs;
+  if (!gc.on || s->timer.on) return enqueue();
+  auto it = gc.entries.find(key);
+  if (it == gc.entries.end()) {
+    if (gc.entries.size() >= kMaxGraphs) {
+      HIP_TRY(hipStreamSynchronize(s->stream));
+      gc.clear();
+    }
+    it = gc.entries.emplace(key, GraphCache::Entry()).first;
+  }
+  GraphCache::Entry& e = it->second;
+  if (e.exec) {
+    HIP_TRY(hipGraphLaunch(e.exec, s->stream));
+    return QSV_OK;
+  }
+  if (e.seen++ == 0) return enqueue();
+  if (!gc.capture_stream) HIP_TRY(hipStreamCreateWithFlags(&gc.capture_stream, hipStreamNonBlocking));
+  // the capture stream must not run ahead of work already queued on the caller's stream
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const hipStream_t user = s->stream;
+  std::vector<std::pair<qsv_state*, hipStream_t>> saved;
+  for (int i = 0; i < n_extra; ++i) {
+    saved.push_back({extra[i], extra[i]->stream});
+    extra[i]->stream = gc.capture_stream;
+  }
+  s->stream = gc.capture_stream;
+  HIP_TRY(hipStreamBeginCapture(gc.capture_stream, hipStreamCaptureModeThreadLocal));
+  const qsv_status st = enqueue();
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(gc.capture_stream, &graph);
+  s->stream = user;
+  for (auto& kv : saved) kv.first->stream = kv.second;
+  if (st != QSV_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ec != hipSuccess) return fail(QSV_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(QSV_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  }
+  e.graph = graph;
+  e.exec = exec;
+  HIP_TRY(hipGraphLaunch(exec, s->stream));
   return QSV_OK;
 }
 
@@ -878,8 +966,16 @@ extern "C" qsv_status qsv_adjoint_gradient(qsv_state* s, const qsv_gate* gates, 
   QSV_TRY(check_theta(p, d_theta));
   PauliPlan* hp = nullptr;
   QSV_TRY(get_pauli(s, H, &hp));
-  return s->dt == QSV_C128 ? adjoint_t<double>(s, p, hp, d_theta, d_energy, d_grad)
-                           : adjoint_t<float>(s, p, hp, d_theta, d_energy, d_grad);
+  int r = 0, w = 0;
+  const bool fz = fusion_geometry(s, &r, &w);
+  const void* key_parts[5] = {p, hp, d_theta, d_energy, d_grad};
+  uint64_t key = fnv1a(key_parts, sizeof key_parts);
+  const int geo[3] = {fz ? 1 : 0, r, w};
+  key = fnv1a(geo, sizeof geo, key ^ 0xad301ull);
+  return run_graph(s, key, [&] {
+    return s->dt == QSV_C128 ? adjoint_t<double>(s, p, hp, d_theta, d_energy, d_grad)
+                             : adjoint_t<float>(s, p, hp, d_theta, d_energy, d_grad);
+  });
 }
 // ------------------------------------------------------------------------------------------------
 // batches of independent circuits
@@ -1119,11 +1215,18 @@ extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* c
     bp = nbp.get();
     s0->batches[key] = std::move(nbp);
   }
-  return s0->dt == QSV_C128
-             ? batched_t<double>(states, n_batch, plans, hps, bp, d_theta_flat, theta_off,
-                                 d_energy, d_grad_flat)
-             : batched_t<float>(states, n_batch, plans, hps, bp, d_theta_flat, theta_off,
-                                d_energy, d_grad_flat);
+  const void* key_parts[4] = {bp, d_theta_flat, d_energy, d_grad_flat};
+  const uint64_t gkey = fnv1a(key_parts, sizeof key_parts, key);
+  return run_graph(
+      s0, gkey,
+      [&] {
+        return s0->dt == QSV_C128
+                   ? batched_t<double>(states, n_batch, plans, hps, bp, d_theta_flat, theta_off,
+                                       d_energy, d_grad_flat)
+                   : batched_t<float>(states, n_batch, plans, hps, bp, d_theta_flat, theta_off,
+                                      d_energy, d_grad_flat);
+      },
+      states + 1, n_batch - 1);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1307,5 +1410,117 @@ extern "C" qsv_status qsv_schedule_describe(int32_t n, const qsv_gate* gates, in
   }
   for (size_t i = 0; i < sc.passes.size(); ++i) out->tile_mask[i] = sc.tile_mask[i];
   for (size_t i = 0; i < sc.phases.size(); ++i) out->reg_mask[i] = sc.reg_mask[i];
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_set_graphs(qsv_state* s, int32_t on) {
+  QSV_TRY(check_handle(s));
+  if (!on) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->graphs.clear();
+  }
+  s->graphs.on = on != 0;
+  return QSV_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// autotuner
+// ------------------------------------------------------------------------------------------------
+struct TuneKey {
+  uint64_t h;
+  bool operator==(const TuneKey& o) const { return h == o.h; }
+};
+struct TuneHash {
+  size_t operator()(const TuneKey& k) const { return (size_t)k.h; }
+};
+static std::unordered_map<TuneKey, std::array<int, 3>, TuneHash> g_tuned;  // mode, r, w
+
+// Circuit structure (kinds and qubits, not angles), qubit count and storage type.
+static uint64_t tune_key(const qsv_state* s, const Plan* p) {
+  uint64_t h = fnv1a(&s->n, sizeof s->n);
+  h = fnv1a(&s->dt, sizeof s->dt, h);
+  for (const GateDesc& g : p->gates) {
+    const int32_t v[3] = {g.kind, g.q0, g.q1};
+    h = fnv1a(v, sizeof v, h);
+  }
+  return h;
+}
+
+extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                                   const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
+                                   int32_t repeats, int32_t* out_mode, int32_t* out_reg_qubits,
+                                   int32_t* out_threads_log2, double* out_ms) {
+  QSV_TRY(check_handle(s));
+  QSV_TRY(qsv_validate_circuit(s->n, gates, n_gates, n_theta));
+  QSV_TRY(qsv_validate_pauli_sum(s->n, H));
+  if (repeats < 1) repeats = 1;
+  Plan* p = nullptr;
+  QSV_TRY(get_plan(s, gates, n_gates, n_theta, &p));
+  QSV_TRY(check_theta(p, d_theta));
+  const TuneKey key{tune_key(s, p)};
+  auto found = g_tuned.find(key);
+  std::array<int, 3> best = {0, 0, 0};
+  double best_ms = -1;
+  if (found != g_tuned.end()) {
+    best = found->second;
+  } else {
+    std::vector<std::array<int, 3>> cands;
+    if (s->n <= 20) cands.push_back({0, 0, 0});
+    const int ws[2] = {8, 6};
+    for (int w : ws)
+      for (int r = 2; r <= kMaxRegBits; ++r)
+        if (fused_config_supported(r, w, s->dt == QSV_C128) && r + w <= s->n)
+          cands.push_back({1, r, w});
+    DevBuf e, g;
+    QSV_TRY(e.ensure(sizeof(double), s->stream));
+    QSV_TRY(g.ensure(sizeof(double) * (n_theta ? n_theta : 1), s->stream));
+    const int saved[3] = {s->fusion_mode, s->fr, s->fw};
+    const bool graphs = s->graphs.on;
+    s->graphs.on = false;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    qsv_status st = QSV_OK;
+    for (const auto& c : cands) {
+      s->fusion_mode = c[0];
+      s->fr = c[1];
+      s->fw = c[2];
+      st = qsv_adjoint_gradient(s, gates, n_gates, d_theta, n_theta, H, e.as<double>(),
+                                g.as<double>());  // warm-up: builds the schedules
+      if (st != QSV_OK) break;
+      if (hipEventRecord(a, s->stream) != hipSuccess) { st = QSV_ERR_HIP; break; }
+      for (int i = 0; i < repeats && st == QSV_OK; ++i)
+        st = qsv_adjoint_gradient(s, gates, n_gates, d_theta, n_theta, H, e.as<double>(),
+                                  g.as<double>());
+      if (st != QSV_OK) break;
+      if (hipEventRecord(b, s->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+        st = QSV_ERR_HIP;
+        break;
+      }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, a, b);
+      ms /= repeats;
+      if (best_ms < 0 || ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    s->fusion_mode = saved[0];
+    s->fr = saved[1];
+    s->fw = saved[2];
+    s->graphs.on = graphs;
+    (void)hipStreamSynchronize(s->stream);  // the temporary outputs are freed on return
+    if (st != QSV_OK) return st;
+    g_tuned[key] = best;
+  }
+  s->fusion_mode = best[0] ? 1 : 0;
+  s->fr = best[1];
+  s->fw = best[2];
+  if (out_mode) *out_mode = best[0];
+  if (out_reg_qubits) *out_reg_qubits = best[1];
+  if (out_threads_log2) *out_threads_log2 = best[2];
+  if (out_ms) *out_ms = best_ms;
   return QSV_OK;
 }

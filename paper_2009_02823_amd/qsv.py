@@ -86,6 +86,9 @@ def lib() -> ctypes.CDLL:
         "qsv_get_fusion": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                            i32),
         "qsv_schedule_describe": ([i32, P, i32, i32, i32, i32, P], i32),
+        "qsv_set_graphs": ([P, i32], i32),
+        "qsv_autotune": ([P, P, i32, P, i32, P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                          ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], i32),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -300,6 +303,25 @@ class StateVector:
         check(lib().qsv_get_fusion(self._h, ctypes.byref(m), ctypes.byref(r), ctypes.byref(w)))
         return m.value, r.value, w.value
 
+    def set_graphs(self, on: bool = True):
+        """Capture repeated adjoint calls into hipGraphs and replay them (see qsv_set_graphs)."""
+        check(lib().qsv_set_graphs(self._h, 1 if on else 0))
+
+    def autotune(self, gates, theta, codes, coeffs, repeats: int = 2):
+        """Time every execution mode on this circuit and keep the fastest; returns
+        (mode, reg_qubits, threads_log2, ms per gradient or -1 if cached)."""
+        g = as_gate_table(gates)
+        t = self._theta(theta)
+        s, keep = pauli_struct(codes, coeffs, self.n)
+        m, r, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_double()
+        check(lib().qsv_autotune(self._h, g.ctypes.data, g.shape[0],
+                                 t.data_ptr() if t.numel() else None, t.numel(), ctypes.byref(s),
+                                 repeats, ctypes.byref(m), ctypes.byref(r), ctypes.byref(w),
+                                 ctypes.byref(ms)))
+        del keep
+        return m.value, r.value, w.value, ms.value
+
     def timing_enable(self, name_filter: str | None = ""):
         check(lib().qsv_timing_enable(self._h, None if name_filter is None
                                       else name_filter.encode()))
@@ -382,6 +404,9 @@ class Batch:
 
     def sync(self):
         self.handles[0].sync()
+
+    def set_graphs(self, on: bool = True):
+        self.handles[0].set_graphs(on)
 
     def close(self):
         for h in self.handles:

@@ -1,25 +1,28 @@
 """Benchmark: full reverse-mode gradients per second on one MI355X, against GPU parameter shift
 and the CPU oracle.
 
-Workload (one "step" = one energy + one full gradient, Algorithm 1): the hardware-efficient
-ansatz on 20 qubits with 20 layers of RY and RZ on every qubit plus a CNOT ladder (P = 800
-angles, seeded uniform in [0, 2pi)), under the open transverse-field Ising chain
+Default workload (one "step" = one energy + one full gradient, Algorithm 1): the
+hardware-efficient ansatz on 20 qubits with 20 layers of RY and RZ on every qubit plus a CNOT
+ladder (P = 800 angles, seeded uniform in [0, 2pi)), under the open transverse-field Ising chain
 sum Z_i Z_{i+1} + 0.7 sum X_i, complex128 storage. Inputs are synthetic and resident on the GPU
-before the timed region starts.
+before the timed region starts. --config 3 / 4 / 5 select the 26-qubit complex64 workload, the
+512-circuit batch and the 30-qubit workload.
 
 Prints one JSON line. Besides the headline value it carries:
   roofline      the dominant kernel family's algorithmic bytes per launch over its average
-                launch duration (HIP events around each of its launches in the timed region),
-                against the 8 TB/s HBM peak;
+                launch duration (HIP events around each of its launches, in a second timed region
+                of the same steps run without graph replay), against the 8 TB/s HBM peak;
+  eager         the step time without graph replay (the second timed region);
   c64           the same workload with complex64 storage and FP64 reductions;
   param_shift   the faithful O(P^2) gradient on the same GPU, timed on a sample of entries;
   cpu_baseline  the CPU oracle (Algorithm 1, complex128) on the host cores.
+--sweep-p prints the adjoint / parameter-shift times over the number of layers instead.
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import glob
+import hashlib
 import json
 import math
 import os
@@ -57,31 +60,97 @@ def traffic_for(family: str, workload: str, dtype: str):
     return rec.get("bytes_per_launch")
 
 
-def run_adjoint(qsv, torch, prob, dtype, steps, warmup, family_filter=None):
-    sv = qsv.StateVector(prob.n_qubits, dtype, device="cuda:0")
-    theta = torch.as_tensor(prob.theta, device="cuda:0")
-    e = torch.empty(1, dtype=torch.float64, device="cuda:0")
-    g = torch.empty(prob.n_params, dtype=torch.float64, device="cuda:0")
-    # warm-up with every kernel timed, to find the dominant kernel family
-    sv.timing_enable("")
-    for _ in range(max(warmup, 1)):
-        sv.adjoint_gradient(prob.gates, theta, prob.codes, prob.coeffs, e, g)
-    stats = sv.timing_read()
-    dominant = stats[0]["name"] if family_filter is None else family_filter
-    sv.timing_enable(dominant)
+class Single:
+    """One circuit on one handle."""
+
+    def __init__(self, qsv, torch, prob, dtype):
+        self.torch = torch
+        self.prob = prob
+        self.sv = qsv.StateVector(prob.n_qubits, dtype, device="cuda:0")
+        self.theta = torch.as_tensor(prob.theta, device="cuda:0")
+        self.e = torch.empty(1, dtype=torch.float64, device="cuda:0")
+        self.g = torch.empty(prob.n_params, dtype=torch.float64, device="cuda:0")
+        self.units = 1
+
+    def autotune(self):
+        return self.sv.autotune(self.prob.gates, self.theta, self.prob.codes, self.prob.coeffs)
+
+    def step(self):
+        self.sv.adjoint_gradient(self.prob.gates, self.theta, self.prob.codes, self.prob.coeffs,
+                                 self.e, self.g)
+
+    def handle(self):
+        return self.sv
+
+    def result(self):
+        return float(self.e.cpu()[0]), self.g.cpu().numpy()
+
+    def close(self):
+        self.sv.close()
+
+
+class Batched:
+    """The batch of independent circuits (one step = every circuit's energy and gradient)."""
+
+    def __init__(self, qsv, torch, probs, dtype):
+        self.torch = torch
+        self.batch = qsv.Batch(probs, dtype)
+        self.theta = self.batch.theta_flat()
+        self.e = torch.empty(len(probs), dtype=torch.float64, device=self.batch.device)
+        self.g = torch.empty(self.batch.n_params, dtype=torch.float64, device=self.batch.device)
+        self.units = len(probs)
+
+    def autotune(self):
+        return None
+
+    def step(self):
+        self.batch.adjoint_gradient(self.theta, self.e, self.g)
+
+    def handle(self):
+        return self.batch.handles[0]
+
+    def result(self):
+        return self.e.cpu().numpy(), self.g.cpu().numpy()
+
+    def close(self):
+        self.batch.close()
+
+
+def timed_steps(torch, runner, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        sv.adjoint_gradient(prob.gates, theta, prob.codes, prob.coeffs, e, g)
+        runner.step()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    dom = sv.timing_read()
-    sv.timing_enable(None)
-    out = {"seconds": dt, "ms_per_step": 1e3 * dt / steps, "value": steps / dt,
-           "energy": float(e.cpu()[0]), "grad": g.cpu().numpy(), "warmup_stats": stats,
-           "dominant": dom[0] if dom else None}
-    sv.close()
-    return out
+    return time.perf_counter() - t0
+
+
+def run(qsv, torch, runner, steps, warmup, graphs=True):
+    tuned = runner.autotune()
+    h = runner.handle()
+    # warm-up with every kernel timed, to find the dominant kernel family
+    h.timing_enable("")
+    for _ in range(max(warmup, 1)):
+        runner.step()
+    stats = h.timing_read()
+    h.timing_enable(None)
+    dominant = stats[0]["name"]
+    # timed region 1: the headline (graph replay of the whole step)
+    if graphs:
+        h.set_graphs(True)
+        for _ in range(2):
+            runner.step()      # eager run, then capture
+    dt = timed_steps(torch, runner, steps)
+    if graphs:
+        h.set_graphs(False)
+    # timed region 2: the same steps launched eagerly, the dominant family timed per launch
+    h.timing_enable(dominant)
+    dt_eager = timed_steps(torch, runner, steps)
+    dom = h.timing_read()
+    h.timing_enable(None)
+    return {"seconds": dt, "ms_per_step": 1e3 * dt / steps, "value": runner.units * steps / dt,
+            "ms_per_step_eager": 1e3 * dt_eager / steps, "dominant": dom[0] if dom else None,
+            "warmup_stats": stats, "tuned": tuned}
 
 
 def grad_error(prob, energy, grad, dtype):
@@ -91,18 +160,21 @@ def grad_error(prob, energy, grad, dtype):
     if ref is None:
         return None
     e_ref, g_ref = ref
+    scale = max(float(np.max(np.abs(g_ref))), 1e-6 * float(np.abs(prob.coeffs).sum()))
     d = {"max_abs_grad_err": float(np.max(np.abs(grad - g_ref))),
          "abs_energy_err": abs(energy - e_ref.real),
          "max_abs_grad_ref": float(np.max(np.abs(g_ref)))}
-    d["rel_grad_err"] = d["max_abs_grad_err"] / d["max_abs_grad_ref"]
-    d["tolerance"] = "1e-10 abs" if dtype == "c128" else "2e-4 * max|g_oracle|"
+    d["rel_grad_err"] = d["max_abs_grad_err"] / scale
+    d["tolerance"] = "1e-10 abs" if dtype == "c128" else "2e-4 * max(max|g_oracle|, 1e-6 sum|c|)"
     d["ok"] = (d["max_abs_grad_err"] <= 1e-10 if dtype == "c128" else d["rel_grad_err"] <= 2e-4)
     return d
 
 
-def run_param_shift(qsv, torch, prob, dtype, entries, adj_grad):
+def run_param_shift(qsv, torch, prob, dtype, entries, adj_grad=None, tune=None):
     import numpy as np
     sv = qsv.StateVector(prob.n_qubits, dtype, device="cuda:0")
+    if tune:
+        sv.set_fusion(*tune)
     theta = torch.as_tensor(prob.theta, device="cuda:0")
     g = torch.zeros(prob.n_params, dtype=torch.float64, device="cuda:0")
     sv.param_shift_gradient(prob.gates, theta, prob.codes, prob.coeffs, 0, 1, g)  # warm-up
@@ -114,12 +186,16 @@ def run_param_shift(qsv, torch, prob, dtype, entries, adj_grad):
     gs = g.cpu().numpy()[:entries]
     sv.close()
     per_grad = dt * prob.n_params / entries
-    return {"seconds_per_gradient": per_grad, "value": 1.0 / per_grad,
-            "sampled_entries": entries, "sample_seconds": dt,
-            "max_abs_diff_vs_adjoint": float(np.max(np.abs(gs - adj_grad[:entries])))}
+    out = {"seconds_per_gradient": per_grad, "value": 1.0 / per_grad,
+           "sampled_entries": entries, "sample_seconds": dt,
+           "method": "2 energy evaluations per entry (reset + forward + expectation), same "
+                     "kernels; sampled entries scaled by P (every entry costs the same)"}
+    if adj_grad is not None:
+        out["max_abs_diff_vs_adjoint"] = float(np.max(np.abs(gs - adj_grad[:entries])))
+    return out
 
 
-def run_cpu_baseline(prob, budget_s):
+def run_cpu_baseline(prob):
     from oracle import oracle as O
     O.lib()
     t0 = time.perf_counter()
@@ -128,6 +204,33 @@ def run_cpu_baseline(prob, budget_s):
     return {"value": 1.0 / dt, "unit": "gradients/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"one full energy + gradient of {prob.name} (Algorithm 1, complex128, "
                       f"{dt:.1f} s)", "seconds": dt}
+
+
+def sweep_p(qsv, torch, W, n, layers_list, ps_entries):
+    """Adjoint and parameter-shift times over the number of layers (P = 2 n L), with the
+    least-squares slopes of log t against log P."""
+    import numpy as np
+    rows = []
+    for L in layers_list:
+        prob = W.config2(n=n, layers=L)
+        runner = Single(qsv, torch, prob, "c128")
+        runner.autotune()
+        for _ in range(2):
+            runner.step()
+        steps = 5
+        t_adj = timed_steps(torch, runner, steps) / steps
+        runner.close()
+        ps = run_param_shift(qsv, torch, prob, "c128", min(ps_entries, prob.n_params))
+        rows.append({"layers": L, "P": prob.n_params, "adjoint_s": t_adj,
+                     "param_shift_s": ps["seconds_per_gradient"],
+                     "speedup": ps["seconds_per_gradient"] / t_adj})
+        log(f"L={L} P={prob.n_params}: adjoint {1e3 * t_adj:.3f} ms, parameter shift "
+            f"{ps['seconds_per_gradient']:.3f} s, speedup {rows[-1]['speedup']:.0f}")
+    lp = np.log([r["P"] for r in rows])
+    fit = {k: float(np.polyfit(lp, np.log([r[c] for r in rows]), 1)[0])
+           for k, c in (("adjoint", "adjoint_s"), ("param_shift", "param_shift_s"),
+                        ("speedup", "speedup"))}
+    return {"n_qubits": n, "rows": rows, "loglog_slopes": fit}
 
 
 def main():
@@ -139,9 +242,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-param-shift", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--config", type=int, default=2,
-                    help="2: 20 qubits (headline); 3: 26 qubits complex64; 5: 30 qubits")
+                    help="2: 20 qubits (headline); 3: 26 qubits complex64; 4: 512-circuit batch; "
+                         "5: 30 qubits")
+    ap.add_argument("--sweep-p", action="store_true",
+                    help="adjoint vs parameter shift over the number of layers at 20 qubits")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -153,52 +259,83 @@ def main():
     from paper_2009_02823_amd import qsv
     from paper_2009_02823_amd import workloads as W
 
-    prob = W.CONFIGS[args.config]()
-    main_dt = "c64" if args.config == 3 else "c128"
-    log(f"workload {prob.name}: n={prob.n_qubits} gates={prob.n_gates} P={prob.n_params}")
-    res = run_adjoint(qsv, torch, prob, main_dt, args.steps, args.warmup)
-    log(f"{main_dt} adjoint: {res['ms_per_step']:.3f} ms/gradient")
-    err = grad_error(prob, res["energy"], res["grad"], main_dt)
+    if args.sweep_p:
+        res = sweep_p(qsv, torch, W, 20, [1, 2, 4, 8, 16, 20], args.ps_entries)
+        print(json.dumps({"metric": "adjoint vs parameter-shift scaling in P", **res}))
+        return
+
+    if args.config == 4:
+        probs = W.config4()
+        main_dt = "c128"
+        runner = Batched(qsv, torch, probs, main_dt)
+        name = f"batch{len(probs)}_hea12-18_L5-15_heisenberg"
+        S = float(sum((16 << p.n_qubits) for p in probs))
+        log(f"workload {name}: {len(probs)} circuits, P total {runner.batch.n_params}")
+    else:
+        prob = W.CONFIGS[args.config]()
+        main_dt = "c64" if args.config == 3 else "c128"
+        runner = Single(qsv, torch, prob, main_dt)
+        name = prob.name
+        S = (16.0 if main_dt == "c128" else 8.0) * (1 << prob.n_qubits)
+        log(f"workload {name}: n={prob.n_qubits} gates={prob.n_gates} P={prob.n_params}")
+    res = run(qsv, torch, runner, args.steps, args.warmup, graphs=not args.no_graphs)
+    log(f"{main_dt} adjoint: {res['ms_per_step']:.3f} ms/step (eager "
+        f"{res['ms_per_step_eager']:.3f}), tuned {res['tuned']}")
+    e_res, g_res = runner.result()
+    if args.config == 4:
+        err = None
+    else:
+        err = grad_error(prob, e_res, g_res, main_dt)
+    runner.close()
     dom = res["dominant"]
-    S = (16.0 if main_dt == "c128" else 8.0) * (1 << prob.n_qubits)
     roof = None
     if dom:
         avg_s = dom["total_ms"] * 1e-3 / dom["launches"]
         achieved = dom["bytes_per_launch"] / avg_s / 1e9
-        traffic = traffic_for(dom["name"], prob.name, main_dt)
         roof = {"bound": "hbm", "kernel": dom["name"], "achieved": achieved,
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                "traffic": traffic, "bytes_per_launch": dom["bytes_per_launch"],
-                "avg_launch_us": 1e6 * avg_s, "launches_per_step": dom["launches"] / args.steps,
-                "share_of_step": dom["total_ms"] / (res["ms_per_step"] * args.steps),
+                "traffic": traffic_for(dom["name"], name, main_dt),
+                "bytes_per_launch": dom["bytes_per_launch"], "avg_launch_us": 1e6 * avg_s,
+                "launches_per_step": dom["launches"] / args.steps,
+                "share_of_eager_step": dom["total_ms"] / (res["ms_per_step_eager"] * args.steps),
                 "state_bytes": S}
     out = {
-        "metric": METRIC, "value": res["value"], "unit": "gradients/s", "n_gpus": 1,
+        "metric": METRIC, "value": res["value"],
+        "unit": "gradients/s" if args.config != 4 else "circuit gradients/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if main_dt == "c128" else "f32 (FP64 reductions)",
         "data": "synthetic",
-        "config": {"workload": prob.name, "n_qubits": prob.n_qubits,
-                   "n_params": prob.n_params, "n_gates": prob.n_gates,
-                   "pauli_terms": int(len(prob.coeffs)),
-                   "storage": "complex128" if main_dt == "c128" else "complex64",
-                   "parallelism": "single GPU"},
+        "config": {"workload": name, "storage": "complex128" if main_dt == "c128" else "complex64",
+                   "graph_replay": not args.no_graphs, "parallelism": "single GPU"},
         "grad_error": err,
         "roofline": roof,
+        "eager": {"ms_per_step": res["ms_per_step_eager"]},
+        "execution": {"tuned_mode_r_w": res["tuned"][:3] if res["tuned"] else None},
     }
-    if not args.no_c64 and main_dt == "c128" and prob.n_qubits <= 26:
-        r64 = run_adjoint(qsv, torch, prob, "c64", args.steps, args.warmup)
-        log(f"c64 adjoint: {r64['ms_per_step']:.3f} ms/gradient")
-        out["c64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
-                      "grad_error": grad_error(prob, r64["energy"], r64["grad"], "c64"),
-                      "dominant_kernel": r64["dominant"]}
-    if not args.no_param_shift:
-        ps = run_param_shift(qsv, torch, prob, main_dt, args.ps_entries, res["grad"])
+    if args.config != 4:
+        out["config"].update({"n_qubits": prob.n_qubits, "n_params": prob.n_params,
+                              "n_gates": prob.n_gates, "pauli_terms": int(len(prob.coeffs))})
+    tune = None
+    if res["tuned"]:
+        m, r, w, _ = res["tuned"]
+        tune = (m, r, w) if m else (0, 0, 0)
+    if not args.no_c64 and main_dt == "c128" and args.config != 4 and prob.n_qubits <= 26:
+        r64 = Single(qsv, torch, prob, "c64")
+        res64 = run(qsv, torch, r64, args.steps, args.warmup, graphs=not args.no_graphs)
+        e64, g64 = r64.result()
+        r64.close()
+        log(f"c64 adjoint: {res64['ms_per_step']:.3f} ms/gradient")
+        out["c64"] = {"value": res64["value"], "ms_per_step": res64["ms_per_step"],
+                      "grad_error": grad_error(prob, e64, g64, "c64"),
+                      "dominant_kernel": res64["dominant"]}
+    if not args.no_param_shift and args.config != 4:
+        ps = run_param_shift(qsv, torch, prob, main_dt, args.ps_entries, g_res, tune)
         ps["speedup_of_adjoint"] = ps["seconds_per_gradient"] / (res["ms_per_step"] * 1e-3)
         log(f"param shift: {ps['seconds_per_gradient']:.3f} s/gradient (sampled)")
         out["param_shift"] = ps
-    if not args.no_cpu_baseline and prob.n_qubits <= 22:
-        out["cpu_baseline"] = run_cpu_baseline(prob, args.cpu_budget)
+    if not args.no_cpu_baseline and args.config != 4 and prob.n_qubits <= 22:
+        out["cpu_baseline"] = run_cpu_baseline(prob)
         log(f"cpu oracle: {out['cpu_baseline']['seconds']:.2f} s/gradient")
     out["kernel_source_sha"] = kernel_source_sha()
     print(json.dumps(out, default=float))

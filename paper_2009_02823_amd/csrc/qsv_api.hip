@@ -236,6 +236,7 @@ struct Timer {
 // the reverse sweep) is one launch over the k-th pass of every circuit that has one.
 struct BatchLevel {
   DevBuf d_items;
+  double bytes = 0;  // algorithmic bytes of the launch (all its circuits)
   int n_items = 0;
   int64_t total = 0, chunk = 1;
   int grid = 1;
@@ -1018,6 +1019,7 @@ static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>
       PassItem it = fps[b]->items_fwd_phi[k];
       it.tile_begin = L->total;
       L->total += fps[b]->tiles;
+      L->bytes += 2.0 * (double)qsv_state_bytes(states[b]->n, states[b]->dt);
       L->general = L->general || fps[b]->fwd.sched.passes[k].general;
       items.push_back(it);
     }
@@ -1038,6 +1040,7 @@ static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>
       PassItem it = fps[b]->items_bwd[k];
       it.tile_begin = L->total;
       L->total += fps[b]->tiles;
+      L->bytes += 4.0 * (double)qsv_state_bytes(states[b]->n, states[b]->dt);
       L->general = L->general || fps[b]->bwd.sched.passes[k].general;
       level_items[k].push_back(it);
       level_owner[k].push_back(b);
@@ -1112,12 +1115,11 @@ static qsv_status batched_t(qsv_state* const* states, int B, const std::vector<P
                             double* d_energy, double* d_grad_flat) {
   qsv_state* s0 = states[0];
   const hipStream_t st = s0->stream;
-  const double S0 = state_bytes_d(s0);
   for (int b = 0; b < B; ++b)
     HIP_TRY(launch_prep(plans[b]->d_gates.as<GateDesc>(), (int)plans[b]->gates.size(),
                         d_theta_flat + theta_off[b], plans[b]->d_recs.as<GateRec>(), st));
   for (auto& L : bp->fwd)
-    QSV_TRY(timed(s0, "k_pass_fwd", 2 * S0, [&] {
+    QSV_TRY(timed(s0, "k_pass_fwd", L->bytes, [&] {
       return launch_fused_forward<R>(L->d_items.as<PassItem>(), L->n_items, L->total, L->chunk,
                                      bp->r, bp->w, L->general, L->grid, st);
     }));
@@ -1130,7 +1132,7 @@ static qsv_status batched_t(qsv_state* const* states, int B, const std::vector<P
     HIP_TRY(launch_final_energy(s->epartials.as<double2>(), s->nb, d_energy + b, nullptr, st));
   }
   for (auto& L : bp->bwd)
-    QSV_TRY(timed(s0, "k_pass_bwd", 4 * S0, [&] {
+    QSV_TRY(timed(s0, "k_pass_bwd", L->bytes, [&] {
       return launch_fused_backward<R>(L->d_items.as<PassItem>(), L->n_items, L->total, L->chunk,
                                       bp->r, bp->w, L->general, L->grid, st);
     }));

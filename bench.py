@@ -243,6 +243,9 @@ def main():
     ap.add_argument("--no-param-shift", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device twice (a plain copy kernel of known "
+                         "size, against which hardware byte counters are scaled)")
     ap.add_argument("--config", type=int, default=2,
                     help="2: 20 qubits (headline); 3: 26 qubits complex64; 4: 512-circuit batch; "
                          "5: 30 qubits")
@@ -258,6 +261,15 @@ def main():
     import torch
     from paper_2009_02823_amd import qsv
     from paper_2009_02823_amd import workloads as W
+
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy calibration: 2 x {args.copy_calibration} MiB")
 
     if args.sweep_p:
         res = sweep_p(qsv, torch, W, 20, [1, 2, 4, 8, 16, 20], args.ps_entries)

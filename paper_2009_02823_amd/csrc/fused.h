@@ -18,8 +18,9 @@ namespace qsv {
 
 constexpr int kMaxTileBits = 14;
 constexpr int kMaxRegBits = 5;
-constexpr int kMaxSlotsPerPass = 64;
-constexpr int kMaxOpsPerPass = 1024;
+constexpr int kMaxSlotsPerPass = 64;    // one wave lane per product slot
+constexpr int kMaxOpsPerPass = 256;     // ops of a pass are staged in LDS
+constexpr int kMaxPhasesPerPass = 64;
 
 enum FusedOpType : uint8_t {
   // lean op set (every bit location compile-time in registers or constant per thread)
@@ -62,6 +63,7 @@ struct PhaseDesc {
 };
 
 struct PassDesc {
+  uint64_t outer_mask;            // physical qubits outside the tile
   int32_t nt;                     // tile bits t
   int32_t n_outer;                // N - t
   int8_t tile[kMaxTileBits];      // physical qubit of tile bit s (ascending)
@@ -72,6 +74,7 @@ struct PassDesc {
   int32_t n_slots;                // products accumulated by this pass
   int32_t slot_begin;             // into the slot map (local slot -> global reduction slot)
   int32_t general;                // 1 if any op of the pass is of the general set
+  int32_t n_ops;                  // ops of the pass
 };
 
 // One unit of work of a fused launch: one pass of one circuit over all of its tiles. A launch
@@ -79,7 +82,7 @@ struct PassDesc {
 // concatenated tiles into contiguous chunks, one per workgroup. Items are built on the host and
 // hold device pointers only.
 struct PassItem {
-  const PassDesc* pass;
+  PassDesc pd;          // the pass (a copy: one load gives the kernel its whole description)
   const PhaseDesc* phases;
   const FusedOp* ops;
   const GateRec* recs;
@@ -93,6 +96,13 @@ struct PassItem {
   int32_t first_wg;     // first workgroup whose chunk reaches into the item
   int32_t nb;           // workgroups whose chunks reach into the item (partials stride)
   int32_t pad;
+};
+
+// An op as staged in LDS at the start of a pass: the op record and, for RX/RY/RZ, cos(t/2) and
+// sin(t/2) of its angle.
+struct alignas(16) OpStage {
+  FusedOp op;
+  double c, s;
 };
 
 // A schedule of one gate sequence (forward order, or the reverse sweep) as host tables ready to

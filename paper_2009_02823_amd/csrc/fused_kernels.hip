@@ -11,14 +11,22 @@
 // phi <- U^dag phi and lambda <- U^dag lambda. For the rotations R = exp(-i t G/2) the product
 // uses dR/dt = -(i/2) G R (paper App. A): Re <lambda|dR phi'> = (1/2) Im <lambda|G|phi> with phi
 // taken before un-applying R; other parameterised gates use their explicit derivative matrices.
-// Per-thread products (FP64) are summed over the wave with DPP row operations, accumulated per
-// wave in LDS over all tiles of the workgroup, and written as one partial per workgroup and
-// product slot; no atomics, fixed order.
+// Per-thread products (FP64) are summed over the wave with DPP row operations and accumulated in a
+// register of the wave, lane j holding product slot j, over all tiles of the workgroup; the waves'
+// sums are combined through LDS and written as one partial per workgroup and product slot; no
+// atomics, fixed order.
+//
+// At the start of a pass every workgroup copies the pass's op records, with the cos/sin of the
+// rotation angles, and its phase descriptors into LDS in one round of loads issued behind the
+// first tile's loads. Ops are then read from LDS one ahead of their execution, so no op waits for a
+// dependent global load.
 //
 // Two instances per geometry: the lean one handles RX, RY, RZ, CNOT, CZ and fixed one-qubit
 // gates, with every control/diagonal bit resolved either at compile time (register bit) or once
 // per thread (thread bit); the general one adds parameterised dense/diagonal gates with explicit
 // derivatives, controlled rotations and two-qubit rotations.
+#include <cstddef>
+
 #include "fused.h"
 #include "qsv_device.h"
 
@@ -37,6 +45,13 @@ template <>
 struct Swz<float> {  // 8-byte elements, 32 per bank row
   static __device__ __forceinline__ uint32_t f(uint32_t x) { return x ^ (((x >> 5) ^ (x >> 10)) & 31u); }
 };
+
+// Workgroup barrier for LDS traffic: waits for this wave's LDS (and scalar) operations only, so
+// global loads already issued stay in flight across it. The memory clobber keeps the compiler
+// from moving memory accesses across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 // ---------------------------------------------------------------------------------------------
 // Layouts
@@ -91,14 +106,14 @@ __device__ __forceinline__ void relayout(cx<R>* a, const Layout<RB>& from, const
     v.y = a[ri].i;
     lds[Swz<R>::f(from.tdep | reg_deposit<RB>(from, ri))] = v;
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
     const typename Vec2<R>::T v = lds[Swz<R>::f(to.tdep | reg_deposit<RB>(to, ri))];
     a[ri].r = v.x;
     a[ri].i = v.y;
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Both states of the reverse sweep through one pair of barriers (two LDS halves).
@@ -118,7 +133,7 @@ __device__ __forceinline__ void relayout2(cx<R>* a, cx<R>* b, const Layout<RB>& 
     lds[x] = v;
     lds[half + x] = w;
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
     const uint32_t x = Swz<R>::f(to.tdep | reg_deposit<RB>(to, ri));
@@ -128,7 +143,7 @@ __device__ __forceinline__ void relayout2(cx<R>* a, cx<R>* b, const Layout<RB>& 
     b[ri].r = w.x;
     b[ri].i = w.y;
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 template <int RB>
@@ -142,16 +157,6 @@ __device__ __forceinline__ bool same_layout(const Layout<RB>& a, const int8_t* r
 // ---------------------------------------------------------------------------------------------
 // Lean ops. ADJ selects U^dag (reverse sweep) instead of U.
 // ---------------------------------------------------------------------------------------------
-// cos(t/2), sin(t/2) of a rotation from its record: RY m[2] = s, RX m[1] = -i s, RZ m[0] = c - i s
-template <typename R>
-__device__ __forceinline__ void rot_cs(const GateRec* rec, int type, R& c, R& s) {
-  const double2 m0 = rec->m[0];
-  c = (R)m0.x;
-  if (type == FOP_RY) s = (R)rec->m[2].x;
-  else if (type == FOP_RX) s = (R)(-rec->m[1].y);
-  else s = (R)(-m0.y);
-}
-
 template <typename R, int NA, int K, bool ADJ>
 __device__ __forceinline__ void ry_k(cx<R>* a, R c, R s) {
   const R sp = ADJ ? -s : s;  // U = [[c, -s], [s, c]]
@@ -307,30 +312,22 @@ __device__ __forceinline__ void neg_rr_at(int ka, int kb, cx<R>* a, bool on) {
 __device__ __forceinline__ bool thread_bit(uint32_t tdep, int s) { return (tdep >> s) & 1u; }
 
 // Applies a lean op (or its inverse when ADJ) to one state's registers.
+// Rotations take cos(t/2), sin(t/2) from the staged op; fixed gates read their matrix record.
 template <typename R, int RB, bool ADJ>
-__device__ __forceinline__ void apply_lean(const FusedOp& op, const GateRec* rec, cx<R>* a,
-                                           uint32_t tdep) {
+__device__ __forceinline__ void apply_lean(const FusedOp& op, R c, R s, const GateRec* rec,
+                                           cx<R>* a, uint32_t tdep) {
   constexpr int NA = 1 << RB;
   switch (op.type) {
-    case FOP_RY: {
-      R c, s;
-      rot_cs<R>(rec, FOP_RY, c, s);
+    case FOP_RY:
       ry_at<R, RB, ADJ>(op.k0, a, c, s);
       break;
-    }
-    case FOP_RX: {
-      R c, s;
-      rot_cs<R>(rec, FOP_RX, c, s);
+    case FOP_RX:
       rx_at<R, RB, ADJ>(op.k0, a, c, s);
       break;
-    }
-    case FOP_RZ: {
-      R c, s;
-      rot_cs<R>(rec, FOP_RZ, c, s);
+    case FOP_RZ:
       if (op.flags & FOPF_S0_REG) rz_at<R, RB, ADJ>(op.ks0, a, c, s);
       else rz_thr<R, NA, ADJ>(a, c, s, thread_bit(tdep, op.s0));
       break;
-    }
     case FOP_CNOT:  // self-inverse
       if (op.flags & FOPF_S0_REG) cnot_rr_at<R, RB>(op.ks0, op.k0, a);
       else cnot_tr_at<R, RB, ADJ>(op.k0, a, thread_bit(tdep, op.s0));
@@ -633,13 +630,6 @@ struct Geometry {
   static constexpr int NW = NT / 64;
 };
 
-__device__ __forceinline__ uint64_t outer_base(const PassDesc* __restrict__ pdp, int n_outer,
-                                               uint64_t tile) {
-  uint64_t b = 0;
-  for (int j = 0; j < n_outer; ++j) b |= ((tile >> j) & 1ull) << pdp->outer[j];
-  return b;
-}
-
 template <int RB, int W>
 __device__ __forceinline__ void direct_offsets(const PassDesc& pd, uint32_t tid, uint64_t& gthr,
                                                uint64_t* groff) {
@@ -674,12 +664,100 @@ __device__ __forceinline__ int find_item(const PassItem* __restrict__ items, int
   return lo;
 }
 
+// The low bits of x deposited into the set bits of mask, lowest first (the amplitude offset of
+// tile x of a pass whose outer qubits are mask).
+__device__ __forceinline__ uint64_t deposit_bits(uint64_t x, uint64_t mask) {
+  uint64_t r = 0;
+  for (uint64_t m = mask; m && x; m &= m - 1, x >>= 1)
+    if (x & 1) r |= m & (~m + 1);
+  return r;
+}
+
+// The next subset of mask after b in increasing order (the offset of the next tile).
+__device__ __forceinline__ uint64_t next_in_mask(uint64_t b, uint64_t mask) {
+  return (b - mask) & mask;
+}
+
+// Copies the pass's op records (with the cos/sin of the rotation angles) and phase descriptors to
+// LDS; every thread loads a share, so the whole op stream arrives in one round of loads.
+__device__ __forceinline__ void stage_pass(const PassItem& I, OpStage* sops, PhaseDesc* sph,
+                                           int tid, int nt) {
+  const int n_ops = I.pd.n_ops, n_ph = I.pd.phase_end - I.pd.phase_begin;
+  for (int i = tid; i < n_ops; i += nt) {
+    // the 16-byte op record moves as one word quadruple (type in the low byte of the first)
+    const uint4 raw = reinterpret_cast<const uint4*>(I.ops + I.pd.op_begin)[i];
+    const int type = (int)(raw.x & 0xffu);
+    double c = 0.0, s = 0.0;
+    if (type <= FOP_RZ) {  // RY m[2] = s, RX m[1] = -i s, RZ m[0] = c - i s
+      const GateRec* rec = I.recs + (int32_t)raw.w;
+      const double2 m0 = rec->m[0];
+      c = m0.x;
+      s = type == FOP_RY ? rec->m[2].x : type == FOP_RX ? -rec->m[1].y : -m0.y;
+    }
+    *reinterpret_cast<uint4*>(&sops[i].op) = raw;
+    *reinterpret_cast<double2*>(&sops[i].c) = make_double2(c, s);
+  }
+  for (int i = tid; i < n_ph; i += nt) sph[i] = I.phases[I.pd.phase_begin + i];
+}
+
+static_assert(sizeof(FusedOp) == 16 && offsetof(FusedOp, s0) == 3 && offsetof(FusedOp, flags) == 7 &&
+                  offsetof(FusedOp, ks1) == 9 && offsetof(FusedOp, gate) == 12,
+              "FusedOp is read from LDS as four words");
+
+// Raw words of staged op k (issued early; made uniform when the op is executed).
+__device__ __forceinline__ uint4 staged_words(const OpStage* sops, int k) {
+  return *reinterpret_cast<const uint4*>(&sops[k].op);
+}
+__device__ __forceinline__ double2 staged_cs(const OpStage* sops, int k) {
+  return *reinterpret_cast<const double2*>(&sops[k].c);
+}
+__device__ __forceinline__ FusedOp uniform_op(uint4 raw) {
+  const uint32_t w0 = __builtin_amdgcn_readfirstlane(raw.x);
+  const uint32_t w1 = __builtin_amdgcn_readfirstlane(raw.y);
+  const uint32_t w2 = __builtin_amdgcn_readfirstlane(raw.z);
+  FusedOp op;
+  op.type = (uint8_t)w0;
+  op.k0 = (uint8_t)(w0 >> 8);
+  op.k1 = (uint8_t)(w0 >> 16);
+  op.s0 = (uint8_t)(w0 >> 24);
+  op.s1 = (uint8_t)w1;
+  op.np = (uint8_t)(w1 >> 8);
+  op.lslot = (uint8_t)(w1 >> 16);
+  op.flags = (uint8_t)(w1 >> 24);
+  op.ks0 = (uint8_t)w2;
+  op.ks1 = (uint8_t)(w2 >> 8);
+  op.pad[0] = op.pad[1] = 0;
+  op.gate = (int32_t)__builtin_amdgcn_readfirstlane(raw.w);
+  return op;
+}
+
+// Phase ph of the staged pass: its op end and register bits, as uniform values.
+template <int RB>
+__device__ __forceinline__ int uniform_phase(const PhaseDesc* sph, int ph, int8_t* rb) {
+  static_assert(sizeof(PhaseDesc) == 12, "PhaseDesc is read from LDS as three words");
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(sph + ph);
+  const uint32_t w0 = __builtin_amdgcn_readfirstlane(p[0]);
+  const uint32_t w1 = __builtin_amdgcn_readfirstlane(p[1]);
+  const uint32_t w2 = __builtin_amdgcn_readfirstlane(p[2]);
+#pragma unroll
+  for (int k = 0; k < RB; ++k) rb[k] = (int8_t)(((k < 4 ? w1 >> (8 * k) : w2 >> (8 * (k - 4)))) & 0xffu);
+  return (int)w0;
+}
+
+__device__ __forceinline__ double lane63_value(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 template <typename R, int RB, int W, bool GEN>
 __global__ void __launch_bounds__(1 << W)
 k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64_t chunk) {
   using G = Geometry<RB, W>;
   using V = typename Vec2<R>::T;
   __shared__ V lds[1 << G::T];
+  __shared__ OpStage sops[kMaxOpsPerPass + 1];
+  __shared__ PhaseDesc sph[kMaxPhasesPerPass];
   const uint32_t tid = threadIdx.x;
   int64_t g0 = (int64_t)blockIdx.x * chunk;
   const int64_t g1 = g0 + chunk < total ? g0 + chunk : total;
@@ -689,39 +767,50 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
   direct_layout<RB, W>(D, tid);
   while (g0 < g1) {
     const PassItem I = items[it];
-    const PassDesc pd = *I.pass;
     const int64_t stop = I.tile_begin + (1ll << I.n_outer) < g1 ? I.tile_begin + (1ll << I.n_outer) : g1;
     const V* src = static_cast<const V*>(I.src);
     V* dst = static_cast<V*>(I.dst);
+    const int n_ph = I.pd.phase_end - I.pd.phase_begin;
     uint64_t gthr, groff[G::NA];
-    direct_offsets<RB, W>(pd, tid, gthr, groff);
-    for (int64_t g = g0; g < stop; ++g) {
-      const uint64_t ob = outer_base(I.pass, pd.n_outer, (uint64_t)(g - I.tile_begin)) | gthr;
+    direct_offsets<RB, W>(I.pd, tid, gthr, groff);
+    uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
+    for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
+      const uint64_t ob = obase | gthr;
       cx<R> a[G::NA];
 #pragma unroll
       for (int ri = 0; ri < G::NA; ++ri) a[ri] = load<R>(src, ob | groff[ri]);
+      if (g == g0) {  // staged while the first tile's loads are in flight
+        stage_pass(I, sops, sph, (int)tid, G::NT);
+        lds_barrier();
+      }
       Layout<RB> cur = D;
-      int op_at = pd.op_begin;
-      for (int ph = pd.phase_begin; ph < pd.phase_end; ++ph) {
-        const PhaseDesc P = I.phases[ph];
-        if (!same_layout<RB>(cur, P.regbit)) {
+      int k = 0;
+      uint4 nraw = staged_words(sops, 0);
+      double2 ncs = staged_cs(sops, 0);
+      for (int ph = 0; ph < n_ph; ++ph) {
+        int8_t rb[RB];
+        const int op_end = uniform_phase<RB>(sph, ph, rb);
+        if (!same_layout<RB>(cur, rb)) {
           Layout<RB> nxt;
-          make_layout<RB, G::T>(nxt, P.regbit, tid);
+          make_layout<RB, G::T>(nxt, rb, tid);
           relayout<R, RB>(a, cur, nxt, lds);
           cur = nxt;
         }
-        const int op_end = pd.op_begin + P.op_end;
-        for (; op_at < op_end; ++op_at) {
-          const FusedOp op = I.ops[op_at];
+        for (; k < op_end; ++k) {
+          const FusedOp op = uniform_op(nraw);
+          const double2 cs = ncs;
+          nraw = staged_words(sops, k + 1);
+          ncs = staged_cs(sops, k + 1);
           const GateRec* rec = I.recs + op.gate;
           if (GEN && op.type >= FOP_FIRST_GENERAL) apply_general<R, RB, false>(op, rec, a, cur);
-          else apply_lean<R, RB, false>(op, rec, a, cur.tdep);
+          else apply_lean<R, RB, false>(op, (R)cs.x, (R)cs.y, rec, a, cur.tdep);
         }
       }
       if (!same_layout<RB>(cur, D.rb)) relayout<R, RB>(a, cur, D, lds);
 #pragma unroll
       for (int ri = 0; ri < G::NA; ++ri) store<R>(dst, ob | groff[ri], a[ri]);
     }
+    lds_barrier();  // the staged tables are rewritten for the next item
     g0 = stop;
     ++it;
   }
@@ -733,6 +822,8 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
   using G = Geometry<RB, W>;
   using V = typename Vec2<R>::T;
   __shared__ V lds[2 << G::T];
+  __shared__ OpStage sops[kMaxOpsPerPass + 1];
+  __shared__ PhaseDesc sph[kMaxPhasesPerPass];
   __shared__ double wacc[kMaxSlotsPerPass][G::NW];
   const uint32_t tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -744,35 +835,45 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
   direct_layout<RB, W>(D, tid);
   while (g0 < g1) {
     const PassItem I = items[it];
-    const PassDesc pd = *I.pass;
     const int64_t stop = I.tile_begin + (1ll << I.n_outer) < g1 ? I.tile_begin + (1ll << I.n_outer) : g1;
     V* phi = static_cast<V*>(I.dst);
     V* lam = static_cast<V*>(I.lam);
-    for (int i = tid; i < kMaxSlotsPerPass * G::NW; i += G::NT) (&wacc[0][0])[i] = 0.0;
-    __syncthreads();
+    const int n_ph = I.pd.phase_end - I.pd.phase_begin;
     uint64_t gthr, groff[G::NA];
-    direct_offsets<RB, W>(pd, tid, gthr, groff);
-    for (int64_t g = g0; g < stop; ++g) {
-      const uint64_t ob = outer_base(I.pass, pd.n_outer, (uint64_t)(g - I.tile_begin)) | gthr;
+    direct_offsets<RB, W>(I.pd, tid, gthr, groff);
+    uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
+    // lane j of every wave accumulates product slot j over the wave's share of the tiles
+    double acc = 0.0;
+    for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
+      const uint64_t ob = obase | gthr;
       cx<R> f[G::NA], l[G::NA];
 #pragma unroll
       for (int ri = 0; ri < G::NA; ++ri) {
         f[ri] = load<R>(phi, ob | groff[ri]);
         l[ri] = load<R>(lam, ob | groff[ri]);
       }
+      if (g == g0) {  // staged while the first tile's loads are in flight
+        stage_pass(I, sops, sph, (int)tid, G::NT);
+        lds_barrier();
+      }
       Layout<RB> cur = D;
-      int op_at = pd.op_begin;
-      for (int ph = pd.phase_begin; ph < pd.phase_end; ++ph) {
-        const PhaseDesc P = I.phases[ph];
-        if (!same_layout<RB>(cur, P.regbit)) {
+      int k = 0;
+      uint4 nraw = staged_words(sops, 0);
+      double2 ncs = staged_cs(sops, 0);
+      for (int ph = 0; ph < n_ph; ++ph) {
+        int8_t rb[RB];
+        const int op_end = uniform_phase<RB>(sph, ph, rb);
+        if (!same_layout<RB>(cur, rb)) {
           Layout<RB> nxt;
-          make_layout<RB, G::T>(nxt, P.regbit, tid);
+          make_layout<RB, G::T>(nxt, rb, tid);
           relayout2<R, RB>(f, l, cur, nxt, lds, 1 << G::T);
           cur = nxt;
         }
-        const int op_end = pd.op_begin + P.op_end;
-        for (; op_at < op_end; ++op_at) {
-          const FusedOp op = I.ops[op_at];
+        for (; k < op_end; ++k) {
+          const FusedOp op = uniform_op(nraw);
+          const double2 cs = ncs;
+          nraw = staged_words(sops, k + 1);
+          ncs = staged_cs(sops, k + 1);
           const GateRec* rec = I.recs + op.gate;
           double prod[3] = {0, 0, 0};
           if (GEN && op.type >= FOP_FIRST_GENERAL) {
@@ -781,14 +882,14 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
             apply_general<R, RB, true>(op, rec, l, cur);
           } else {
             if (op.np) prod[0] = lean_product<R, RB>(op, f, l, cur.tdep);
-            apply_lean<R, RB, true>(op, rec, f, cur.tdep);
-            apply_lean<R, RB, true>(op, rec, l, cur.tdep);
+            apply_lean<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, f, cur.tdep);
+            apply_lean<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, l, cur.tdep);
           }
 #pragma unroll
           for (int j = 0; j < 3; ++j) {
             if (j >= op.np) break;
-            const double s = wave_total_lane63(prod[j]);
-            if (lane == 63) wacc[op.lslot + j][wave] += s;
+            const double s = lane63_value(wave_total_lane63(prod[j]));
+            acc += lane == op.lslot + j ? s : 0.0;
           }
         }
       }
@@ -799,14 +900,16 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
         store<R>(lam, ob | groff[ri], l[ri]);
       }
     }
-    __syncthreads();
+    wacc[lane][wave] = acc;
+    lds_barrier();
     const int col = (int)blockIdx.x - I.first_wg;
-    for (int j = tid; j < pd.n_slots; j += G::NT) {
+    for (int j = tid; j < I.pd.n_slots; j += G::NT) {
       double s = 0;
+#pragma unroll
       for (int w = 0; w < G::NW; ++w) s += wacc[j][w];
       I.partials[(size_t)j * I.nb + col] = make_double2(s, 0.0);
     }
-    __syncthreads();
+    lds_barrier();  // wacc and the staged tables are rewritten for the next item
     g0 = stop;
     ++it;
   }

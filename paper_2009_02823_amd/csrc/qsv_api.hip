@@ -670,7 +670,7 @@ static PassItem make_item(const FusedSchedule& fs, size_t i, const Plan* p, cons
                           void* dst, void* lam, int n_outer) {
   PassItem it;
   std::memset(&it, 0, sizeof it);
-  it.pass = fs.d_passes.as<PassDesc>() + i;
+  it.pd = fs.sched.passes[i];
   it.phases = fs.d_phases.as<PhaseDesc>();
   it.ops = fs.d_ops.as<FusedOp>();
   it.recs = p->d_recs.as<GateRec>();

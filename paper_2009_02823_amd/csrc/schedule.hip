@@ -135,6 +135,7 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
         pd.tile[s++] = (int8_t)q;
       } else {
         pd.outer[o++] = (int8_t)q;
+        pd.outer_mask |= 1ull << q;
       }
     }
     pd.n_outer = o;
@@ -147,8 +148,11 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
     // ---- register phases inside the pass
     const uint32_t dmask = ((1u << t) - 1) & ~((1u << w) - 1);  // layout D register bits
     std::vector<int> prem(taken);
+    std::vector<int> placed;
     int lslot = 0;
-    while (!prem.empty()) {
+    // phases up to the staging limit; gates left over return to the remaining sequence (the
+    // phase scan is itself a blocked scan, so they only follow gates they commute with)
+    while (!prem.empty() && (int)out.phases.size() - pd.phase_begin < kMaxPhasesPerPass) {
       uint32_t R = 0;
       uint64_t blocked = 0;
       std::vector<int> ph;
@@ -260,6 +264,7 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
           lslot += np;
         }
         out.ops.push_back(op);
+        placed.push_back(k);
         out.order.push_back(k);
         out.pass_of.push_back(pass_id);
         out.phase_of.push_back(phase_id);
@@ -270,11 +275,12 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
     }
     pd.phase_end = (int32_t)out.phases.size();
     pd.n_slots = lslot;
+    pd.n_ops = (int32_t)out.ops.size() - pd.op_begin;
     out.passes.push_back(pd);
 
-    // drop the taken gates from the remaining sequence
+    // drop the executed gates from the remaining sequence
     std::vector<char> done(gates.size(), 0);
-    for (int k : taken) done[k] = 1;
+    for (int k : placed) done[k] = 1;
     std::vector<int> nrem;
     nrem.reserve(rem.size());
     for (int k : rem)

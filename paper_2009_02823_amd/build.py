@@ -28,6 +28,9 @@ CFLAGS = [
     # per-register-position branches turns static array indices into address selects, which
     # forces the thread's amplitude arrays into scratch memory
     "-mllvm", "-simplifycfg-sink-common=false", "-mllvm", "-simplifycfg-hoist-common=false",
+    # branches on wave-uniform values (the op dispatch of the fused passes) stay plain scalar
+    # branches; structurizing them inserts flow blocks whose joins copy the amplitude registers
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     "-I", CSRC, "-I", INCLUDE,
 ]
 

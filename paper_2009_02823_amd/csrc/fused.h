@@ -52,9 +52,20 @@ struct FusedOp {
   uint8_t lslot;    // local slot of the first product
   uint8_t flags;    // FOPF_*
   uint8_t ks0, ks1; // register positions of s0 / s1 when they are register bits
-  uint8_t pad[2];
+  uint16_t opc;     // lean op code QSV_OPC(type, variant), see below
   int32_t gate;     // gate record index
 };
+
+// Op codes of the lean ops: type * 64 + variant, the variant naming the register positions:
+//   RY, RX, DENSE1: k0;  RZ, DIAG1: ks0, or QSV_V_THREAD for a thread bit;
+//   CNOT: 8 * ks0 + k0 (register control), QSV_V_CTL_THREAD + k0 (thread control);
+//   CZ: 8 * ks0 + ks1 (both register bits), QSV_V_REG0 + ks0 (only s0 in registers),
+//       QSV_V_REG1 + ks1 (only s1 in registers), QSV_V_THREAD (both thread bits).
+#define QSV_OPC(T, V) ((T) * 64 + (V))
+#define QSV_V_REG0 40
+#define QSV_V_REG1 48
+#define QSV_V_CTL_THREAD 48
+#define QSV_V_THREAD 63
 
 struct PhaseDesc {
   int32_t op_end;                 // ops [previous op_end, op_end) of the pass

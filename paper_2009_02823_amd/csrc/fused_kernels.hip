@@ -260,115 +260,20 @@ __device__ __forceinline__ void diag1_k(cx<R>* a, cx<R> d0, cx<R> d1) {
   for (int ri = 0; ri < NA; ++ri) a[ri] = (((ri >> K) & 1) ? d1 : d0) * a[ri];
 }
 
-// ---- runtime register position -> compile-time template instance
-#define QSV_AT_K(NAME, CALL)                                                   \
-  template <typename R, int RB, bool ADJ, int K = 0, typename... Args>        \
-  __device__ __forceinline__ void NAME(int k, cx<R>* a, Args... args) {       \
-    if constexpr (K < RB) {                                                    \
-      if (k == K) CALL;                                                        \
-      else NAME<R, RB, ADJ, K + 1>(k, a, args...);                             \
-    }                                                                          \
-  }
-QSV_AT_K(ry_at, (ry_k<R, 1 << RB, K, ADJ>(a, args...)))
-QSV_AT_K(rx_at, (rx_k<R, 1 << RB, K, ADJ>(a, args...)))
-QSV_AT_K(rz_at, (rz_k<R, 1 << RB, K, ADJ>(a, args...)))
-QSV_AT_K(cnot_tr_at, (cnot_tr<R, 1 << RB, K>(a, args...)))
-QSV_AT_K(dense1_at, (dense1_k<R, 1 << RB, K>(a, args...)))
-QSV_AT_K(diag1_at, (diag1_k<R, 1 << RB, K>(a, args...)))
-#undef QSV_AT_K
-
-template <typename R, int RB, int KC = 0, int KT = 0>
-__device__ __forceinline__ void cnot_rr_at(int kc, int kt, cx<R>* a) {
-  if constexpr (KC < RB) {
-    if constexpr (KT < RB) {
-      if constexpr (KC != KT) {
-        if (kc == KC && kt == KT) {
-          cnot_rr<R, 1 << RB, KC, KT>(a);
-          return;
-        }
-      }
-      cnot_rr_at<R, RB, KC, KT + 1>(kc, kt, a);
-    } else {
-      cnot_rr_at<R, RB, KC + 1, 0>(kc, kt, a);
-    }
-  }
-}
-
-template <typename R, int RB, int KA = 0, int KB = 0>
-__device__ __forceinline__ void neg_rr_at(int ka, int kb, cx<R>* a, bool on) {
-  if constexpr (KA < RB) {
-    if constexpr (KB < RB) {
-      if (ka == KA && kb == KB) {
-        neg_where<R, 1 << RB, (1 << KA) | (1 << KB)>(a, on);
-        return;
-      }
-      neg_rr_at<R, RB, KA, KB + 1>(ka, kb, a, on);
-    } else {
-      neg_rr_at<R, RB, KA + 1, 0>(ka, kb, a, on);
-    }
+// ---- runtime register position -> compile-time template instance (general ops)
+template <typename R, int RB, bool ADJ, int K = 0, typename... Args>
+__device__ __forceinline__ void dense1_at(int k, cx<R>* a, Args... args) {
+  if constexpr (K < RB) {
+    if (k == K) dense1_k<R, 1 << RB, K>(a, args...);
+    else dense1_at<R, RB, ADJ, K + 1>(k, a, args...);
   }
 }
 
 __device__ __forceinline__ bool thread_bit(uint32_t tdep, int s) { return (tdep >> s) & 1u; }
 
-// Applies a lean op (or its inverse when ADJ) to one state's registers.
-// Rotations take cos(t/2), sin(t/2) from the staged op; fixed gates read their matrix record.
-template <typename R, int RB, bool ADJ>
-__device__ __forceinline__ void apply_lean(const FusedOp& op, R c, R s, const GateRec* rec,
-                                           cx<R>* a, uint32_t tdep) {
-  constexpr int NA = 1 << RB;
-  switch (op.type) {
-    case FOP_RY:
-      ry_at<R, RB, ADJ>(op.k0, a, c, s);
-      break;
-    case FOP_RX:
-      rx_at<R, RB, ADJ>(op.k0, a, c, s);
-      break;
-    case FOP_RZ:
-      if (op.flags & FOPF_S0_REG) rz_at<R, RB, ADJ>(op.ks0, a, c, s);
-      else rz_thr<R, NA, ADJ>(a, c, s, thread_bit(tdep, op.s0));
-      break;
-    case FOP_CNOT:  // self-inverse
-      if (op.flags & FOPF_S0_REG) cnot_rr_at<R, RB>(op.ks0, op.k0, a);
-      else cnot_tr_at<R, RB, ADJ>(op.k0, a, thread_bit(tdep, op.s0));
-      break;
-    case FOP_CZ: {  // self-inverse
-      const bool r0 = op.flags & FOPF_S0_REG, r1 = op.flags & FOPF_S1_REG;
-      if (r0 && r1) neg_rr_at<R, RB>(op.ks0, op.ks1, a, true);
-      else if (r0) neg_rr_at<R, RB>(op.ks0, op.ks0, a, thread_bit(tdep, op.s1));
-      else if (r1) neg_rr_at<R, RB>(op.ks1, op.ks1, a, thread_bit(tdep, op.s0));
-      else neg_where<R, NA, 0>(a, thread_bit(tdep, op.s0) && thread_bit(tdep, op.s1));
-      break;
-    }
-    case FOP_DENSE1: {
-      cx<R> m00 = mat<R>(rec, 0), m01 = mat<R>(rec, 1), m10 = mat<R>(rec, 2), m11 = mat<R>(rec, 3);
-      if (ADJ) {
-        const cx<R> t = m01;
-        m00 = conj(m00); m11 = conj(m11); m01 = conj(m10); m10 = conj(t);
-      }
-      dense1_at<R, RB, ADJ>(op.k0, a, m00, m01, m10, m11);
-      break;
-    }
-    case FOP_DIAG1: {
-      cx<R> d0 = mat<R>(rec, 0), d1 = mat<R>(rec, 3);
-      if (ADJ) { d0 = conj(d0); d1 = conj(d1); }
-      if (op.flags & FOPF_S0_REG) {
-        diag1_at<R, RB, ADJ>(op.ks0, a, d0, d1);
-      } else {
-        const cx<R> d = sel(thread_bit(tdep, op.s0), d1, d0);
-#pragma unroll
-        for (int ri = 0; ri < NA; ++ri) a[ri] = d * a[ri];
-      }
-      break;
-    }
-    default:
-      break;
-  }
-}
-
 // ---------------------------------------------------------------------------------------------
 // Products of the lean parameterised ops: Re <lambda|dR phi'> = (1/2) Im <lambda|G|phi>, phi
-// before the un-application.
+// before the un-application. Per-pair terms are summed as a balanced tree.
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ double im_cm(double lr, double li, double fr, double fi) {
   return lr * fi - li * fr;  // Im(conj(l) f)
@@ -377,68 +282,250 @@ __device__ __forceinline__ double re_cm(double lr, double li, double fr, double 
   return lr * fr + li * fi;  // Re(conj(l) f)
 }
 
+template <int N>
+__device__ __forceinline__ double tree_sum(const double* t) {
+  if constexpr (N == 1) return t[0];
+  else return tree_sum<N / 2>(t) + tree_sum<N - N / 2>(t + N / 2);
+}
+
 template <typename R, int NA, int K>
 __device__ __forceinline__ double prod_ry_k(const cx<R>* f, const cx<R>* l) {
-  double s = 0;  // Y f = (-i f1, i f0)
+  double t[NA / 2];  // Y f = (-i f1, i f0)
+  int j = 0;
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
     if (ri & (1 << K)) continue;
     const int rj = ri | (1 << K);
-    s += re_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i) - re_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i);
+    t[j++] = re_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i) - re_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i);
   }
-  return 0.5 * s;
+  return 0.5 * tree_sum<NA / 2>(t);
 }
 
 template <typename R, int NA, int K>
 __device__ __forceinline__ double prod_rx_k(const cx<R>* f, const cx<R>* l) {
-  double s = 0;  // X f = (f1, f0)
+  double t[NA / 2];  // X f = (f1, f0)
+  int j = 0;
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
     if (ri & (1 << K)) continue;
     const int rj = ri | (1 << K);
-    s += im_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i) + im_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i);
+    t[j++] = im_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i) + im_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i);
   }
-  return 0.5 * s;
+  return 0.5 * tree_sum<NA / 2>(t);
 }
 
 template <typename R, int NA, int K>
 __device__ __forceinline__ double prod_rz_k(const cx<R>* f, const cx<R>* l) {
-  double s = 0;  // Z f = (-1)^bit f
+  double t[NA / 2];  // Z f = (-1)^bit f
+  int j = 0;
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
-    const double v = im_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i);
-    s += ((ri >> K) & 1) ? -v : v;
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    t[j++] = im_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i) - im_cm(l[rj].r, l[rj].i, f[rj].r, f[rj].i);
   }
-  return 0.5 * s;
+  return 0.5 * tree_sum<NA / 2>(t);
 }
 
-#define QSV_PROD_AT(NAME, FN)                                                       \
-  template <typename R, int RB, int K = 0>                                          \
-  __device__ __forceinline__ double NAME(int k, const cx<R>* f, const cx<R>* l) {   \
-    if constexpr (K < RB) {                                                         \
-      if (k == K) return FN<R, 1 << RB, K>(f, l);                                    \
-      return NAME<R, RB, K + 1>(k, f, l);                                            \
-    } else {                                                                        \
-      return 0.0;                                                                   \
-    }                                                                               \
-  }
-QSV_PROD_AT(prod_ry_at, prod_ry_k)
-QSV_PROD_AT(prod_rx_at, prod_rx_k)
-QSV_PROD_AT(prod_rz_at, prod_rz_k)
-#undef QSV_PROD_AT
-
-template <typename R, int RB>
-__device__ __forceinline__ double lean_product(const FusedOp& op, const cx<R>* f, const cx<R>* l,
-                                               uint32_t tdep) {
-  constexpr int NA = 1 << RB;
-  if (op.type == FOP_RY) return prod_ry_at<R, RB>(op.k0, f, l);
-  if (op.type == FOP_RX) return prod_rx_at<R, RB>(op.k0, f, l);
-  if (op.flags & FOPF_S0_REG) return prod_rz_at<R, RB>(op.ks0, f, l);
-  double s = 0;
+template <typename R, int NA>
+__device__ __forceinline__ double prod_im_all(const cx<R>* f, const cx<R>* l) {
+  double t[NA];
 #pragma unroll
-  for (int ri = 0; ri < NA; ++ri) s += im_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i);
-  return thread_bit(tdep, op.s0) ? -0.5 * s : 0.5 * s;
+  for (int ri = 0; ri < NA; ++ri) t[ri] = im_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i);
+  return tree_sum<NA>(t);
 }
+
+// ---------------------------------------------------------------------------------------------
+// Lean ops, one fully specialised function per (op, register positions). With BWD the op runs
+// as a step of the reverse sweep on (phi = f, lambda = l): the product with phi taken before the
+// un-application, then U^dag on both states; otherwise U on f alone.
+// ---------------------------------------------------------------------------------------------
+template <typename R, int RB, bool BWD, int K>
+__device__ __forceinline__ double op_ry(R c, R s, cx<R>* f, cx<R>* l) {
+  constexpr int NA = 1 << RB;
+  double p = 0.0;
+  if constexpr (K < RB) {
+    if constexpr (BWD) p = prod_ry_k<R, NA, K>(f, l);
+    ry_k<R, NA, K, BWD>(f, c, s);
+    if constexpr (BWD) ry_k<R, NA, K, true>(l, c, s);
+  }
+  return p;
+}
+
+template <typename R, int RB, bool BWD, int K>
+__device__ __forceinline__ double op_rx(R c, R s, cx<R>* f, cx<R>* l) {
+  constexpr int NA = 1 << RB;
+  double p = 0.0;
+  if constexpr (K < RB) {
+    if constexpr (BWD) p = prod_rx_k<R, NA, K>(f, l);
+    rx_k<R, NA, K, BWD>(f, c, s);
+    if constexpr (BWD) rx_k<R, NA, K, true>(l, c, s);
+  }
+  return p;
+}
+
+template <typename R, int RB, bool BWD, int K>
+__device__ __forceinline__ double op_rz(R c, R s, cx<R>* f, cx<R>* l) {
+  constexpr int NA = 1 << RB;
+  double p = 0.0;
+  if constexpr (K < RB) {
+    if constexpr (BWD) p = prod_rz_k<R, NA, K>(f, l);
+    rz_k<R, NA, K, BWD>(f, c, s);
+    if constexpr (BWD) rz_k<R, NA, K, true>(l, c, s);
+  }
+  return p;
+}
+
+// RZ on a thread bit b: Z = (-1)^b on all of the thread's amplitudes
+template <typename R, int RB, bool BWD>
+__device__ __forceinline__ double op_rz_thr(R c, R s, cx<R>* f, cx<R>* l, bool b) {
+  constexpr int NA = 1 << RB;
+  double p = 0.0;
+  if constexpr (BWD) {
+    const double v = 0.5 * prod_im_all<R, NA>(f, l);
+    p = b ? -v : v;
+  }
+  rz_thr<R, NA, BWD>(f, c, s, b);
+  if constexpr (BWD) rz_thr<R, NA, true>(l, c, s, b);
+  return p;
+}
+
+template <typename R, int RB, bool BWD, int KC, int KT>
+__device__ __forceinline__ double op_cnot_rr(cx<R>* f, cx<R>* l) {
+  if constexpr (KC < RB && KT < RB && KC != KT) {  // self-inverse
+    cnot_rr<R, 1 << RB, KC, KT>(f);
+    if constexpr (BWD) cnot_rr<R, 1 << RB, KC, KT>(l);
+  }
+  return 0.0;
+}
+
+template <typename R, int RB, bool BWD, int KT>
+__device__ __forceinline__ double op_cnot_tr(cx<R>* f, cx<R>* l, bool on) {
+  if constexpr (KT < RB) {
+    cnot_tr<R, 1 << RB, KT>(f, on);
+    if constexpr (BWD) cnot_tr<R, 1 << RB, KT>(l, on);
+  }
+  return 0.0;
+}
+
+template <typename R, int RB, bool BWD, int KA, int KB>
+__device__ __forceinline__ double op_cz_rr(cx<R>* f, cx<R>* l) {
+  if constexpr (KA < RB && KB < RB && KA != KB) {  // self-inverse
+    neg_where<R, 1 << RB, (1 << KA) | (1 << KB)>(f, true);
+    if constexpr (BWD) neg_where<R, 1 << RB, (1 << KA) | (1 << KB)>(l, true);
+  }
+  return 0.0;
+}
+
+// CZ with one register bit K and one thread bit (on = its value)
+template <typename R, int RB, bool BWD, int K>
+__device__ __forceinline__ double op_cz_r(cx<R>* f, cx<R>* l, bool on) {
+  if constexpr (K < RB) {
+    neg_where<R, 1 << RB, 1 << K>(f, on);
+    if constexpr (BWD) neg_where<R, 1 << RB, 1 << K>(l, on);
+  }
+  return 0.0;
+}
+
+template <typename R, int RB, bool BWD>
+__device__ __forceinline__ double op_cz_tt(cx<R>* f, cx<R>* l, bool on) {
+  neg_where<R, 1 << RB, 0>(f, on);
+  if constexpr (BWD) neg_where<R, 1 << RB, 0>(l, on);
+  return 0.0;
+}
+
+template <typename R, int RB, bool BWD, int K>
+__device__ __forceinline__ double op_dense1(const GateRec* rec, cx<R>* f, cx<R>* l) {
+  if constexpr (K < RB) {
+    cx<R> m00 = mat<R>(rec, 0), m01 = mat<R>(rec, 1), m10 = mat<R>(rec, 2), m11 = mat<R>(rec, 3);
+    if constexpr (BWD) {
+      const cx<R> t = m01;
+      m00 = conj(m00); m11 = conj(m11); m01 = conj(m10); m10 = conj(t);
+    }
+    dense1_k<R, 1 << RB, K>(f, m00, m01, m10, m11);
+    if constexpr (BWD) dense1_k<R, 1 << RB, K>(l, m00, m01, m10, m11);
+  }
+  return 0.0;
+}
+
+template <typename R, int RB, bool BWD, int K>
+__device__ __forceinline__ double op_diag1(const GateRec* rec, cx<R>* f, cx<R>* l) {
+  if constexpr (K < RB) {
+    cx<R> d0 = mat<R>(rec, 0), d1 = mat<R>(rec, 3);
+    if constexpr (BWD) { d0 = conj(d0); d1 = conj(d1); }
+    diag1_k<R, 1 << RB, K>(f, d0, d1);
+    if constexpr (BWD) diag1_k<R, 1 << RB, K>(l, d0, d1);
+  }
+  return 0.0;
+}
+
+template <typename R, int RB, bool BWD>
+__device__ __forceinline__ double op_diag1_thr(const GateRec* rec, cx<R>* f, cx<R>* l, bool b) {
+  constexpr int NA = 1 << RB;
+  cx<R> d = sel(b, mat<R>(rec, 3), mat<R>(rec, 0));
+  if constexpr (BWD) d = conj(d);
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) f[ri] = d * f[ri];
+  if constexpr (BWD) {
+#pragma unroll
+    for (int ri = 0; ri < NA; ++ri) l[ri] = d * l[ri];
+  }
+  return 0.0;
+}
+
+// One lean op, dispatched on its op code by a single switch whose cases are all fully
+// specialised: no nested per-position branches whose joins would copy the amplitude registers.
+// Returns the op's product (reverse sweep, RX/RY/RZ; 0 otherwise).
+#define QSV_K5(T, V0, FN, ...)                                                      \
+  case QSV_OPC(T, (V0) + 0): p = FN<R, RB, BWD, 0>(__VA_ARGS__); break;           \
+  case QSV_OPC(T, (V0) + 1): p = FN<R, RB, BWD, 1>(__VA_ARGS__); break;           \
+  case QSV_OPC(T, (V0) + 2): p = FN<R, RB, BWD, 2>(__VA_ARGS__); break;           \
+  case QSV_OPC(T, (V0) + 3): p = FN<R, RB, BWD, 3>(__VA_ARGS__); break;           \
+  case QSV_OPC(T, (V0) + 4): p = FN<R, RB, BWD, 4>(__VA_ARGS__); break;
+#define QSV_KK1(T, A, FN, ...)                                                      \
+  case QSV_OPC(T, 8 * (A) + 0): p = FN<R, RB, BWD, A, 0>(__VA_ARGS__); break;     \
+  case QSV_OPC(T, 8 * (A) + 1): p = FN<R, RB, BWD, A, 1>(__VA_ARGS__); break;     \
+  case QSV_OPC(T, 8 * (A) + 2): p = FN<R, RB, BWD, A, 2>(__VA_ARGS__); break;     \
+  case QSV_OPC(T, 8 * (A) + 3): p = FN<R, RB, BWD, A, 3>(__VA_ARGS__); break;     \
+  case QSV_OPC(T, 8 * (A) + 4): p = FN<R, RB, BWD, A, 4>(__VA_ARGS__); break;
+#define QSV_KK5(T, FN, ...)                                                         \
+  QSV_KK1(T, 0, FN, __VA_ARGS__) QSV_KK1(T, 1, FN, __VA_ARGS__)                     \
+  QSV_KK1(T, 2, FN, __VA_ARGS__) QSV_KK1(T, 3, FN, __VA_ARGS__)                     \
+  QSV_KK1(T, 4, FN, __VA_ARGS__)
+
+template <typename R, int RB, bool BWD>
+__device__ __forceinline__ double lean_step(const FusedOp& op, R c, R s, const GateRec* rec,
+                                            cx<R>* f, cx<R>* l, uint32_t tdep) {
+  static_assert(RB <= 5, "op codes hold register positions below 5");
+  double p = 0.0;
+  switch (op.opc) {
+    QSV_K5(FOP_RY, 0, op_ry, c, s, f, l)
+    QSV_K5(FOP_RX, 0, op_rx, c, s, f, l)
+    QSV_K5(FOP_RZ, 0, op_rz, c, s, f, l)
+    case QSV_OPC(FOP_RZ, QSV_V_THREAD):
+      p = op_rz_thr<R, RB, BWD>(c, s, f, l, thread_bit(tdep, op.s0));
+      break;
+    QSV_KK5(FOP_CNOT, op_cnot_rr, f, l)
+    QSV_K5(FOP_CNOT, QSV_V_CTL_THREAD, op_cnot_tr, f, l, thread_bit(tdep, op.s0))
+    QSV_KK5(FOP_CZ, op_cz_rr, f, l)
+    QSV_K5(FOP_CZ, QSV_V_REG0, op_cz_r, f, l, thread_bit(tdep, op.s1))
+    QSV_K5(FOP_CZ, QSV_V_REG1, op_cz_r, f, l, thread_bit(tdep, op.s0))
+    case QSV_OPC(FOP_CZ, QSV_V_THREAD):
+      p = op_cz_tt<R, RB, BWD>(f, l, thread_bit(tdep, op.s0) && thread_bit(tdep, op.s1));
+      break;
+    QSV_K5(FOP_DENSE1, 0, op_dense1, rec, f, l)
+    QSV_K5(FOP_DIAG1, 0, op_diag1, rec, f, l)
+    case QSV_OPC(FOP_DIAG1, QSV_V_THREAD):
+      p = op_diag1_thr<R, RB, BWD>(rec, f, l, thread_bit(tdep, op.s0));
+      break;
+    default:
+      break;
+  }
+  return p;
+}
+#undef QSV_K5
+#undef QSV_KK1
+#undef QSV_KK5
 
 // ---------------------------------------------------------------------------------------------
 // General ops (tile bits evaluated per amplitude)
@@ -701,7 +788,8 @@ __device__ __forceinline__ void stage_pass(const PassItem& I, OpStage* sops, Pha
 }
 
 static_assert(sizeof(FusedOp) == 16 && offsetof(FusedOp, s0) == 3 && offsetof(FusedOp, flags) == 7 &&
-                  offsetof(FusedOp, ks1) == 9 && offsetof(FusedOp, gate) == 12,
+                  offsetof(FusedOp, ks1) == 9 && offsetof(FusedOp, opc) == 10 &&
+                  offsetof(FusedOp, gate) == 12,
               "FusedOp is read from LDS as four words");
 
 // Raw words of staged op k (issued early; made uniform when the op is executed).
@@ -726,7 +814,7 @@ __device__ __forceinline__ FusedOp uniform_op(uint4 raw) {
   op.flags = (uint8_t)(w1 >> 24);
   op.ks0 = (uint8_t)w2;
   op.ks1 = (uint8_t)(w2 >> 8);
-  op.pad[0] = op.pad[1] = 0;
+  op.opc = (uint16_t)(w2 >> 16);
   op.gate = (int32_t)__builtin_amdgcn_readfirstlane(raw.w);
   return op;
 }
@@ -803,7 +891,7 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           ncs = staged_cs(sops, k + 1);
           const GateRec* rec = I.recs + op.gate;
           if (GEN && op.type >= FOP_FIRST_GENERAL) apply_general<R, RB, false>(op, rec, a, cur);
-          else apply_lean<R, RB, false>(op, (R)cs.x, (R)cs.y, rec, a, cur.tdep);
+          else lean_step<R, RB, false>(op, (R)cs.x, (R)cs.y, rec, a, nullptr, cur.tdep);
         }
       }
       if (!same_layout<RB>(cur, D.rb)) relayout<R, RB>(a, cur, D, lds);
@@ -881,9 +969,7 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
             if (op.np) general_products<R, RB>(op, rec, f, l, cur, prod);
             apply_general<R, RB, true>(op, rec, l, cur);
           } else {
-            if (op.np) prod[0] = lean_product<R, RB>(op, f, l, cur.tdep);
-            apply_lean<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, f, cur.tdep);
-            apply_lean<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, l, cur.tdep);
+            prod[0] = lean_step<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, f, l, cur.tdep);
           }
 #pragma unroll
           for (int j = 0; j < 3; ++j) {

@@ -257,6 +257,19 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
             if (msg) *msg = "unknown gate kind";
             return false;
         }
+        const bool r0 = op.flags & FOPF_S0_REG, r1 = op.flags & FOPF_S1_REG;
+        int v = 0;
+        switch (op.type) {
+          case FOP_RY: case FOP_RX: case FOP_DENSE1: v = op.k0; break;
+          case FOP_RZ: case FOP_DIAG1: v = r0 ? op.ks0 : QSV_V_THREAD; break;
+          case FOP_CNOT: v = r0 ? 8 * op.ks0 + op.k0 : QSV_V_CTL_THREAD + op.k0; break;
+          case FOP_CZ:
+            v = r0 && r1 ? 8 * op.ks0 + op.ks1 : r0 ? QSV_V_REG0 + op.ks0
+                : r1 ? QSV_V_REG1 + op.ks1 : QSV_V_THREAD;
+            break;
+          default: v = 0; break;
+        }
+        op.opc = (uint16_t)QSV_OPC(op.type, v);
         if (op.type >= FOP_FIRST_GENERAL) pd.general = 1;
         if (np) {
           op.lslot = (uint8_t)lslot;

@@ -1007,12 +1007,13 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
 // Geometries with a kernel instance whose amplitude registers do not spill (reverse sweep: two
 // states per thread).
 bool fused_config_supported(int r, int w, bool c128) {
+  if (w == 9) return r == 3 || (!c128 && r == 4);
   if (w == 8) return r >= 2 && r <= (c128 ? 3 : 4);
   if (w == 6) return r >= 2 && r <= 3;
   return false;
 }
 
-#define QSV_FUSED_CASES(X, R) X(R, 2, 8) X(R, 3, 8) X(R, 2, 6) X(R, 3, 6)
+#define QSV_FUSED_CASES(X, R) X(R, 2, 8) X(R, 3, 8) X(R, 3, 9) X(R, 2, 6) X(R, 3, 6)
 
 template <typename R>
 hipError_t launch_fused_forward(const PassItem* d_items, int n_items, int64_t total, int64_t chunk,
@@ -1028,7 +1029,7 @@ hipError_t launch_fused_forward(const PassItem* d_items, int n_items, int64_t to
     return hipGetLastError();                                                                  \
   }
   QSV_FUSED_CASES(X, R)
-  if constexpr (sizeof(R) == 4) { X(R, 4, 8) }
+  if constexpr (sizeof(R) == 4) { X(R, 4, 8) X(R, 4, 9) }
 #undef X
   return hipErrorInvalidValue;
 }
@@ -1048,7 +1049,7 @@ hipError_t launch_fused_backward(const PassItem* d_items, int n_items, int64_t t
     return hipGetLastError();                                                                  \
   }
   QSV_FUSED_CASES(X, R)
-  if constexpr (sizeof(R) == 4) { X(R, 4, 8) }
+  if constexpr (sizeof(R) == 4) { X(R, 4, 8) X(R, 4, 9) }
 #undef X
   return hipErrorInvalidValue;
 }

@@ -1468,7 +1468,7 @@ extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t 
   } else {
     std::vector<std::array<int, 3>> cands;
     if (s->n <= 20) cands.push_back({0, 0, 0});
-    const int ws[2] = {8, 6};
+    const int ws[3] = {9, 8, 6};
     for (int w : ws)
       for (int r = 2; r <= kMaxRegBits; ++r)
         if (fused_config_supported(r, w, s->dt == QSV_C128) && r + w <= s->n)

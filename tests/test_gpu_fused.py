@@ -12,7 +12,8 @@ from paper_2009_02823_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-GEOMS = {"c128": [(2, 8), (3, 8), (2, 6), (3, 6)], "c64": [(2, 8), (3, 8), (4, 8), (2, 6), (3, 6)]}
+GEOMS = {"c128": [(2, 8), (3, 8), (3, 9), (2, 6), (3, 6)],
+         "c64": [(2, 8), (3, 8), (4, 8), (3, 9), (4, 9), (2, 6), (3, 6)]}
 ALL_KINDS = list(W.GATE_NAMES)
 
 
@@ -79,7 +80,7 @@ def test_hea_many_tiles(Q, orc, dtype):
     coeffs = rng.standard_normal(30)
     e_ref, g_ref = orc.adjoint_gradient(n, gates, theta, codes, coeffs)
     psi_ref = orc.statevector(n, gates, theta)
-    for geom in GEOMS[dtype][:3]:
+    for geom in GEOMS[dtype]:
         e, g, psi = run(Q, n, gates, theta, codes, coeffs, dtype, geom)
         tol_check(dtype, e, g, psi, e_ref, g_ref, psi_ref, coeffs)
 

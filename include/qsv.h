@@ -248,10 +248,13 @@ qsv_status qsv_timing_read(qsv_state* s, qsv_kernel_stat* out, int32_t max_out, 
      mode = 1   fused passes: each pass loads every tile of 2^(reg_qubits + threads_log2)
                 amplitudes once (workgroups of 2^threads_log2 threads, 2^reg_qubits amplitudes of
                 each state per thread), applies a scheduled run of gates in registers and LDS, and
-                stores it once; supported (reg_qubits, threads_log2): (2..3, 8) for complex128,
-                (2..4, 8) for complex64, (2..3, 6) for both;
-     mode = -1  automatic (the default): fused with a size-dependent geometry when the state holds
-                a tile, gate-granular otherwise. */
+                stores it once; supported (reg_qubits, threads_log2): (2..3, 8) and (3, 9) for
+                complex128, (2..4, 8) and (3..4, 9) for complex64, (2..3, 6) for both. A tile
+                may exceed the state: its extra ("phantom") bits hold amplitudes that are never
+                loaded or stored, and a state within one tile runs every pass of a sweep in a
+                single launch (one workgroup walks the passes in order);
+     mode = -1  automatic (the default): fused with a size-dependent geometry. qsv_autotune
+                picks among all modes by measurement. */
 qsv_status qsv_set_fusion(qsv_state* s, int32_t mode, int32_t reg_qubits, int32_t threads_log2);
 
 /* The geometry the handle currently runs with: *mode = 1 (fused, with *reg_qubits and

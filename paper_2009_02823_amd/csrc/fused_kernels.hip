@@ -717,17 +717,32 @@ struct Geometry {
   static constexpr int NW = NT / 64;
 };
 
+// Offsets of the thread's amplitudes in the direct layout: thread bits = tile bits 0..W-1,
+// register bits = tile bits W..T-1. Phantom tile bits (tile[s] < 0, states smaller than the tile)
+// contribute no address bit; amplitudes with a phantom bit set are not live (never loaded or
+// stored, zero in registers). live: the thread's phantom bits are all zero; preg: register
+// positions on phantom bits.
 template <int RB, int W>
 __device__ __forceinline__ void direct_offsets(const PassDesc& pd, uint32_t tid, uint64_t& gthr,
-                                               uint64_t* groff) {
+                                               uint64_t* groff, bool& live, uint32_t& preg) {
   gthr = 0;
+  live = true;
 #pragma unroll
-  for (int s = 0; s < W; ++s) gthr |= (uint64_t)((tid >> s) & 1u) << pd.tile[s];
+  for (int s = 0; s < W; ++s) {
+    const uint32_t b = (tid >> s) & 1u;
+    if (pd.tile[s] >= 0) gthr |= (uint64_t)b << pd.tile[s];
+    else live = live && !b;
+  }
+  preg = 0;
+#pragma unroll
+  for (int k = 0; k < RB; ++k)
+    if (pd.tile[W + k] < 0) preg |= 1u << k;
 #pragma unroll
   for (int ri = 0; ri < (1 << RB); ++ri) {
     uint64_t o = 0;
 #pragma unroll
-    for (int k = 0; k < RB; ++k) o |= (uint64_t)((ri >> k) & 1) << pd.tile[W + k];
+    for (int k = 0; k < RB; ++k)
+      if (pd.tile[W + k] >= 0) o |= (uint64_t)((ri >> k) & 1) << pd.tile[W + k];
     groff[ri] = o;
   }
 }
@@ -860,13 +875,18 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     V* dst = static_cast<V*>(I.dst);
     const int n_ph = I.pd.phase_end - I.pd.phase_begin;
     uint64_t gthr, groff[G::NA];
-    direct_offsets<RB, W>(I.pd, tid, gthr, groff);
+    bool live;
+    uint32_t preg;
+    direct_offsets<RB, W>(I.pd, tid, gthr, groff, live, preg);
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
     for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
       const uint64_t ob = obase | gthr;
       cx<R> a[G::NA];
 #pragma unroll
-      for (int ri = 0; ri < G::NA; ++ri) a[ri] = load<R>(src, ob | groff[ri]);
+      for (int ri = 0; ri < G::NA; ++ri) {
+        a[ri] = cx<R>{0, 0};
+        if (live && !(ri & preg)) a[ri] = load<R>(src, ob | groff[ri]);
+      }
       if (g == g0) {  // staged while the first tile's loads are in flight
         stage_pass(I, sops, sph, (int)tid, G::NT);
         lds_barrier();
@@ -896,8 +916,12 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
       }
       if (!same_layout<RB>(cur, D.rb)) relayout<R, RB>(a, cur, D, lds);
 #pragma unroll
-      for (int ri = 0; ri < G::NA; ++ri) store<R>(dst, ob | groff[ri], a[ri]);
+      for (int ri = 0; ri < G::NA; ++ri)
+        if (live && !(ri & preg)) store<R>(dst, ob | groff[ri], a[ri]);
     }
+    // the next item may be the next pass over the same tile (a circuit whose state is one tile
+    // runs all its passes in one launch): this thread's stores precede its loads there
+    __threadfence_block();
     lds_barrier();  // the staged tables are rewritten for the next item
     g0 = stop;
     ++it;
@@ -928,7 +952,9 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     V* lam = static_cast<V*>(I.lam);
     const int n_ph = I.pd.phase_end - I.pd.phase_begin;
     uint64_t gthr, groff[G::NA];
-    direct_offsets<RB, W>(I.pd, tid, gthr, groff);
+    bool live;
+    uint32_t preg;
+    direct_offsets<RB, W>(I.pd, tid, gthr, groff, live, preg);
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
     // lane j of every wave accumulates product slot j over the wave's share of the tiles
     double acc = 0.0;
@@ -937,8 +963,12 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
       cx<R> f[G::NA], l[G::NA];
 #pragma unroll
       for (int ri = 0; ri < G::NA; ++ri) {
-        f[ri] = load<R>(phi, ob | groff[ri]);
-        l[ri] = load<R>(lam, ob | groff[ri]);
+        f[ri] = cx<R>{0, 0};
+        l[ri] = cx<R>{0, 0};
+        if (live && !(ri & preg)) {
+          f[ri] = load<R>(phi, ob | groff[ri]);
+          l[ri] = load<R>(lam, ob | groff[ri]);
+        }
       }
       if (g == g0) {  // staged while the first tile's loads are in flight
         stage_pass(I, sops, sph, (int)tid, G::NT);
@@ -982,8 +1012,10 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
       if (!same_layout<RB>(cur, D.rb)) relayout2<R, RB>(f, l, cur, D, lds, 1 << G::T);
 #pragma unroll
       for (int ri = 0; ri < G::NA; ++ri) {
-        store<R>(phi, ob | groff[ri], f[ri]);
-        store<R>(lam, ob | groff[ri], l[ri]);
+        if (live && !(ri & preg)) {
+          store<R>(phi, ob | groff[ri], f[ri]);
+          store<R>(lam, ob | groff[ri], l[ri]);
+        }
       }
     }
     wacc[lane][wave] = acc;
@@ -995,6 +1027,7 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
       for (int w = 0; w < G::NW; ++w) s += wacc[j][w];
       I.partials[(size_t)j * I.nb + col] = make_double2(s, 0.0);
     }
+    __threadfence_block();  // see k_pass_fwd
     lds_barrier();  // wacc and the staged tables are rewritten for the next item
     g0 = stop;
     ++it;

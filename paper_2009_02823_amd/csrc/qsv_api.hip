@@ -177,6 +177,10 @@ struct FusedPlan {
   std::vector<int32_t> occ_nb;
   DevBuf d_items_fwd_phi, d_items_fwd_state, d_items_bwd, partials, d_occ_base, d_occ_nb,
       d_final;
+  // When one tile covers the state, every pass of a sweep runs in one launch: a single
+  // workgroup walks the passes in order (items with consecutive tile indices).
+  DevBuf d_seq_fwd_phi, d_seq_fwd_state, d_seq_bwd;
+  bool seq_gen_fwd = false, seq_gen_bwd = false;
 };
 
 // A circuit lowered for the device: gate table, matrix records, and the map from parameters to
@@ -620,7 +624,9 @@ static bool fusion_geometry(const qsv_state* s, int* r, int* w) {
       *w = 6;
       return true;
     }
-  return false;
+  *r = 2;  // the state is smaller than the smallest tile: one tile with phantom bits
+  *w = 6;
+  return true;
 }
 
 static qsv_status upload_schedule(FusedSchedule& fs, hipStream_t st) {
@@ -705,8 +711,8 @@ static qsv_status get_fused(qsv_state* s, Plan* p, int r, int w, FusedPlan** out
     *out = it->second.get();
     return QSV_OK;
   }
-  if (!fused_config_supported(r, w, s->dt == QSV_C128) || r + w > s->n)
-    return fail(QSV_ERR_UNSUPPORTED, "fused geometry r=%d w=%d not available for n=%d", r, w, s->n);
+  if (!fused_config_supported(r, w, s->dt == QSV_C128))
+    return fail(QSV_ERR_UNSUPPORTED, "fused geometry r=%d w=%d not available", r, w);
   const hipStream_t st = s->stream;
   auto fp = std::make_unique<FusedPlan>();
   fp->r = r;
@@ -725,7 +731,7 @@ static qsv_status get_fused(qsv_state* s, Plan* p, int r, int w, FusedPlan** out
   QSV_TRY(upload_schedule(fp->bwd, st));
 
   // single-circuit launch items
-  const int n_outer = s->n - fp->t;
+  const int n_outer = std::max(0, s->n - fp->t);
   fp->tiles = 1ll << n_outer;
   launch_shape(fp->tiles, &fp->grid, &fp->chunk);
   int32_t first = 0, nb = 1;
@@ -764,6 +770,21 @@ static qsv_status get_fused(qsv_state* s, Plan* p, int r, int w, FusedPlan** out
   QSV_TRY(upload_vec(fp->d_items_fwd_phi, fp->items_fwd_phi, st));
   QSV_TRY(upload_vec(fp->d_items_fwd_state, fp->items_fwd_state, st));
   QSV_TRY(upload_vec(fp->d_items_bwd, fp->items_bwd, st));
+  if (fp->tiles == 1) {
+    auto sequence = [](std::vector<PassItem> v) {
+      for (size_t i = 0; i < v.size(); ++i) {
+        v[i].tile_begin = (int64_t)i;
+        v[i].first_wg = 0;
+        v[i].nb = 1;
+      }
+      return v;
+    };
+    QSV_TRY(upload_vec(fp->d_seq_fwd_phi, sequence(fp->items_fwd_phi), st));
+    QSV_TRY(upload_vec(fp->d_seq_fwd_state, sequence(fp->items_fwd_state), st));
+    QSV_TRY(upload_vec(fp->d_seq_bwd, sequence(fp->items_bwd), st));
+    for (const PassDesc& pd : fp->fwd.sched.passes) fp->seq_gen_fwd = fp->seq_gen_fwd || pd.general;
+    for (const PassDesc& pd : bs.passes) fp->seq_gen_bwd = fp->seq_gen_bwd || pd.general;
+  }
   QSV_TRY(upload_vec(fp->d_occ_base, fp->occ_base, st));
   QSV_TRY(upload_vec(fp->d_occ_nb, fp->occ_nb, st));
   QSV_TRY(upload_final(fp->d_final, fp->partials, fp->d_occ_base, fp->d_occ_nb, p, st));
@@ -799,6 +820,13 @@ static qsv_status forward(qsv_state* s, Plan* p, const void* src, void* dst) {
     FusedPlan* fp = nullptr;
     QSV_TRY(get_fused(s, p, r, w, &fp));
     const Schedule& sc = fp->fwd.sched;
+    if (fp->tiles == 1) {
+      const PassItem* seq = (src == dst ? fp->d_seq_fwd_state : fp->d_seq_fwd_phi).as<PassItem>();
+      const int K = (int)sc.passes.size();
+      return timed(s, "k_pass_fwd", 2 * S * K, [&] {
+        return launch_fused_forward<R>(seq, K, K, K, r, w, fp->seq_gen_fwd, 1, st);
+      });
+    }
     const PassItem* items = (src == dst ? fp->d_items_fwd_state : fp->d_items_fwd_phi).as<PassItem>();
     for (size_t i = 0; i < sc.passes.size(); ++i) {
       QSV_TRY(timed(s, "k_pass_fwd", 2 * S, [&] {
@@ -833,6 +861,14 @@ static qsv_status backward(qsv_state* s, Plan* p, const FinalDesc** final_desc) 
     FusedPlan* fp = nullptr;
     QSV_TRY(get_fused(s, p, r, w, &fp));
     const Schedule& sc = fp->bwd.sched;
+    *final_desc = fp->d_final.as<FinalDesc>();
+    if (fp->tiles == 1) {
+      const int K = (int)sc.passes.size();
+      return timed(s, "k_pass_bwd", 4 * S * K, [&] {
+        return launch_fused_backward<R>(fp->d_seq_bwd.as<PassItem>(), K, K, K, r, w,
+                                        fp->seq_gen_bwd, 1, st);
+      });
+    }
     const PassItem* items = fp->d_items_bwd.as<PassItem>();
     for (size_t i = 0; i < sc.passes.size(); ++i) {
       QSV_TRY(timed(s, "k_pass_bwd", 4 * S, [&] {
@@ -1354,9 +1390,6 @@ extern "C" qsv_status qsv_set_fusion(qsv_state* s, int32_t mode, int32_t reg_qub
     if (!fused_config_supported(reg_qubits, threads_log2, s->dt == QSV_C128))
       return fail(QSV_ERR_UNSUPPORTED, "no fused kernel for reg_qubits=%d threads_log2=%d",
                   reg_qubits, threads_log2);
-    if (reg_qubits + threads_log2 > s->n)
-      return fail(QSV_ERR_INVALID_ARG, "tile of %d qubits exceeds the %d-qubit state",
-                  reg_qubits + threads_log2, s->n);
   }
   s->fusion_mode = mode;
   s->fr = mode == 1 ? reg_qubits : 0;
@@ -1384,7 +1417,7 @@ extern "C" qsv_status qsv_schedule_describe(int32_t n, const qsv_gate* gates, in
                                !out->tile_mask || !out->reg_mask)))
     return fail(QSV_ERR_INVALID_ARG, "NULL output array");
   if (reg_qubits < 1 || reg_qubits > kMaxRegBits || threads_log2 < 1 ||
-      reg_qubits + threads_log2 > n || reg_qubits + threads_log2 > kMaxTileBits)
+      reg_qubits + threads_log2 > kMaxTileBits)
     return fail(QSV_ERR_INVALID_ARG, "tile geometry r=%d w=%d invalid for n=%d", reg_qubits,
                 threads_log2, n);
   std::vector<GateDesc> g(reinterpret_cast<const GateDesc*>(gates),
@@ -1471,7 +1504,7 @@ extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t 
     const int ws[3] = {9, 8, 6};
     for (int w : ws)
       for (int r = 2; r <= kMaxRegBits; ++r)
-        if (fused_config_supported(r, w, s->dt == QSV_C128) && r + w <= s->n)
+        if (fused_config_supported(r, w, s->dt == QSV_C128) && r + w <= std::max(s->n, 8))
           cands.push_back({1, r, w});
     DevBuf e, g;
     QSV_TRY(e.ensure(sizeof(double), s->stream));

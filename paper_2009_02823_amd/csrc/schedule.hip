@@ -85,11 +85,14 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
   out.t = t;
   out.r = r;
   out.w = w;
-  if (t != r + w || t > n || t > kMaxTileBits || r > kMaxRegBits || r < 1) {
+  if (t != r + w || t > kMaxTileBits || r > kMaxRegBits || r < 1 || n < 1) {
     if (msg) *msg = "tile/register sizes do not fit the state";
     return false;
   }
   const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  // a state smaller than the tile fills its low tile bits; the other tile bits are phantom
+  // (their amplitudes are never loaded or stored and stay zero)
+  const int tq = std::min(t, n);
   // low qubits always in the tile: contiguous runs of 2^c amplitudes per load
   const int c = std::min(4, std::min(w, n));
   const uint64_t low = (1ull << c) - 1;
@@ -98,16 +101,16 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
   while (!rem.empty()) {
     // ---- choose the tile: best of several candidates by gates taken
     std::vector<uint64_t> cands;
-    cands.push_back(fill_tile(grow_tile(rem, gates, low, t), n, t));
-    cands.push_back(fill_tile(grow_tile(rem, gates, low | qmask(gates[rem[0]]), t), n, t));
-    for (int a = c; a + (t - c) <= n; ++a) {
-      uint64_t win = (((1ull << (t - c)) - 1) << a) | low;
+    cands.push_back(fill_tile(grow_tile(rem, gates, low, tq), n, tq));
+    cands.push_back(fill_tile(grow_tile(rem, gates, low | qmask(gates[rem[0]]), tq), n, tq));
+    for (int a = c; a + (tq - c) <= n; ++a) {
+      uint64_t win = (((1ull << (tq - c)) - 1) << a) | low;
       cands.push_back(win & all);
     }
     uint64_t bestT = 0;
     int best = -1;
     for (uint64_t T : cands) {
-      if (popc(T) != t) continue;
+      if (popc(T) != tq) continue;
       int cnt = 0;
       scan(rem, gates, T, backward, kMaxSlotsPerPass, kMaxOpsPerPass, nullptr, &cnt);
       if (cnt > best) {
@@ -138,6 +141,7 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
         pd.outer_mask |= 1ull << q;
       }
     }
+    while (s < t) pd.tile[s++] = -1;  // phantom tile bits
     pd.n_outer = o;
     pd.phase_begin = (int32_t)out.phases.size();
     pd.op_begin = (int32_t)out.ops.size();
@@ -192,7 +196,8 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
         }
       const int phase_id = (int32_t)out.phases.size();
       uint64_t rphys = 0;
-      for (int k2 = 0; k2 < r; ++k2) rphys |= 1ull << pd.tile[P.regbit[k2]];
+      for (int k2 = 0; k2 < r; ++k2)
+        if (pd.tile[P.regbit[k2]] >= 0) rphys |= 1ull << pd.tile[P.regbit[k2]];
       out.reg_mask.push_back(rphys);
       for (int k : ph) {
         const GateDesc& g = gates[k];

@@ -116,11 +116,32 @@ def test_fused_deterministic(Q):
 
 def test_set_fusion_validation(Q):
     with Q.StateVector(9) as sv:
-        with pytest.raises(Q.QsvError):
-            sv.set_fusion(1, 3, 8)      # tile of 11 qubits > 9
+        sv.set_fusion(1, 3, 8)          # an 11-qubit tile over 9 qubits: 2 phantom tile bits
+        assert sv.get_fusion() == (1, 3, 8)
         with pytest.raises(Q.QsvError):
             sv.set_fusion(1, 7, 8)      # no kernel for 7 register qubits
         sv.set_fusion(1, 3, 6)
         assert sv.get_fusion() == (1, 3, 6)
         sv.set_fusion(0)
         assert sv.get_fusion()[0] == 0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 9])
+def test_states_smaller_than_the_tile(Q, orc, dtype, n):
+    """Phantom tile bits: every gate kind on states of 1..9 qubits inside one 8- to 12-bit tile;
+    all passes of a sweep run in one launch."""
+    rng = np.random.default_rng(300 + n)
+    kinds = [k for k in ALL_KINDS if n >= 2 or W.N_QUBITS[k] == 1]
+    gates, P = W.random_circuit(rng, n, 120, kinds)
+    theta = W.uniform_angles(rng, P)
+    codes = W.random_pauli_strings(rng, n, 5)
+    coeffs = rng.standard_normal(5)
+    e_ref, g_ref = orc.adjoint_gradient(n, gates, theta, codes, coeffs)
+    psi_ref = orc.statevector(n, gates, theta)
+    geoms = [(2, 6), (3, 8)] + ([(4, 9)] if dtype == "c64" else [(3, 9)])
+    for geom in geoms:
+        e, g, psi = run(Q, n, gates, theta, codes, coeffs, dtype, geom)
+        tol_check(dtype, e, g, psi, e_ref, g_ref, psi_ref, coeffs)
+    with Q.StateVector(n, dtype) as sv:       # the automatic geometry
+        assert sv.get_fusion()[0] == 1

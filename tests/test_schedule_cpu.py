@@ -45,11 +45,13 @@ def check_schedule(n, gates, backward, r, w):
     t = r + w
     for i, k in enumerate(order):
         tile = int(info["tile_mask"][info["pass_of"][i]])
-        assert bin(tile).count("1") == t
+        # a state smaller than the tile fills it; the other tile bits are phantom
+        assert bin(tile).count("1") == min(t, n)
         for q in qubits(gates[k]):
             assert (tile >> q) & 1, "gate outside its pass's tile"
         regm = int(info["reg_mask"][info["phase_of"][i]])
-        assert bin(regm).count("1") == r and (regm & ~tile) == 0
+        assert (regm & ~tile) == 0
+        assert bin(regm).count("1") == r if t <= n else bin(regm).count("1") <= r
         assert (reg_need(gates[k]) & ~regm) == 0, "non-diagonal target not in registers"
     return info
 
@@ -70,7 +72,7 @@ def test_hea_schedules_valid(n, L, cz, backward, r, w):
 @pytest.mark.parametrize("seed", range(12))
 def test_random_schedules_valid_and_equivalent(seed, orc):
     rng = np.random.default_rng(seed)
-    n = int(rng.integers(8, 13))
+    n = int(rng.integers(2, 13))
     gates, P = W.random_circuit(rng, n, 150, list(W.GATE_NAMES))
     theta = W.uniform_angles(rng, P)
     r, w = (2, 6) if seed % 2 else (3, 6)
@@ -94,9 +96,20 @@ def test_random_schedules_valid_and_equivalent(seed, orc):
 def test_schedule_rejects_bad_geometry():
     gates = W.hea_circuit(8, 1)
     with pytest.raises(qsv.QsvError):
-        qsv.schedule_describe(8, gates, False, 4, 8)      # tile of 12 > 8 qubits
-    with pytest.raises(qsv.QsvError):
         qsv.schedule_describe(8, gates, False, 0, 6)
+    with pytest.raises(qsv.QsvError):
+        qsv.schedule_describe(8, gates, False, 6, 8)      # more register bits than supported
+    with pytest.raises(qsv.QsvError):
+        qsv.schedule_describe(8, gates, False, 5, 10)     # tile of 15 > 14 bits
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_tile_larger_than_state(n):
+    """A 12-bit tile over a smaller state: one tile, every pass over all qubits."""
+    gates = W.hea_circuit(n, 6)
+    for backward in (False, True):
+        info = check_schedule(n, gates, backward, 4, 8)
+        assert np.all(info["tile_mask"][:info["n_passes"]] == (1 << n) - 1)
 
 
 def test_pass_counts_reported():

@@ -233,6 +233,55 @@ def sweep_p(qsv, torch, W, n, layers_list, ps_entries):
     return {"n_qubits": n, "rows": rows, "loglog_slopes": fit}
 
 
+def paper_sweep(qsv, torch, W, n, layers_list, runs, cpu):
+    """The paper's benchmark (Sec. 3): Algorithm 1 (adjoint) and Algorithm 2 (reference) on the
+    GPU at a few qubits under Hadamard^(x)n, P = 2 n L; mean and standard deviation over `runs`
+    timed runs each (every run synchronised), and the log-log slopes of time against P. With
+    `cpu`, the CPU oracle's Algorithm 1 and 2 times beside them (one run each)."""
+    import numpy as np
+    rows = []
+    for L in layers_list:
+        prob = W.paper_benchmark(n, L)
+        sv = qsv.StateVector(n, "c128", device="cuda:0")
+        theta = torch.as_tensor(prob.theta, device="cuda:0")
+        e = torch.empty(1, dtype=torch.float64, device="cuda:0")
+        g = torch.empty(prob.n_params, dtype=torch.float64, device="cuda:0")
+        row = {"layers": L, "P": prob.n_params, "gates": prob.n_gates}
+        for name, fn in (("adjoint", sv.adjoint_gradient), ("reference", sv.reference_gradient)):
+            for _ in range(2):
+                fn(prob.gates, theta, prob.codes, prob.coeffs, e, g)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(runs):
+                t0 = time.perf_counter()
+                fn(prob.gates, theta, prob.codes, prob.coeffs, e, g)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row[name + "_s"] = float(np.mean(ts))
+            row[name + "_std_s"] = float(np.std(ts))
+            row[name + "_grad"] = g.cpu().numpy()
+        row["max_abs_diff"] = float(np.max(np.abs(row.pop("adjoint_grad") - row.pop("reference_grad"))))
+        row["speedup"] = row["reference_s"] / row["adjoint_s"]
+        sv.close()
+        if cpu:
+            from oracle import oracle as O
+            t0 = time.perf_counter()
+            O.adjoint_gradient(n, prob.gates, prob.theta, prob.codes, prob.coeffs)
+            row["cpu_adjoint_s"] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            O.reference_gradient(n, prob.gates, prob.theta, prob.codes, prob.coeffs)
+            row["cpu_reference_s"] = time.perf_counter() - t0
+        rows.append(row)
+        log(f"N={n} L={L} P={prob.n_params}: adjoint {1e3 * row['adjoint_s']:.3f} ms, reference "
+            f"{1e3 * row['reference_s']:.3f} ms, speedup {row['speedup']:.1f}, "
+            f"|dg| {row['max_abs_diff']:.1e}")
+    lp = np.log([r["P"] for r in rows])
+    keys = ["adjoint_s", "reference_s", "speedup"] + (["cpu_adjoint_s", "cpu_reference_s"] if cpu else [])
+    fit = {k: float(np.polyfit(lp, np.log([r[k] for r in rows]), 1)[0]) for k in keys}
+    return {"n_qubits": n, "observable": "Hadamard^(x)n", "runs": runs, "rows": rows,
+            "loglog_slopes": fit}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +300,11 @@ def main():
                          "5: 30 qubits")
     ap.add_argument("--sweep-p", action="store_true",
                     help="adjoint vs parameter shift over the number of layers at 20 qubits")
+    ap.add_argument("--paper", type=int, default=0, metavar="N",
+                    help="the paper's benchmark at N qubits (4 or 5): Algorithm 1 vs Algorithm 2 "
+                         "on the GPU, P up to 1290, 24 runs per point")
+    ap.add_argument("--paper-cpu", action="store_true",
+                    help="with --paper: also time the CPU oracle's Algorithms 1 and 2")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -270,6 +324,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log(f"copy calibration: 2 x {args.copy_calibration} MiB")
+
+    if args.paper:
+        n = args.paper
+        layers = [1, 2, 4, 8, 16, 32, 64, 1290 // (2 * n)]
+        res = paper_sweep(qsv, torch, W, n, layers, 24, args.paper_cpu)
+        print(json.dumps({"metric": "Algorithm 1 vs Algorithm 2 gradient time over P", **res}))
+        return
 
     if args.sweep_p:
         res = sweep_p(qsv, torch, W, 20, [1, 2, 4, 8, 16, 20], args.ps_entries)

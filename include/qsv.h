@@ -201,6 +201,17 @@ qsv_status qsv_param_shift_gradient(qsv_state* s, const qsv_gate* gates, int32_t
                                     const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
                                     int32_t first, int32_t count, double* d_grad);
 
+/* The same energy and gradient by the reference scheme of Algorithm 2 (Sec. 3): lambda = H U |in>,
+   then for every parameter occurrence i a separate simulation mu = U_G..U_{i+1} dU_i/dtheta
+   U_{i-1}..U_1 |in> and the entry 2 Re <lambda|mu> (summed over the occurrences of a repeated
+   parameter); O(P^2) gate applications. Arguments and results as qsv_adjoint_gradient. States that
+   fit one fused tile (see qsv_set_fusion) run all entries in parallel, one workgroup each, with a
+   library-allocated pool of up to 1 GiB of mu states; larger states run the entries one after
+   another in the phi buffer. Meant as the faithful comparison baseline for small circuits. */
+qsv_status qsv_reference_gradient(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                                  const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
+                                  double* d_energy, double* d_grad);
+
 /* ---- graphs and tuning ------------------------------------------------------------------- */
 
 /* on != 0: qsv_adjoint_gradient and qsv_adjoint_gradient_batched capture their launch sequence

@@ -100,12 +100,16 @@ struct PassItem {
   const int32_t* slot_map;
   const void* src;      // forward: state read by the pass
   void* dst;            // forward: state written (may equal src); backward: phi
-  void* lam;            // backward: lambda
+  void* lam;            // backward: lambda. Forward (reference gradient): if set, the item ends
+                        // with Re <lam|state> per workgroup in partials[] instead of a store
   double2* partials;    // backward: this item's block of partials, [local slot][workgroup]
   int64_t tile_begin;   // first tile of the item in the launch's concatenated tile range
   int32_t n_outer;      // log2 of the item's tile count
   int32_t first_wg;     // first workgroup whose chunk reaches into the item
   int32_t nb;           // workgroups whose chunks reach into the item (partials stride)
+  int32_t sub_op;       // forward, general instance: pass-local op applied as its derivative
+                        // in parameter sub_param instead of its matrix (-1: none)
+  int32_t sub_param;
   int32_t pad;
 };
 

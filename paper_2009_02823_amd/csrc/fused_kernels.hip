@@ -633,6 +633,47 @@ __device__ __forceinline__ void apply_general(const FusedOp& op, const GateRec* 
   }
 }
 
+// mu <- D_j mu, D_j the derivative of the op's matrix in its j-th parameter, from the op's record:
+// rotations and one-qubit parameterised gates m[4 + 4j ..], controlled rotations the |1><1| (x) dR
+// block (amplitudes with control 0 zeroed), two-qubit gates m[16 ..].
+template <typename R, int RB>
+__device__ __forceinline__ void apply_derivative(const FusedOp& op, const GateRec* rec, int j,
+                                                 cx<R>* mu, const Layout<RB>& L) {
+  constexpr int NA = 1 << RB;
+  switch (op.type) {
+    case FOP_RY: case FOP_RX: case FOP_PDENSE1: {
+      const int o = 4 + 4 * j;
+      dense1_at<R, RB, false>(op.k0, mu, mat<R>(rec, o), mat<R>(rec, o + 1), mat<R>(rec, o + 2),
+                              mat<R>(rec, o + 3));
+      break;
+    }
+    case FOP_RZ: case FOP_PDIAG1: {
+      const cx<R> e0 = mat<R>(rec, 4), e1 = mat<R>(rec, 7);
+#pragma unroll
+      for (int ri = 0; ri < NA; ++ri) mu[ri] = sel(bit_of<RB>(op.s0, L, ri), e1, e0) * mu[ri];
+      break;
+    }
+    case FOP_CDENSE1:
+      dense1_at<R, RB, false>(op.k0, mu, mat<R>(rec, 26), mat<R>(rec, 27), mat<R>(rec, 30),
+                              mat<R>(rec, 31));
+#pragma unroll
+      for (int ri = 0; ri < NA; ++ri) mu[ri] = sel(bit_of<RB>(op.s0, L, ri), mu[ri], cx<R>{0, 0});
+      break;
+    case FOP_DIAG2: {
+      const cx<R> e[4] = {mat<R>(rec, 16), mat<R>(rec, 21), mat<R>(rec, 26), mat<R>(rec, 31)};
+#pragma unroll
+      for (int ri = 0; ri < NA; ++ri)
+        mu[ri] = pick_diag4<R, RB>(e, bit_of<RB>(op.s0, L, ri), bit_of<RB>(op.s1, L, ri)) * mu[ri];
+      break;
+    }
+    case FOP_DENSE2:
+      dense2_at<R, RB>(op.k0, op.k1, mu, rec, 16, false);
+      break;
+    default:
+      break;
+  }
+}
+
 // Re <l|D_j f> for the explicit derivative matrices of a general op (f already un-applied).
 template <typename R, int RB>
 __device__ __forceinline__ void general_products(const FusedOp& op, const GateRec* rec,
@@ -645,39 +686,7 @@ __device__ __forceinline__ void general_products(const FusedOp& op, const GateRe
     if (j >= op.np) break;
 #pragma unroll
     for (int ri = 0; ri < NA; ++ri) mu[ri] = f[ri];
-    switch (op.type) {
-      case FOP_PDENSE1: {
-        const int o = 4 + 4 * j;
-        dense1_at<R, RB, false>(op.k0, mu, mat<R>(rec, o), mat<R>(rec, o + 1),
-                                mat<R>(rec, o + 2), mat<R>(rec, o + 3));
-        break;
-      }
-      case FOP_CDENSE1:
-        // derivative of a controlled gate: dU on the target, amplitudes with control 0 zeroed
-        dense1_at<R, RB, false>(op.k0, mu, mat<R>(rec, 26), mat<R>(rec, 27), mat<R>(rec, 30),
-                                mat<R>(rec, 31));
-#pragma unroll
-        for (int ri = 0; ri < NA; ++ri) mu[ri] = sel(bit_of<RB>(op.s0, L, ri), mu[ri], cx<R>{0, 0});
-        break;
-      case FOP_PDIAG1: {
-        const cx<R> e0 = mat<R>(rec, 4), e1 = mat<R>(rec, 7);
-#pragma unroll
-        for (int ri = 0; ri < NA; ++ri) mu[ri] = sel(bit_of<RB>(op.s0, L, ri), e1, e0) * mu[ri];
-        break;
-      }
-      case FOP_DIAG2: {
-        const cx<R> e[4] = {mat<R>(rec, 16), mat<R>(rec, 21), mat<R>(rec, 26), mat<R>(rec, 31)};
-#pragma unroll
-        for (int ri = 0; ri < NA; ++ri)
-          mu[ri] = pick_diag4<R, RB>(e, bit_of<RB>(op.s0, L, ri), bit_of<RB>(op.s1, L, ri)) * mu[ri];
-        break;
-      }
-      case FOP_DENSE2:
-        dense2_at<R, RB>(op.k0, op.k1, mu, rec, 16, false);
-        break;
-      default:
-        break;
-    }
+    apply_derivative<R, RB>(op, rec, j, mu, L);
     double s = 0;
 #pragma unroll
     for (int ri = 0; ri < NA; ++ri) s += re_cm(l[ri].r, l[ri].i, mu[ri].r, mu[ri].i);
@@ -861,7 +870,9 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
   __shared__ V lds[1 << G::T];
   __shared__ OpStage sops[kMaxOpsPerPass + 1];
   __shared__ PhaseDesc sph[kMaxPhasesPerPass];
+  __shared__ double wsum[G::NW];
   const uint32_t tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   int64_t g0 = (int64_t)blockIdx.x * chunk;
   const int64_t g1 = g0 + chunk < total ? g0 + chunk : total;
   if (g0 >= g1) return;
@@ -879,6 +890,10 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     uint32_t preg;
     direct_offsets<RB, W>(I.pd, tid, gthr, groff, live, preg);
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
+    // reference gradient (Algorithm 2): an item with lam set ends its entry with Re <lambda|mu>
+    // in place of storing mu
+    const V* lamv = static_cast<const V*>(I.lam);
+    double dot = 0.0;
     for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
       const uint64_t ob = obase | gthr;
       cx<R> a[G::NA];
@@ -910,14 +925,35 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           nraw = staged_words(sops, k + 1);
           ncs = staged_cs(sops, k + 1);
           const GateRec* rec = I.recs + op.gate;
-          if (GEN && op.type >= FOP_FIRST_GENERAL) apply_general<R, RB, false>(op, rec, a, cur);
+          if (GEN && k == I.sub_op) apply_derivative<R, RB>(op, rec, I.sub_param, a, cur);
+          else if (GEN && op.type >= FOP_FIRST_GENERAL) apply_general<R, RB, false>(op, rec, a, cur);
           else lean_step<R, RB, false>(op, (R)cs.x, (R)cs.y, rec, a, nullptr, cur.tdep);
         }
       }
       if (!same_layout<RB>(cur, D.rb)) relayout<R, RB>(a, cur, D, lds);
+      if (lamv) {
 #pragma unroll
-      for (int ri = 0; ri < G::NA; ++ri)
-        if (live && !(ri & preg)) store<R>(dst, ob | groff[ri], a[ri]);
+        for (int ri = 0; ri < G::NA; ++ri)
+          if (live && !(ri & preg)) {
+            const cx<R> l = load<R>(lamv, ob | groff[ri]);
+            dot += re_cm(l.r, l.i, a[ri].r, a[ri].i);
+          }
+      } else {
+#pragma unroll
+        for (int ri = 0; ri < G::NA; ++ri)
+          if (live && !(ri & preg)) store<R>(dst, ob | groff[ri], a[ri]);
+      }
+    }
+    if (lamv) {
+      const double t = wave_total_lane63(dot);
+      if (lane == 63) wsum[wave] = t;
+      lds_barrier();
+      if (tid == 0) {
+        double sum = 0;
+#pragma unroll
+        for (int w = 0; w < G::NW; ++w) sum += wsum[w];
+        I.partials[(int)blockIdx.x - I.first_wg] = make_double2(sum, 0.0);
+      }
     }
     // the next item may be the next pass over the same tile (a circuit whose state is one tile
     // runs all its passes in one launch): this thread's stores precede its loads there

@@ -183,6 +183,18 @@ struct FusedPlan {
   bool seq_gen_fwd = false, seq_gen_bwd = false;
 };
 
+// Reference-gradient (Algorithm 2) tables of one circuit for one tile geometry: for every
+// parameter occurrence ("entry"), the forward passes with that occurrence's gate applied as its
+// derivative, the last pass ending in Re <lambda|mu>. Entry e's K items are consecutive.
+struct RefPlan {
+  int K = 0;                // forward passes
+  int64_t E = 0;            // entries
+  bool single = false;      // one tile covers the state: entries in parallel, a workgroup each
+  int64_t per_launch = 0;   // single: entries per launch (size of the mu pool)
+  int nb = 1;               // partials per entry (workgroups of its last pass)
+  DevBuf items, mu_pool, partials, d_occ_base, d_occ_nb, d_final;
+};
+
 // A circuit lowered for the device: gate table, matrix records, and the map from parameters to
 // the reduction slots of their occurrences (in sweep order, last gate first).
 struct Plan {
@@ -193,6 +205,7 @@ struct Plan {
   std::vector<int32_t> param_ptr, occ;
   DevBuf d_gates, d_recs, d_param_ptr, d_occ;
   std::map<int, std::unique_ptr<FusedPlan>> fused;  // key r * 16 + w
+  std::map<int, std::unique_ptr<RefPlan>> ref;      // key r * 16 + w
   // gate-granular reverse sweep: partials [slot][block] and their descriptors
   bool gg_ready = false;
   DevBuf gg_partials, d_gg_occ_base, d_gg_occ_nb, d_gg_final;
@@ -603,30 +616,37 @@ static constexpr int kFusedGridCap = 1024;
 
 // Tile geometry for the handle: (r, w) with t = r + w tile qubits, or false for the gate-granular
 // path (states too small for a tile, or fusion switched off).
+static void auto_geometry(const qsv_state* s, int* r, int* w);
+
 static bool fusion_geometry(const qsv_state* s, int* r, int* w) {
-  const bool c128 = s->dt == QSV_C128;
   if (s->fusion_mode == 0) return false;
   if (s->fusion_mode == 1) {
     *r = s->fr;
     *w = s->fw;
     return true;
   }
+  auto_geometry(s, r, w);
+  return true;
+}
+
+// Size-dependent default geometry (fusion mode -1).
+static void auto_geometry(const qsv_state* s, int* r, int* w) {
+  const bool c128 = s->dt == QSV_C128;
   const int rmax = c128 ? 3 : 4;
   for (int rr = rmax; rr >= 2; --rr)
     if (rr + 8 <= s->n) {
       *r = rr;
       *w = 8;
-      return true;
+      return;
     }
   for (int rr = 3; rr >= 2; --rr)
     if (rr + 6 <= s->n) {
       *r = rr;
       *w = 6;
-      return true;
+      return;
     }
   *r = 2;  // the state is smaller than the smallest tile: one tile with phantom bits
   *w = 6;
-  return true;
 }
 
 static qsv_status upload_schedule(FusedSchedule& fs, hipStream_t st) {
@@ -685,6 +705,7 @@ static PassItem make_item(const FusedSchedule& fs, size_t i, const Plan* p, cons
   it.dst = dst;
   it.lam = lam;
   it.n_outer = n_outer;
+  it.sub_op = -1;
   return it;
 }
 
@@ -1295,6 +1316,149 @@ static qsv_status param_shift_t(qsv_state* s, Plan* p, PauliPlan* hp, const doub
   }
   HIP_TRY(launch_ps_combine(d_grad, e, first, count, st));
   return QSV_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// reference gradient (Algorithm 2)
+// ------------------------------------------------------------------------------------------------
+static constexpr size_t kRefPoolBytes = size_t(1) << 30;  // mu pool of the parallel entries
+
+static qsv_status get_ref(qsv_state* s, Plan* p, FusedPlan* fp, RefPlan** out) {
+  const int key = fp->r * 16 + fp->w;
+  auto it = p->ref.find(key);
+  if (it != p->ref.end()) {
+    *out = it->second.get();
+    return QSV_OK;
+  }
+  const hipStream_t st = s->stream;
+  auto rp = std::make_unique<RefPlan>();
+  const FusedSchedule& fs = fp->fwd;
+  const Schedule& sc = fs.sched;
+  const int K = (int)sc.passes.size(), G = (int)p->gates.size();
+  const size_t S = qsv_state_bytes(s->n, s->dt);
+  rp->K = K;
+  rp->E = p->n_occ;
+  rp->single = fp->tiles == 1;
+  rp->nb = rp->single ? 1 : fp->nb;
+  std::vector<int> op_of_gate(G, -1);
+  for (size_t i = 0; i < sc.order.size(); ++i) op_of_gate[sc.order[i]] = (int)i;
+  if (rp->single) {
+    rp->per_launch = std::max<int64_t>(1, std::min<int64_t>(rp->E, (int64_t)(kRefPoolBytes / S)));
+    QSV_TRY(rp->mu_pool.ensure(S * (size_t)std::max<int64_t>(rp->per_launch, 1), st));
+  }
+  QSV_TRY(rp->partials.ensure(sizeof(double2) * (size_t)std::max<int64_t>(rp->E * rp->nb, 1), st));
+  const int n_outer = std::max(0, s->n - fp->t);
+  void* lam = static_cast<char*>(s->d_work) + S;
+  std::vector<PassItem> items((size_t)rp->E * K);
+  for (int g = 0; g < G; ++g) {
+    const int np = kind_nparams(p->gates[g].kind);
+    if (!np) continue;
+    const int i = op_of_gate[g];
+    const int pk = sc.pass_of[i];
+    const int kloc = i - sc.passes[pk].op_begin;
+    for (int j = 0; j < np; ++j) {
+      const int64_t o = p->slot_of_gate[g] + j;
+      // mu: a pool slot (parallel entries) or the phi buffer, free once lambda = H psi is built
+      const int64_t slot = rp->single ? o % rp->per_launch : 0;
+      void* mu = rp->single ? static_cast<char*>(rp->mu_pool.p) + (size_t)slot * S : s->d_work;
+      for (int k = 0; k < K; ++k) {
+        PassItem it = make_item(fs, k, p, k == 0 ? s->d_state : mu, mu, nullptr, n_outer);
+        if (rp->single) {
+          it.tile_begin = slot * K + k;
+          it.first_wg = (int32_t)slot;
+          it.nb = 1;
+        } else {
+          it.nb = fp->nb;
+        }
+        if (k == pk) {
+          it.sub_op = kloc;
+          it.sub_param = j;
+        }
+        if (k == K - 1) {
+          it.lam = lam;
+          it.partials = rp->partials.as<double2>() + o * rp->nb;
+        }
+        items[(size_t)o * K + k] = it;
+      }
+    }
+  }
+  QSV_TRY(upload_vec(rp->items, items, st));
+  std::vector<int64_t> base((size_t)std::max<int64_t>(rp->E, 1), 0);
+  std::vector<int32_t> cnt((size_t)std::max<int64_t>(rp->E, 1), rp->nb);
+  for (int64_t o = 0; o < rp->E; ++o) base[o] = o * rp->nb;
+  QSV_TRY(upload_vec(rp->d_occ_base, base, st));
+  QSV_TRY(upload_vec(rp->d_occ_nb, cnt, st));
+  QSV_TRY(upload_final(rp->d_final, rp->partials, rp->d_occ_base, rp->d_occ_nb, p, st));
+  *out = rp.get();
+  p->ref[key] = std::move(rp);
+  return QSV_OK;
+}
+
+template <typename R>
+static qsv_status reference_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* d_theta,
+                              double* d_energy, double* d_grad) {
+  const hipStream_t st = s->stream;
+  const int nb = s->nb;
+  const double S = state_bytes_d(s);
+  void* phi = s->d_work;
+  void* lam = static_cast<char*>(s->d_work) + qsv_state_bytes(s->n, s->dt);
+  QSV_TRY(s->epartials.ensure(sizeof(double2) * nb, st));
+  double2* ep = s->epartials.as<double2>();
+  HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
+                      p->d_recs.as<GateRec>(), st));
+  // lambda := |in>, lambda <- U lambda (in the phi buffer), lambda <- H lambda; E = <psi|H psi>
+  QSV_TRY(forward<R>(s, p, s->d_state, phi));
+  QSV_TRY(pauli<R>(s, hp, phi, lam, ep));
+  HIP_TRY(launch_final_energy(ep, nb, d_energy, nullptr, st));
+  if (p->n_occ == 0) {  // no gate carries a parameter: every entry is 0
+    QSV_TRY(get_gate_granular(s, p));
+    HIP_TRY(launch_final_grad(p->d_gg_final.as<FinalDesc>(), 1, p->n_theta, d_grad, st));
+    return QSV_OK;
+  }
+  int r = 0, w = 0;
+  if (!fusion_geometry(s, &r, &w)) auto_geometry(s, &r, &w);
+  FusedPlan* fp = nullptr;
+  QSV_TRY(get_fused(s, p, r, w, &fp));
+  RefPlan* rp = nullptr;
+  QSV_TRY(get_ref(s, p, fp, &rp));
+  const int K = rp->K;
+  const PassItem* items = rp->items.as<PassItem>();
+  if (rp->single) {
+    for (int64_t e0 = 0; e0 < rp->E; e0 += rp->per_launch) {
+      const int64_t m = std::min<int64_t>(rp->per_launch, rp->E - e0);
+      QSV_TRY(timed(s, "k_pass_fwd_ref", 2 * S * K * m, [&] {
+        return launch_fused_forward<R>(items + e0 * K, (int)(m * K), m * K, K, r, w, true,
+                                       (int)m, st);
+      }));
+    }
+  } else {
+    for (int64_t o = 0; o < rp->E; ++o)
+      for (int k = 0; k < K; ++k)
+        QSV_TRY(timed(s, "k_pass_fwd_ref", 2 * S, [&] {
+          return launch_fused_forward<R>(items + o * K + k, 1, fp->tiles, fp->chunk, r, w, true,
+                                         fp->grid, st);
+        }));
+  }
+  HIP_TRY(launch_final_grad(rp->d_final.as<FinalDesc>(), 1, p->n_theta, d_grad, st));
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_reference_gradient(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                                             const double* d_theta, int32_t n_theta,
+                                             const qsv_pauli_sum* H, double* d_energy,
+                                             double* d_grad) {
+  QSV_TRY(check_handle(s));
+  QSV_TRY(qsv_validate_circuit(s->n, gates, n_gates, n_theta));
+  QSV_TRY(qsv_validate_pauli_sum(s->n, H));
+  if (!d_energy) return fail(QSV_ERR_INVALID_ARG, "d_energy is NULL");
+  if (n_theta > 0 && !d_grad) return fail(QSV_ERR_INVALID_ARG, "d_grad is NULL");
+  Plan* p = nullptr;
+  QSV_TRY(get_plan(s, gates, n_gates, n_theta, &p));
+  QSV_TRY(check_theta(p, d_theta));
+  PauliPlan* hp = nullptr;
+  QSV_TRY(get_pauli(s, H, &hp));
+  return s->dt == QSV_C128 ? reference_t<double>(s, p, hp, d_theta, d_energy, d_grad)
+                           : reference_t<float>(s, p, hp, d_theta, d_energy, d_grad);
 }
 
 extern "C" qsv_status qsv_param_shift_gradient(qsv_state* s, const qsv_gate* gates,

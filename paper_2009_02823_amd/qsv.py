@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
         "qsv_energy": ([P, P, i32, P, i32, P, P], i32),
         "qsv_adjoint_gradient_batched": ([i32, P, P, P, P, P, P, P, P, P], i32),
         "qsv_param_shift_gradient": ([P, P, i32, P, i32, P, i32, i32, P], i32),
+        "qsv_reference_gradient": ([P, P, i32, P, i32, P, P, P], i32),
         "qsv_timing_enable": ([P, ctypes.c_char_p], i32),
         "qsv_timing_read": ([P, P, i32, ctypes.POINTER(i32)], i32),
         "qsv_set_fusion": ([P, i32, i32, i32], i32),
@@ -275,6 +276,24 @@ class StateVector:
                                          t.data_ptr() if t.numel() else None, t.numel(),
                                          ctypes.byref(s), e.data_ptr(),
                                          gr.data_ptr() if gr.numel() else None))
+        del keep
+        return e, gr
+
+    def reference_gradient(self, gates, theta, codes, coeffs, energy=None, grad=None):
+        """(E, grad) by the reference scheme of Algorithm 2: one simulation per parameter
+        occurrence with that gate replaced by its derivative (O(P^2) gates)."""
+        torch = _torch()
+        g = as_gate_table(gates)
+        t = self._theta(theta)
+        s, keep = pauli_struct(codes, coeffs, self.n)
+        e = energy if energy is not None else torch.empty(1, dtype=torch.float64,
+                                                         device=self.device)
+        gr = grad if grad is not None else torch.empty(t.numel(), dtype=torch.float64,
+                                                      device=self.device)
+        check(lib().qsv_reference_gradient(self._h, g.ctypes.data, g.shape[0],
+                                           t.data_ptr() if t.numel() else None, t.numel(),
+                                           ctypes.byref(s), e.data_ptr(),
+                                           gr.data_ptr() if gr.numel() else None))
         del keep
         return e, gr
 

@@ -127,6 +127,18 @@ def heisenberg_chain(n: int) -> tuple[np.ndarray, np.ndarray]:
     return codes, np.ones(3 * (n - 1), dtype=np.float64)
 
 
+def hadamard_product_observable(n: int) -> tuple[np.ndarray, np.ndarray]:
+    """The operator Hadamard^(x)n of the paper's benchmarks (Sec. 3) as an exact Pauli sum:
+    Hadamard = (X + Z)/sqrt(2) on every qubit, so the product is the sum of all 2^n strings over
+    {X, Z} with coefficient 2^(-n/2)."""
+    h = 1 << n
+    codes = np.empty((h, n), dtype=np.uint8)
+    for t in range(h):
+        for q in range(n):
+            codes[t, q] = PAULI_X if (t >> q) & 1 else PAULI_Z
+    return codes, np.full(h, 2.0 ** (-0.5 * n), dtype=np.float64)
+
+
 @dataclass
 class Problem:
     """One energy-plus-gradient instance."""
@@ -232,6 +244,17 @@ def random_circuit(rng: np.random.Generator, n: int, n_gates: int, kinds=None,
         rows.append((k, q0, q1, *ps))
     P = next_p if n_params is None else n_params
     return circuit_table(rows), P
+
+
+def paper_benchmark(n: int = 5, layers: int = 129) -> Problem:
+    """The paper's benchmark regime (Sec. 3): a few qubits, many parameters, under
+    Hadamard^(x)n; the HEA (RY, RZ on every qubit, CNOT ladder) stands in for its ansatz circuits.
+    P = 2 n layers (n = 5, 129 layers: P = 1290, the largest count benchmarked there)."""
+    rng = rng_for(6)
+    theta = uniform_angles(rng, 2 * n * layers)
+    codes, coeffs = hadamard_product_observable(n)
+    return Problem(f"hea{n}_L{layers}_hadamard", n, hea_circuit(n, layers), theta, codes, coeffs,
+                   ("c128",))
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

@@ -259,8 +259,8 @@ qsv_status qsv_timing_read(qsv_state* s, qsv_kernel_stat* out, int32_t max_out, 
      mode = 1   fused passes: each pass loads every tile of 2^(reg_qubits + threads_log2)
                 amplitudes once (workgroups of 2^threads_log2 threads, 2^reg_qubits amplitudes of
                 each state per thread), applies a scheduled run of gates in registers and LDS, and
-                stores it once; supported (reg_qubits, threads_log2): (2..3, 8) and (3, 9) for
-                complex128, (2..4, 8) and (3..4, 9) for complex64, (2..3, 6) for both. A tile
+                stores it once; supported (reg_qubits, threads_log2): (2..4, 8) and (2..3, 9) for
+                complex128, (2..4, 8) and (2..4, 9) for complex64, (2..3, 6) for both. A tile
                 may exceed the state: its extra ("phantom") bits hold amplitudes that are never
                 loaded or stored, and a state within one tile runs every pass of a sweep in a
                 single launch (one workgroup walks the passes in order);

@@ -889,6 +889,7 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     bool live;
     uint32_t preg;
     direct_offsets<RB, W>(I.pd, tid, gthr, groff, live, preg);
+    const bool phantom = I.pd.tile[G::T - 1] < 0;  // phantom bits are the top tile bits
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
     // reference gradient (Algorithm 2): an item with lam set ends its entry with Re <lambda|mu>
     // in place of storing mu
@@ -897,10 +898,15 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
       const uint64_t ob = obase | gthr;
       cx<R> a[G::NA];
+      if (!phantom) {
 #pragma unroll
-      for (int ri = 0; ri < G::NA; ++ri) {
-        a[ri] = cx<R>{0, 0};
-        if (live && !(ri & preg)) a[ri] = load<R>(src, ob | groff[ri]);
+        for (int ri = 0; ri < G::NA; ++ri) a[ri] = load<R>(src, ob | groff[ri]);
+      } else {
+#pragma unroll
+        for (int ri = 0; ri < G::NA; ++ri) {
+          a[ri] = cx<R>{0, 0};
+          if (live && !(ri & preg)) a[ri] = load<R>(src, ob | groff[ri]);
+        }
       }
       if (g == g0) {  // staged while the first tile's loads are in flight
         stage_pass(I, sops, sph, (int)tid, G::NT);
@@ -938,6 +944,9 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
             const cx<R> l = load<R>(lamv, ob | groff[ri]);
             dot += re_cm(l.r, l.i, a[ri].r, a[ri].i);
           }
+      } else if (!phantom) {
+#pragma unroll
+        for (int ri = 0; ri < G::NA; ++ri) store<R>(dst, ob | groff[ri], a[ri]);
       } else {
 #pragma unroll
         for (int ri = 0; ri < G::NA; ++ri)
@@ -991,19 +1000,28 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     bool live;
     uint32_t preg;
     direct_offsets<RB, W>(I.pd, tid, gthr, groff, live, preg);
+    const bool phantom = I.pd.tile[G::T - 1] < 0;  // phantom bits are the top tile bits
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
     // lane j of every wave accumulates product slot j over the wave's share of the tiles
     double acc = 0.0;
     for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
       const uint64_t ob = obase | gthr;
       cx<R> f[G::NA], l[G::NA];
+      if (!phantom) {
 #pragma unroll
-      for (int ri = 0; ri < G::NA; ++ri) {
-        f[ri] = cx<R>{0, 0};
-        l[ri] = cx<R>{0, 0};
-        if (live && !(ri & preg)) {
+        for (int ri = 0; ri < G::NA; ++ri) {
           f[ri] = load<R>(phi, ob | groff[ri]);
           l[ri] = load<R>(lam, ob | groff[ri]);
+        }
+      } else {
+#pragma unroll
+        for (int ri = 0; ri < G::NA; ++ri) {
+          f[ri] = cx<R>{0, 0};
+          l[ri] = cx<R>{0, 0};
+          if (live && !(ri & preg)) {
+            f[ri] = load<R>(phi, ob | groff[ri]);
+            l[ri] = load<R>(lam, ob | groff[ri]);
+          }
         }
       }
       if (g == g0) {  // staged while the first tile's loads are in flight
@@ -1046,11 +1064,19 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
         }
       }
       if (!same_layout<RB>(cur, D.rb)) relayout2<R, RB>(f, l, cur, D, lds, 1 << G::T);
+      if (!phantom) {
 #pragma unroll
-      for (int ri = 0; ri < G::NA; ++ri) {
-        if (live && !(ri & preg)) {
+        for (int ri = 0; ri < G::NA; ++ri) {
           store<R>(phi, ob | groff[ri], f[ri]);
           store<R>(lam, ob | groff[ri], l[ri]);
+        }
+      } else {
+#pragma unroll
+        for (int ri = 0; ri < G::NA; ++ri) {
+          if (live && !(ri & preg)) {
+            store<R>(phi, ob | groff[ri], f[ri]);
+            store<R>(lam, ob | groff[ri], l[ri]);
+          }
         }
       }
     }
@@ -1076,13 +1102,13 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
 // Geometries with a kernel instance whose amplitude registers do not spill (reverse sweep: two
 // states per thread).
 bool fused_config_supported(int r, int w, bool c128) {
-  if (w == 9) return r == 3 || (!c128 && r == 4);
-  if (w == 8) return r >= 2 && r <= (c128 ? 3 : 4);
+  if (w == 9) return r >= 2 && r <= (c128 ? 3 : 4);
+  if (w == 8) return r >= 2 && r <= 4;
   if (w == 6) return r >= 2 && r <= 3;
   return false;
 }
 
-#define QSV_FUSED_CASES(X, R) X(R, 2, 8) X(R, 3, 8) X(R, 3, 9) X(R, 2, 6) X(R, 3, 6)
+#define QSV_FUSED_CASES(X, R) X(R, 2, 8) X(R, 3, 8) X(R, 3, 9) X(R, 2, 9) X(R, 2, 6) X(R, 3, 6)
 
 template <typename R>
 hipError_t launch_fused_forward(const PassItem* d_items, int n_items, int64_t total, int64_t chunk,
@@ -1098,7 +1124,8 @@ hipError_t launch_fused_forward(const PassItem* d_items, int n_items, int64_t to
     return hipGetLastError();                                                                  \
   }
   QSV_FUSED_CASES(X, R)
-  if constexpr (sizeof(R) == 4) { X(R, 4, 8) X(R, 4, 9) }
+  X(R, 4, 8)
+  if constexpr (sizeof(R) == 4) { X(R, 4, 9) }
 #undef X
   return hipErrorInvalidValue;
 }
@@ -1118,7 +1145,8 @@ hipError_t launch_fused_backward(const PassItem* d_items, int n_items, int64_t t
     return hipGetLastError();                                                                  \
   }
   QSV_FUSED_CASES(X, R)
-  if constexpr (sizeof(R) == 4) { X(R, 4, 8) X(R, 4, 9) }
+  X(R, 4, 8)
+  if constexpr (sizeof(R) == 4) { X(R, 4, 9) }
 #undef X
   return hipErrorInvalidValue;
 }

@@ -12,8 +12,8 @@ from paper_2009_02823_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-GEOMS = {"c128": [(2, 8), (3, 8), (3, 9), (2, 6), (3, 6)],
-         "c64": [(2, 8), (3, 8), (4, 8), (3, 9), (4, 9), (2, 6), (3, 6)]}
+GEOMS = {"c128": [(2, 8), (3, 8), (4, 8), (2, 9), (3, 9), (2, 6), (3, 6)],
+         "c64": [(2, 8), (3, 8), (4, 8), (2, 9), (3, 9), (4, 9), (2, 6), (3, 6)]}
 ALL_KINDS = list(W.GATE_NAMES)
 
 

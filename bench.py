@@ -48,14 +48,19 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(family: str, workload: str, dtype: str):
+def traffic_for(family: str, workload: str, dtype: str, geometry):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
-    current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{family}_{workload}_{dtype}.json")
+    current kernel sources and the same tile geometry (else None)."""
+    if geometry is None:
+        return None
+    path = os.path.join(ROOT, "profiles",
+                        f"traffic_{family}_{workload}_{dtype}_r{geometry[0]}w{geometry[1]}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    if list(rec.get("geometry", [])) != list(geometry):
         return None
     return rec.get("bytes_per_launch")
 
@@ -72,7 +77,10 @@ class Single:
         self.g = torch.empty(prob.n_params, dtype=torch.float64, device="cuda:0")
         self.units = 1
 
-    def autotune(self):
+    def autotune(self, geometry=None):
+        if geometry:
+            self.sv.set_fusion(1, *geometry)
+            return (1, geometry[0], geometry[1], -1.0)
         return self.sv.autotune(self.prob.gates, self.theta, self.prob.codes, self.prob.coeffs)
 
     def step(self):
@@ -100,7 +108,7 @@ class Batched:
         self.g = torch.empty(self.batch.n_params, dtype=torch.float64, device=self.batch.device)
         self.units = len(probs)
 
-    def autotune(self):
+    def autotune(self, geometry=None):
         return None
 
     def step(self):
@@ -125,9 +133,10 @@ def timed_steps(torch, runner, steps):
     return time.perf_counter() - t0
 
 
-def run(qsv, torch, runner, steps, warmup, graphs=True):
-    tuned = runner.autotune()
+def run(qsv, torch, runner, steps, warmup, graphs=True, geometry=None):
+    tuned = runner.autotune(geometry)
     h = runner.handle()
+    runner.step()   # plans, schedules and code objects load outside the recorded steps
     # warm-up with every kernel timed, to find the dominant kernel family
     h.timing_enable("")
     for _ in range(max(warmup, 1)):
@@ -292,6 +301,9 @@ def main():
     ap.add_argument("--no-param-shift", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--geometry", type=str, default="", metavar="R,W",
+                    help="run the fused passes with this tile geometry instead of autotuning "
+                         "(for profiling a fixed kernel instance)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device twice (a plain copy kernel of known "
                          "size, against which hardware byte counters are scaled)")
@@ -351,7 +363,9 @@ def main():
         name = prob.name
         S = (16.0 if main_dt == "c128" else 8.0) * (1 << prob.n_qubits)
         log(f"workload {name}: n={prob.n_qubits} gates={prob.n_gates} P={prob.n_params}")
-    res = run(qsv, torch, runner, args.steps, args.warmup, graphs=not args.no_graphs)
+    geometry = tuple(int(x) for x in args.geometry.split(",")) if args.geometry else None
+    res = run(qsv, torch, runner, args.steps, args.warmup, graphs=not args.no_graphs,
+              geometry=geometry)
     log(f"{main_dt} adjoint: {res['ms_per_step']:.3f} ms/step (eager "
         f"{res['ms_per_step_eager']:.3f}), tuned {res['tuned']}")
     e_res, g_res = runner.result()
@@ -367,7 +381,8 @@ def main():
         achieved = dom["bytes_per_launch"] / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": dom["name"], "achieved": achieved,
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                "traffic": traffic_for(dom["name"], name, main_dt),
+                "traffic": traffic_for(dom["name"], name, main_dt,
+                                       res["tuned"][1:3] if res["tuned"] and res["tuned"][0] else None),
                 "bytes_per_launch": dom["bytes_per_launch"], "avg_launch_us": 1e6 * avg_s,
                 "launches_per_step": dom["launches"] / args.steps,
                 "share_of_eager_step": dom["total_ms"] / (res["ms_per_step_eager"] * args.steps),
@@ -384,6 +399,10 @@ def main():
         "grad_error": err,
         "roofline": roof,
         "eager": {"ms_per_step": res["ms_per_step_eager"]},
+        # per kernel family over the eager warm-up steps (HIP events around every launch)
+        "breakdown": [{"kernel": x["name"], "ms_per_step": x["total_ms"] / max(args.warmup, 1),
+                       "launches_per_step": x["launches"] / max(args.warmup, 1)}
+                      for x in res["warmup_stats"]],
         "execution": {"tuned_mode_r_w": res["tuned"][:3] if res["tuned"] else None},
     }
     if args.config != 4:

@@ -39,8 +39,10 @@ def load(path: str):
     L.orc_energy.argtypes = [i, P, P, i, P, i, i, P, P, P]
     L.orc_adjoint_gradient.argtypes = [i, P, P, i, P, i, i, P, P, P, P, P]
     L.orc_reference_gradient.argtypes = [i, P, P, i, P, i, i, P, P, P]
+    L.orc_adjoint_gradient_nonhermitian.argtypes = [i, P, P, i, P, i, i, P, P, P, P, P]
     for f in (L.orc_apply_circuit, L.orc_apply_derivative, L.orc_apply_pauli_sum,
-              L.orc_inner, L.orc_energy, L.orc_adjoint_gradient, L.orc_reference_gradient):
+              L.orc_inner, L.orc_energy, L.orc_adjoint_gradient, L.orc_reference_gradient,
+              L.orc_adjoint_gradient_nonhermitian):
         f.restype = i
     return L
 
@@ -156,6 +158,23 @@ def adjoint_gradient(n, gates, theta, codes, coeffs, psi_in=None, return_prods=F
     if return_prods:
         return e, grad, prods[: 2 * n_occ].view(np.complex128)
     return e, grad
+
+
+def adjoint_gradient_nonhermitian(n, gates, theta, codes, coeffs, psi_in=None):
+    """<A> and its complex gradient for A = sum c_t P_t with complex c (App. B.4): Algorithm 1
+    with complex entries run with A and with A^dag, combined as conj(g_A) + g_{A^dag}.
+    Returns (energy (complex), grad (P,) complex)."""
+    c = np.asarray(coeffs, dtype=np.complex128).reshape(-1)
+    cre = np.ascontiguousarray(c.real)
+    cim = np.ascontiguousarray(c.imag)
+    gates, theta, codes, cre, psi_in = _prep(n, gates, theta, codes, cre, psi_in)
+    out = np.zeros(2)
+    grad = np.zeros(2 * theta.shape[0])
+    _check(lib().orc_adjoint_gradient_nonhermitian(
+        n, _ptr(psi_in), _ptr(gates), gates.shape[0], _ptr(theta), theta.shape[0],
+        codes.shape[0], _ptr(codes), _ptr(cre), _ptr(cim), _ptr(out), _ptr(grad)),
+        "adjoint_gradient_nonhermitian")
+    return complex(out[0], out[1]), grad.view(np.complex128)
 
 
 def reference_gradient(n, gates, theta, codes, coeffs, psi_in=None) -> np.ndarray:

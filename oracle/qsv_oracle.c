@@ -15,6 +15,9 @@
  *   - phase-gate and controlled-gate derivatives ................................. Appendix A
  *   - several parameters in one gate: one clone/derivative/product per parameter . Algorithm 3
  *   - repeated parameters: entries of one parameter are summed .......... App. B.2, Algorithm 4
+ *   - non-Hermitian operator A: Algorithm 1 with the complex <lambda|mu> as the entry, run once
+ *     with A and once with A^dag; d<A>/dtheta = conj(g_A) + g_{A^dag} .................. App. B.4
+ *     (read with the conjugate on the A run: <dpsi|A|psi> = conj(<psi|A^dag|dpsi>))
  * Fixed (parameter-free) gates are un-applied from phi and lambda like any other gate and give no
  * gradient entry (the recurrences of Sec. 2.2 hold for any unitary).
  *
@@ -307,6 +310,28 @@ static void apply_pauli_sum(const cplx* psi, cplx* out, cplx* tmp, int n, int n_
   }
 }
 
+/* out <- A psi for A = sum_t (cre_t + i cim_t) P_t, the complex-weighted sum of App. B.4 (Pauli
+   strings as above; with cim = NULL the weights are real). */
+static void apply_pauli_sum_complex(const cplx* psi, cplx* out, cplx* tmp, int n, int n_terms,
+                                    const uint8_t* codes, const double* cre, const double* cim) {
+  const int64_t dim = (int64_t)1 << n;
+  memset(out, 0, sizeof(cplx) * dim);
+  for (int t = 0; t < n_terms; ++t) {
+    clone(tmp, psi, n);
+    for (int q = 0; q < n; ++q) {
+      int code = codes[(int64_t)t * n + q];
+      if (code == 0) continue;
+      cplx p2[2][2], m[4][4] = {{0}};
+      pauli(code, p2);
+      m[0][0] = p2[0][0]; m[0][1] = p2[0][1]; m[1][0] = p2[1][0]; m[1][1] = p2[1][1];
+      apply_1q(tmp, n, q, m);
+    }
+    const cplx c = cre[t] + I * (cim ? cim[t] : 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < dim; ++j) out[j] += c * tmp[j];
+  }
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Validation                                                                                 */
 /* ------------------------------------------------------------------------------------------ */
@@ -447,6 +472,68 @@ int orc_adjoint_gradient(int n, const cplx* in, const orc_gate* gates, int n_gat
   }
   free(lam); free(phi); free(mu);
   return ORC_OK;
+}
+
+/* Algorithm 1 with operator B = sum (cre + i sign*cim) P and the complex <lambda|mu> of every
+   occurrence as its entry (App. B.4: line 9 without 2 Re), summed per parameter into z[p]
+   (n_theta complex values). Returns <psi|B|psi> in *e. */
+static int adjoint_complex_entries(int n, const cplx* in, const orc_gate* gates, int n_gates,
+                                   const double* theta, int n_theta, int n_terms,
+                                   const uint8_t* codes, const double* cre, const double* cim,
+                                   double sign, cplx* z, cplx* e) {
+  cplx *lam = new_state(n), *phi = new_state(n), *mu = new_state(n);
+  double* cb = (double*)malloc(sizeof(double) * (n_terms ? n_terms : 1));
+  if (!lam || !phi || !mu || !cb) { free(lam); free(phi); free(mu); free(cb); return ORC_ENOMEM; }
+  for (int t = 0; t < n_terms; ++t) cb[t] = sign * cim[t];
+  for (int p = 0; p < n_theta; ++p) z[p] = 0;
+  set_input(lam, in, n);                                      /* lambda := |in>          */
+  for (int k = 0; k < n_gates; ++k) apply_gate(lam, n, &gates[k], theta, 0);
+  clone(phi, lam, n);                                         /* phi := lambda           */
+  apply_pauli_sum_complex(phi, lam, mu, n, n_terms, codes, cre, cb); /* lambda <- B lambda */
+  *e = inner(phi, lam, n);
+  for (int k = n_gates - 1; k >= 0; --k) {
+    const orc_gate* g = &gates[k];
+    apply_gate(phi, n, g, theta, 1);                          /* phi <- U_i^dag phi      */
+    for (int j = 0; j < gate_nparams(g->kind); ++j) {
+      clone(mu, phi, n);
+      apply_derivative(mu, n, g, theta, j);                   /* mu <- dU_i/dtheta phi   */
+      z[g->p[j]] += inner(lam, mu, n);                        /* <lambda|mu>, complex    */
+    }
+    if (k > 0) apply_gate(lam, n, g, theta, 1);               /* lambda <- U_i^dag lambda */
+  }
+  free(lam); free(phi); free(mu); free(cb);
+  return ORC_OK;
+}
+
+/* The expectation <A> = <psi|A|psi> of a non-Hermitian A = sum (cre + i cim) P and its complex
+   gradient (App. B.4): g_B[p] = sum <lambda|mu> of Algorithm 1 run with operator B; then
+   d<A>/dtheta_p = conj(g_A[p]) + g_{A^dag}[p]. energy = (Re, Im); grad = n_theta (Re, Im) pairs. */
+int orc_adjoint_gradient_nonhermitian(int n, const cplx* in, const orc_gate* gates, int n_gates,
+                                      const double* theta, int n_theta, int n_terms,
+                                      const uint8_t* codes, const double* cre, const double* cim,
+                                      double* energy, double* grad) {
+  if (check_inputs(n, gates, n_gates, n_theta, n_terms, codes, cre)) return ORC_EINVAL;
+  if (n_terms && !cim) return ORC_EINVAL;
+  cplx *za = (cplx*)malloc(sizeof(cplx) * (n_theta ? n_theta : 1));
+  cplx *zd = (cplx*)malloc(sizeof(cplx) * (n_theta ? n_theta : 1));
+  if (!za || !zd) { free(za); free(zd); return ORC_ENOMEM; }
+  cplx ea, ed;
+  int rc = adjoint_complex_entries(n, in, gates, n_gates, theta, n_theta, n_terms, codes, cre,
+                                   cim, 1.0, za, &ea);                   /* run with A     */
+  if (!rc)
+    rc = adjoint_complex_entries(n, in, gates, n_gates, theta, n_theta, n_terms, codes, cre,
+                                 cim, -1.0, zd, &ed);                    /* run with A^dag */
+  if (!rc) {
+    energy[0] = creal(ea);
+    energy[1] = cimag(ea);
+    for (int p = 0; p < n_theta; ++p) {
+      const cplx d = conj(za[p]) + zd[p];
+      grad[2 * p] = creal(d);
+      grad[2 * p + 1] = cimag(d);
+    }
+  }
+  free(za); free(zd);
+  return rc;
 }
 
 /* Algorithm 2, the reference gradient: for every parameter occurrence, re-simulate

@@ -10,6 +10,7 @@ import subprocess
 
 import pytest
 
+import test_nonhermitian_cpu as nh
 import test_oracle_pins as pins
 from oracle import build as obuild
 from oracle import oracle as O
@@ -62,6 +63,12 @@ MUTANTS = [
      "if (d) m[1][1] = cexp(I * th[0]);"),
     ("inner product off by one", "for (int64_t i = 0; i < len; ++i) s += conj(a[i]) * b[i];",
      "for (int64_t i = 0; i + 1 < len; ++i) s += conj(a[i]) * b[i];"),
+    ("non-Hermitian: conjugate on the A^dag run (the literal App. B.4 rule)",
+     "const cplx d = conj(za[p]) + zd[p];", "const cplx d = za[p] + conj(zd[p]);"),
+    ("non-Hermitian: second run with A instead of A^dag",
+     "cim, -1.0, zd, &ed);", "cim, 1.0, zd, &ed);"),
+    ("non-Hermitian: imaginary coefficients dropped",
+     "const cplx c = cre[t] + I * (cim ? cim[t] : 0.0);", "const cplx c = cre[t];"),
 ]
 
 
@@ -82,6 +89,8 @@ def _pin_suite():
         suite.append((pins.test_algorithms_vs_dense, dict(seed=seed)))
     suite.append((pins.test_repeated_parameters_sum, {}))
     suite.append((pins.test_hermitian_energy_is_real, {}))
+    suite.append((nh.test_worked_example_rx_under_lowering, {}))
+    suite.append((nh.test_linear_in_the_operator, dict(seed=0)))
     return suite
 
 

@@ -212,6 +212,21 @@ qsv_status qsv_reference_gradient(qsv_state* s, const qsv_gate* gates, int32_t n
                                   const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
                                   double* d_energy, double* d_grad);
 
+/* Non-Hermitian operator A = sum_t (A->coeffs[t] + i coeffs_im[t]) P_t (App. B.4): the complex
+   expectation <A> = <psi|A|psi>, psi = U |in>, and its complex gradient. Algorithm 1 runs twice
+   with the complex <lambda|mu> as the entry of each occurrence: once with A (entries g_A) and
+   once with A^dag = sum conj(c_t) P_t (entries g_{A^dag}); d<A>/dtheta_p = conj(g_A[p]) +
+   g_{A^dag}[p]. (The appendix conjugates the A^dag run instead, which gives the conjugate of the
+   derivative; here the conjugate is on the A run, since <dpsi|A|psi> = conj(<psi|A^dag|dpsi>).)
+   coeffs_im: host float64[A->n_terms]. d_energy: device float64[2] = (Re, Im). d_grad: device
+   float64[2 * n_theta], (Re, Im) per parameter. Runs the fused passes (the handle's geometry, or
+   the automatic one if the handle is set to gate-granular). Real coeffs_im = 0 reproduces
+   qsv_adjoint_gradient with zero imaginary parts. */
+qsv_status qsv_adjoint_gradient_nonhermitian(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
+                                             const double* d_theta, int32_t n_theta,
+                                             const qsv_pauli_sum* A, const double* coeffs_im,
+                                             double* d_energy, double* d_grad);
+
 /* ---- graphs and tuning ------------------------------------------------------------------- */
 
 /* on != 0: qsv_adjoint_gradient and qsv_adjoint_gradient_batched capture their launch sequence

@@ -150,9 +150,10 @@ template <typename R>
 hipError_t launch_fused_forward(const PassItem* d_items, int n_items, int64_t total, int64_t chunk,
                                 int r, int w, bool general, int grid, hipStream_t st);
 
+// cplx: complex entries <lambda|mu> (non-Hermitian operators); runs the general instance.
 template <typename R>
 hipError_t launch_fused_backward(const PassItem* d_items, int n_items, int64_t total,
                                  int64_t chunk, int r, int w, bool general, int grid,
-                                 hipStream_t st);
+                                 hipStream_t st, bool cplx = false);
 
 }  // namespace qsv

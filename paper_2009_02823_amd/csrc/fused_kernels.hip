@@ -674,11 +674,13 @@ __device__ __forceinline__ void apply_derivative(const FusedOp& op, const GateRe
   }
 }
 
-// Re <l|D_j f> for the explicit derivative matrices of a general op (f already un-applied).
+// <l|D_j f> for the explicit derivative matrices of a general op (f already un-applied): the
+// real parts in out, the imaginary parts in out_im when it is given (complex entries).
 template <typename R, int RB>
 __device__ __forceinline__ void general_products(const FusedOp& op, const GateRec* rec,
                                                  const cx<R>* f, const cx<R>* l,
-                                                 const Layout<RB>& L, double* out) {
+                                                 const Layout<RB>& L, double* out,
+                                                 double* out_im) {
   constexpr int NA = 1 << RB;
   cx<R> mu[NA];
 #pragma unroll
@@ -687,11 +689,69 @@ __device__ __forceinline__ void general_products(const FusedOp& op, const GateRe
 #pragma unroll
     for (int ri = 0; ri < NA; ++ri) mu[ri] = f[ri];
     apply_derivative<R, RB>(op, rec, j, mu, L);
-    double s = 0;
+    double s = 0, si = 0;
 #pragma unroll
-    for (int ri = 0; ri < NA; ++ri) s += re_cm(l[ri].r, l[ri].i, mu[ri].r, mu[ri].i);
+    for (int ri = 0; ri < NA; ++ri) {
+      s += re_cm(l[ri].r, l[ri].i, mu[ri].r, mu[ri].i);
+      if (out_im) si += im_cm(l[ri].r, l[ri].i, mu[ri].r, mu[ri].i);
+    }
     out[j] = s;
+    if (out_im) out_im[j] = si;
   }
+}
+
+// Re <lambda|G|phi> of a lean rotation on register position K (G = Y, X or Z), all indices
+// compile-time.
+template <typename R, int NA, int K>
+__device__ __forceinline__ double re_w_k(int type, const cx<R>* f, const cx<R>* l) {
+  double t[NA / 2];
+  int j = 0;
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    if (type == FOP_RY)  // Y f = (-i f1, i f0): Re w = -Im(conj(l1) f0 - conj(l0) f1)
+      t[j++] = im_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i) - im_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i);
+    else if (type == FOP_RX)  // X f = (f1, f0)
+      t[j++] = re_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i) + re_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i);
+    else  // Z f = (-1)^bit f
+      t[j++] = re_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i) - re_cm(l[rj].r, l[rj].i, f[rj].r, f[rj].i);
+  }
+  return tree_sum<NA / 2>(t);
+}
+
+template <typename R, int RB, int K = 0>
+__device__ __forceinline__ double re_w_at(int type, int k, const cx<R>* f, const cx<R>* l) {
+  if constexpr (K < RB) {
+    if (k == K) return re_w_k<R, 1 << RB, K>(type, f, l);
+    return re_w_at<R, RB, K + 1>(type, k, f, l);
+  } else {
+    return 0.0;
+  }
+}
+
+// Im <lambda|dR phi'> of a lean rotation (complex entries, App. B.4), from the states before
+// the un-application: with w = <lambda|G|phi>, <lambda|dR phi'> = -(i/2) w, so its imaginary
+// part is -Re(w)/2 (its real part, Im(w)/2, is the lean product).
+template <typename R, int RB>
+__device__ __forceinline__ double lean_product_im(const FusedOp& op, const cx<R>* f,
+                                                  const cx<R>* l, uint32_t tdep) {
+  constexpr int NA = 1 << RB;
+  double re_w = 0;
+  if (op.type == FOP_RY || op.type == FOP_RX) {
+    re_w = re_w_at<R, RB>(op.type, op.k0, f, l);
+  } else if (op.type == FOP_RZ) {
+    if (op.flags & FOPF_S0_REG) {
+      re_w = re_w_at<R, RB>(FOP_RZ, op.ks0, f, l);
+    } else {
+      double t[NA];
+#pragma unroll
+      for (int ri = 0; ri < NA; ++ri) t[ri] = re_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i);
+      re_w = tree_sum<NA>(t);
+      if (thread_bit(tdep, op.s0)) re_w = -re_w;
+    }
+  }
+  return -0.5 * re_w;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -973,15 +1033,18 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
   }
 }
 
+// cplx (general instance only): complex entries <lambda|mu> (App. B.4); partials hold (Re, Im).
 template <typename R, int RB, int W, bool GEN>
 __global__ void __launch_bounds__(1 << W)
-k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64_t chunk) {
+k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64_t chunk,
+           int cplx) {
   using G = Geometry<RB, W>;
   using V = typename Vec2<R>::T;
   __shared__ V lds[2 << G::T];
   __shared__ OpStage sops[kMaxOpsPerPass + 1];
   __shared__ PhaseDesc sph[kMaxPhasesPerPass];
   __shared__ double wacc[kMaxSlotsPerPass][G::NW];
+  __shared__ double wacc_im[GEN ? kMaxSlotsPerPass : 1][G::NW];
   const uint32_t tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   int64_t g0 = (int64_t)blockIdx.x * chunk;
@@ -1003,7 +1066,8 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     const bool phantom = I.pd.tile[G::T - 1] < 0;  // phantom bits are the top tile bits
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
     // lane j of every wave accumulates product slot j over the wave's share of the tiles
-    double acc = 0.0;
+    double acc = 0.0, acc_im = 0.0;
+    const bool cx_entries = GEN && cplx;
     for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
       const uint64_t ob = obase | gthr;
       cx<R> f[G::NA], l[G::NA];
@@ -1047,12 +1111,13 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           nraw = staged_words(sops, k + 1);
           ncs = staged_cs(sops, k + 1);
           const GateRec* rec = I.recs + op.gate;
-          double prod[3] = {0, 0, 0};
+          double prod[3] = {0, 0, 0}, prod_im[3] = {0, 0, 0};
           if (GEN && op.type >= FOP_FIRST_GENERAL) {
             apply_general<R, RB, true>(op, rec, f, cur);
-            if (op.np) general_products<R, RB>(op, rec, f, l, cur, prod);
+            if (op.np) general_products<R, RB>(op, rec, f, l, cur, prod, cx_entries ? prod_im : nullptr);
             apply_general<R, RB, true>(op, rec, l, cur);
           } else {
+            if (cx_entries && op.np) prod_im[0] = lean_product_im<R, RB>(op, f, l, cur.tdep);
             prod[0] = lean_step<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, f, l, cur.tdep);
           }
 #pragma unroll
@@ -1060,6 +1125,10 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
             if (j >= op.np) break;
             const double s = lane63_value(wave_total_lane63(prod[j]));
             acc += lane == op.lslot + j ? s : 0.0;
+            if (cx_entries) {
+              const double si = lane63_value(wave_total_lane63(prod_im[j]));
+              acc_im += lane == op.lslot + j ? si : 0.0;
+            }
           }
         }
       }
@@ -1081,13 +1150,17 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
       }
     }
     wacc[lane][wave] = acc;
+    if (cx_entries) wacc_im[lane][wave] = acc_im;
     lds_barrier();
     const int col = (int)blockIdx.x - I.first_wg;
     for (int j = tid; j < I.pd.n_slots; j += G::NT) {
-      double s = 0;
+      double s = 0, si = 0;
 #pragma unroll
-      for (int w = 0; w < G::NW; ++w) s += wacc[j][w];
-      I.partials[(size_t)j * I.nb + col] = make_double2(s, 0.0);
+      for (int w = 0; w < G::NW; ++w) {
+        s += wacc[j][w];
+        if (cx_entries) si += wacc_im[j][w];
+      }
+      I.partials[(size_t)j * I.nb + col] = make_double2(s, si);
     }
     __threadfence_block();  // see k_pass_fwd
     lds_barrier();  // wacc and the staged tables are rewritten for the next item
@@ -1133,15 +1206,15 @@ hipError_t launch_fused_forward(const PassItem* d_items, int n_items, int64_t to
 template <typename R>
 hipError_t launch_fused_backward(const PassItem* d_items, int n_items, int64_t total,
                                  int64_t chunk, int r, int w, bool general, int grid,
-                                 hipStream_t st) {
+                                 hipStream_t st, bool cplx) {
 #define X(RR, RB, WW)                                                                          \
   if (r == RB && w == WW) {                                                                    \
-    if (general)                                                                               \
+    if (general || cplx)                                                                       \
       hipLaunchKernelGGL((k_pass_bwd<RR, RB, WW, true>), dim3(grid), dim3(1 << WW), 0, st,     \
-                         d_items, n_items, total, chunk);                                      \
+                         d_items, n_items, total, chunk, cplx ? 1 : 0);                        \
     else                                                                                       \
       hipLaunchKernelGGL((k_pass_bwd<RR, RB, WW, false>), dim3(grid), dim3(1 << WW), 0, st,    \
-                         d_items, n_items, total, chunk);                                      \
+                         d_items, n_items, total, chunk, 0);                                   \
     return hipGetLastError();                                                                  \
   }
   QSV_FUSED_CASES(X, R)
@@ -1156,8 +1229,8 @@ template hipError_t launch_fused_forward<double>(const PassItem*, int, int64_t, 
 template hipError_t launch_fused_forward<float>(const PassItem*, int, int64_t, int64_t, int, int,
                                                 bool, int, hipStream_t);
 template hipError_t launch_fused_backward<double>(const PassItem*, int, int64_t, int64_t, int,
-                                                  int, bool, int, hipStream_t);
+                                                  int, bool, int, hipStream_t, bool);
 template hipError_t launch_fused_backward<float>(const PassItem*, int, int64_t, int64_t, int, int,
-                                                 bool, int, hipStream_t);
+                                                 bool, int, hipStream_t, bool);
 
 }  // namespace qsv

@@ -181,6 +181,8 @@ struct FusedPlan {
   // workgroup walks the passes in order (items with consecutive tile indices).
   DevBuf d_seq_fwd_phi, d_seq_fwd_state, d_seq_bwd;
   bool seq_gen_fwd = false, seq_gen_bwd = false;
+  // non-Hermitian operators: the first sweep's partials, kept while the second sweep runs
+  DevBuf partials_a, d_final_a;
 };
 
 // Reference-gradient (Algorithm 2) tables of one circuit for one tile geometry: for every
@@ -407,11 +409,18 @@ static qsv_status get_plan(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
   return QSV_OK;
 }
 
-static qsv_status get_pauli(qsv_state* s, const qsv_pauli_sum* H, PauliPlan** out) {
+// coeffs_im (may be NULL): imaginary parts of the weights, taken times im_sign (-1 gives the
+// adjoint of a non-Hermitian sum, the Pauli strings being Hermitian).
+static qsv_status get_pauli_ex(qsv_state* s, const qsv_pauli_sum* H, const double* coeffs_im,
+                               double im_sign, PauliPlan** out) {
   const int n = s->n;
   uint64_t h = fnv1a(H->codes, (size_t)H->n_terms * n);
   h = fnv1a(H->coeffs, sizeof(double) * H->n_terms, h);
   h = fnv1a(&H->n_terms, sizeof H->n_terms, h);
+  if (coeffs_im) {
+    h = fnv1a(coeffs_im, sizeof(double) * H->n_terms, h ^ 0x1a5ull);
+    h = fnv1a(&im_sign, sizeof im_sign, h);
+  }
   auto it = s->paulis.find(h);
   if (it != s->paulis.end()) {
     *out = it->second.get();
@@ -435,8 +444,9 @@ static qsv_status get_pauli(qsv_state* s, const qsv_pauli_sum* H, PauliPlan** ou
       if (c == 2) ++ny;
     }
     static const double ire[4] = {1, 0, -1, 0}, iim[4] = {0, 1, 0, -1};
-    const double c = H->coeffs[t];
-    PauliTerm term{z, c * ire[ny & 3], c * iim[ny & 3]};
+    const double c = H->coeffs[t], ci = coeffs_im ? im_sign * coeffs_im[t] : 0.0;
+    // (c + i ci) i^{nY}
+    PauliTerm term{z, c * ire[ny & 3] - ci * iim[ny & 3], c * iim[ny & 3] + ci * ire[ny & 3]};
     size_t g = 0;
     while (g < xs.size() && xs[g] != x) ++g;
     if (g == xs.size()) {
@@ -463,6 +473,10 @@ static qsv_status get_pauli(qsv_state* s, const qsv_pauli_sum* H, PauliPlan** ou
   *out = p.get();
   s->paulis[h] = std::move(p);
   return QSV_OK;
+}
+
+static qsv_status get_pauli(qsv_state* s, const qsv_pauli_sum* H, PauliPlan** out) {
+  return get_pauli_ex(s, H, nullptr, 1.0, out);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -871,7 +885,8 @@ static qsv_status forward(qsv_state* s, Plan* p, const void* src, void* dst) {
 // The reverse sweep of Algorithm 1 over (phi, lambda) = the workspace; *final_desc receives the
 // descriptor table the final reduction reads the partials with.
 template <typename R>
-static qsv_status backward(qsv_state* s, Plan* p, const FinalDesc** final_desc) {
+static qsv_status backward(qsv_state* s, Plan* p, const FinalDesc** final_desc,
+                          bool cplx = false) {
   const double S = state_bytes_d(s);
   const hipStream_t st = s->stream;
   const int n = s->n;
@@ -887,14 +902,14 @@ static qsv_status backward(qsv_state* s, Plan* p, const FinalDesc** final_desc) 
       const int K = (int)sc.passes.size();
       return timed(s, "k_pass_bwd", 4 * S * K, [&] {
         return launch_fused_backward<R>(fp->d_seq_bwd.as<PassItem>(), K, K, K, r, w,
-                                        fp->seq_gen_bwd, 1, st);
+                                        fp->seq_gen_bwd, 1, st, cplx);
       });
     }
     const PassItem* items = fp->d_items_bwd.as<PassItem>();
     for (size_t i = 0; i < sc.passes.size(); ++i) {
       QSV_TRY(timed(s, "k_pass_bwd", 4 * S, [&] {
         return launch_fused_backward<R>(items + i, 1, fp->tiles, fp->chunk, r, w,
-                                        sc.passes[i].general != 0, fp->grid, st);
+                                        sc.passes[i].general != 0, fp->grid, st, cplx);
       }));
     }
     *final_desc = fp->d_final.as<FinalDesc>();
@@ -1316,6 +1331,91 @@ static qsv_status param_shift_t(qsv_state* s, Plan* p, PauliPlan* hp, const doub
   }
   HIP_TRY(launch_ps_combine(d_grad, e, first, count, st));
   return QSV_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// non-Hermitian operators (App. B.4)
+// ------------------------------------------------------------------------------------------------
+template <typename R>
+static qsv_status nonherm_t(qsv_state* s, Plan* p, PauliPlan* ha, PauliPlan* hd,
+                            const double* d_theta, double* d_energy, double* d_grad) {
+  const hipStream_t st = s->stream;
+  const int nb = s->nb;
+  void* phi = s->d_work;
+  void* lam = static_cast<char*>(s->d_work) + qsv_state_bytes(s->n, s->dt);
+  QSV_TRY(s->epartials.ensure(sizeof(double2) * nb, st));
+  double2* ep = s->epartials.as<double2>();
+  int r = 0, w = 0;
+  if (!fusion_geometry(s, &r, &w)) auto_geometry(s, &r, &w);  // complex entries: fused only
+  const int saved[3] = {s->fusion_mode, s->fr, s->fw};
+  s->fusion_mode = 1;
+  s->fr = r;
+  s->fw = w;
+  FusedPlan* fp = nullptr;
+  qsv_status rc = get_fused(s, p, r, w, &fp);
+  if (rc == QSV_OK && fp->partials_a.cap < fp->partials.cap) {
+    rc = fp->partials_a.ensure(fp->partials.cap, st);
+    if (rc == QSV_OK)
+      rc = upload_final(fp->d_final_a, fp->partials_a, fp->d_occ_base, fp->d_occ_nb, p, st);
+  }
+  auto run = [&]() -> qsv_status {
+    HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
+                        p->d_recs.as<GateRec>(), st));
+    // run with A: psi in phi, lambda = A psi, <A> = <psi|A psi>, complex entries
+    QSV_TRY(forward<R>(s, p, s->d_state, phi));
+    QSV_TRY(pauli<R>(s, ha, phi, lam, ep));
+    HIP_TRY(launch_final_energy(ep, nb, d_energy, d_energy + 1, st));
+    const FinalDesc* fd = nullptr;
+    QSV_TRY(backward<R>(s, p, &fd, true));
+    HIP_TRY(hipMemcpyAsync(fp->partials_a.p, fp->partials.p, fp->partials.cap,
+                           hipMemcpyDeviceToDevice, st));
+    // run with A^dag
+    QSV_TRY(forward<R>(s, p, s->d_state, phi));
+    QSV_TRY(pauli<R>(s, hd, phi, lam, ep));
+    QSV_TRY(backward<R>(s, p, &fd, true));
+    HIP_TRY(launch_final_grad_nonherm(fp->d_final_a.as<FinalDesc>(), fd, p->n_theta, d_grad, st));
+    return QSV_OK;
+  };
+  if (rc == QSV_OK) rc = run();
+  s->fusion_mode = saved[0];
+  s->fr = saved[1];
+  s->fw = saved[2];
+  return rc;
+}
+
+extern "C" qsv_status qsv_adjoint_gradient_nonhermitian(qsv_state* s, const qsv_gate* gates,
+                                                        int32_t n_gates, const double* d_theta,
+                                                        int32_t n_theta, const qsv_pauli_sum* A,
+                                                        const double* coeffs_im,
+                                                        double* d_energy, double* d_grad) {
+  QSV_TRY(check_handle(s));
+  QSV_TRY(qsv_validate_circuit(s->n, gates, n_gates, n_theta));
+  QSV_TRY(qsv_validate_pauli_sum(s->n, A));
+  if (A->n_terms > 0 && !coeffs_im) return fail(QSV_ERR_INVALID_ARG, "coeffs_im is NULL");
+  for (int t = 0; t < A->n_terms; ++t)
+    if (!std::isfinite(coeffs_im[t]))
+      return fail(QSV_ERR_INVALID_ARG, "coeffs_im[%d] is not finite", t);
+  if (!d_energy) return fail(QSV_ERR_INVALID_ARG, "d_energy is NULL");
+  if (n_theta > 0 && !d_grad) return fail(QSV_ERR_INVALID_ARG, "d_grad is NULL");
+  Plan* p = nullptr;
+  QSV_TRY(get_plan(s, gates, n_gates, n_theta, &p));
+  QSV_TRY(check_theta(p, d_theta));
+  PauliPlan *ha = nullptr, *hd = nullptr;
+  QSV_TRY(get_pauli_ex(s, A, coeffs_im, 1.0, &ha));
+  QSV_TRY(get_pauli_ex(s, A, coeffs_im, -1.0, &hd));
+  if (p->gates.empty()) {  // <A> of |in> and an all-zero gradient
+    QSV_TRY(s->epartials.ensure(sizeof(double2) * s->nb, s->stream));
+    double2* ep = s->epartials.as<double2>();
+    if (s->dt == QSV_C128) QSV_TRY(pauli<double>(s, ha, s->d_state, nullptr, ep));
+    else QSV_TRY(pauli<float>(s, ha, s->d_state, nullptr, ep));
+    HIP_TRY(launch_final_energy(ep, s->nb, d_energy, d_energy + 1, s->stream));
+    QSV_TRY(get_gate_granular(s, p));
+    const FinalDesc* fd = p->d_gg_final.as<FinalDesc>();
+    HIP_TRY(launch_final_grad_nonherm(fd, fd, p->n_theta, d_grad, s->stream));
+    return QSV_OK;
+  }
+  return s->dt == QSV_C128 ? nonherm_t<double>(s, p, ha, hd, d_theta, d_energy, d_grad)
+                           : nonherm_t<float>(s, p, ha, hd, d_theta, d_energy, d_grad);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -55,6 +55,10 @@ struct FinalDesc {
 
 // One block per gradient entry over n_desc circuits (total_params = sum of n_theta):
 // grad[grad_off + p] = 2 Re sum over the occurrences of p of their partials, in a fixed order.
+// grad[p] = conj(Z_A[p]) + Z_{A^dag}[p] as (Re, Im) pairs, Z the complex entry sums of two sweeps
+// sharing one occurrence layout (a: with A, b: with A^dag).
+hipError_t launch_final_grad_nonherm(const FinalDesc* d_a, const FinalDesc* d_b, int n_theta,
+                                     double* d_grad, hipStream_t st);
 hipError_t launch_final_grad(const FinalDesc* d_desc, int n_desc, int64_t total_params,
                              double* d_grad, hipStream_t st);
 

@@ -584,6 +584,37 @@ k_final_grad(const FinalDesc* __restrict__ descs, int n_desc, double* grad) {
   if (threadIdx.x == 0) grad[d.grad_off + p] = 2.0 * total;
 }
 
+// Complex gradient of a non-Hermitian operator A (App. B.4) from the complex entries of the two
+// sweeps, with A (descriptor a) and A^dag (descriptor b): grad[p] = conj(Z_A[p]) + Z_{A^dag}[p],
+// Z[p] the sum of the entries of the occurrences of p. grad holds (Re, Im) pairs.
+__global__ void __launch_bounds__(kBlock)
+k_final_grad_nonherm(const FinalDesc* __restrict__ a, const FinalDesc* __restrict__ b,
+                     double* grad) {
+  const int p = blockIdx.x;
+  double2 za = make_double2(0, 0), zb = make_double2(0, 0);
+  for (int k = a->param_ptr[p]; k < a->param_ptr[p + 1]; ++k) {
+    const int o = a->occ[k];
+    const double2 sa = block_sum_range(a->partials + a->occ_base[o], a->occ_nb[o]);
+    const double2 sb = block_sum_range(b->partials + b->occ_base[o], b->occ_nb[o]);
+    za.x += sa.x;
+    za.y += sa.y;
+    zb.x += sb.x;
+    zb.y += sb.y;
+  }
+  if (threadIdx.x == 0) {
+    grad[2 * p] = za.x + zb.x;
+    grad[2 * p + 1] = zb.y - za.y;
+  }
+}
+
+hipError_t launch_final_grad_nonherm(const FinalDesc* d_a, const FinalDesc* d_b, int n_theta,
+                                     double* d_grad, hipStream_t st) {
+  if (n_theta <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_final_grad_nonherm, dim3((unsigned)n_theta), dim3(kBlock), 0, st, d_a, d_b,
+                     d_grad);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_final_energy(const double2* partials, int nb, double* energy, double* energy_im) {
   const double2 s = block_sum_range(partials, nb);

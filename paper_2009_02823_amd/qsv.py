@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
         "qsv_adjoint_gradient_batched": ([i32, P, P, P, P, P, P, P, P, P], i32),
         "qsv_param_shift_gradient": ([P, P, i32, P, i32, P, i32, i32, P], i32),
         "qsv_reference_gradient": ([P, P, i32, P, i32, P, P, P], i32),
+        "qsv_adjoint_gradient_nonhermitian": ([P, P, i32, P, i32, P, P, P, P], i32),
         "qsv_timing_enable": ([P, ctypes.c_char_p], i32),
         "qsv_timing_read": ([P, P, i32, ctypes.POINTER(i32)], i32),
         "qsv_set_fusion": ([P, i32, i32, i32], i32),
@@ -296,6 +297,23 @@ class StateVector:
                                            gr.data_ptr() if gr.numel() else None))
         del keep
         return e, gr
+
+    def adjoint_gradient_nonhermitian(self, gates, theta, codes, coeffs):
+        """(<A>, grad) for A = sum c_t P_t with complex coefficients (App. B.4) as complex128
+        device tensors (<A> has shape (1,), grad shape (P,))."""
+        torch = _torch()
+        g = as_gate_table(gates)
+        t = self._theta(theta)
+        c = np.asarray(coeffs, dtype=np.complex128).reshape(-1)
+        s, keep = pauli_struct(codes, np.ascontiguousarray(c.real), self.n)
+        cim = np.ascontiguousarray(c.imag)
+        e = torch.empty(2, dtype=torch.float64, device=self.device)
+        gr = torch.empty(2 * t.numel(), dtype=torch.float64, device=self.device)
+        check(lib().qsv_adjoint_gradient_nonhermitian(
+            self._h, g.ctypes.data, g.shape[0], t.data_ptr() if t.numel() else None, t.numel(),
+            ctypes.byref(s), cim.ctypes.data, e.data_ptr(), gr.data_ptr() if gr.numel() else None))
+        del keep
+        return torch.view_as_complex(e.view(1, 2)), torch.view_as_complex(gr.view(-1, 2))
 
     def param_shift_gradient(self, gates, theta, codes, coeffs, first=0, count=None, grad=None):
         """GPU parameter-shift entries [first, first + count) (the faithful O(P^2) baseline)."""

@@ -18,6 +18,8 @@
  *   - non-Hermitian operator A: Algorithm 1 with the complex <lambda|mu> as the entry, run once
  *     with A and once with A^dag; d<A>/dtheta = conj(g_A) + g_{A^dag} .................. App. B.4
  *     (read with the conjugate on the A run: <dpsi|A|psi> = conj(<psi|A^dag|dpsi>))
+ *   - non-unitary invertible gates: phi is un-done by M^-1, lambda by M^dag ......... App. B.3
+ *     (here the imaginary-time rotations exp(-theta G/2), G = X, Y, Z; M^-1 by the 2x2 inverse)
  * Fixed (parameter-free) gates are un-applied from phi and lambda like any other gate and give no
  * gradient entry (the recurrences of Sec. 2.2 hold for any unitary).
  *
@@ -43,7 +45,8 @@ typedef double complex cplx;
 /* qsv_gate_kind codes of the C-ABI (an interface format; repeated, not included) */
 enum {
   K_RX = 0, K_RY, K_RZ, K_H, K_X, K_Y, K_Z, K_S, K_CNOT, K_CZ,
-  K_PHASE, K_CRX, K_CRY, K_CRZ, K_RXX, K_RYY, K_RZZ, K_U3, K_T, K_SDG, K_NKINDS
+  K_PHASE, K_CRX, K_CRY, K_CRZ, K_RXX, K_RYY, K_RZZ, K_U3, K_T, K_SDG,
+  K_NRX, K_NRY, K_NRZ, K_NKINDS
 };
 
 typedef struct {
@@ -89,7 +92,7 @@ static void rotation(int dim, cplx G[4][4], double theta, int deriv, cplx out[4]
 static int gate_nparams(int kind) {
   switch (kind) {
     case K_RX: case K_RY: case K_RZ: case K_PHASE: case K_CRX: case K_CRY: case K_CRZ:
-    case K_RXX: case K_RYY: case K_RZZ:
+    case K_RXX: case K_RYY: case K_RZZ: case K_NRX: case K_NRY: case K_NRZ:
       return 1;
     case K_U3:
       return 3;
@@ -97,6 +100,8 @@ static int gate_nparams(int kind) {
       return 0;
   }
 }
+
+static int gate_unitary(int kind) { return kind != K_NRX && kind != K_NRY && kind != K_NRZ; }
 
 static int gate_nqubits(int kind) {
   switch (kind) {
@@ -121,6 +126,16 @@ static int gate_matrix(const orc_gate* g, const double* theta, int deriv, cplx m
       pauli(g->kind - K_RX + 1, P);
       cplx G[4][4] = {{P[0][0], P[0][1]}, {P[1][0], P[1][1]}};
       rotation(2, G, th[0], d, m);
+      return 1;
+    }
+    case K_NRX: case K_NRY: case K_NRZ: {
+      /* exp(-theta G/2) = cosh(theta/2) 1 - sinh(theta/2) G (G involutory): invertible, not
+         unitary; derivative sinh(theta/2)/2 1 - cosh(theta/2)/2 G = -(1/2) G M (App. B.3) */
+      pauli(g->kind - K_NRX + 1, P);
+      const double ch = cosh(0.5 * th[0]), sh = sinh(0.5 * th[0]);
+      const double ci = d ? 0.5 * sh : ch, cg = d ? -0.5 * ch : -sh;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) m[a][b] = (a == b ? ci : 0.0) + cg * P[a][b];
       return 1;
     }
     case K_H:
@@ -242,6 +257,20 @@ static void apply_gate(cplx* psi, int n, const orc_gate* g, const double* theta,
   cplx m[4][4];
   int nq = gate_matrix(g, theta, -1, m);
   if (adj) adjoint(nq == 1 ? 2 : 4, m);
+  apply_matrix(psi, n, g, nq, m);
+}
+
+/* psi <- U^-1 psi: the adjoint for unitary gates; for the non-unitary one-qubit gates the 2x2
+   inverse (1/(ad - bc)) [[d, -b], [-c, a]] of App. B.3 (Algorithm 1, the phi un-do step). */
+static void apply_gate_inverse(cplx* psi, int n, const orc_gate* g, const double* theta) {
+  cplx m[4][4];
+  int nq = gate_matrix(g, theta, -1, m);
+  if (gate_unitary(g->kind)) {
+    adjoint(nq == 1 ? 2 : 4, m);
+  } else {
+    const cplx a = m[0][0], b = m[0][1], c = m[1][0], d = m[1][1], det = a * d - b * c;
+    m[0][0] = d / det; m[0][1] = -b / det; m[1][0] = -c / det; m[1][1] = a / det;
+  }
   apply_matrix(psi, n, g, nq, m);
 }
 
@@ -459,7 +488,7 @@ int orc_adjoint_gradient(int n, const cplx* in, const orc_gate* gates, int n_gat
   int64_t occ = 0;
   for (int k = n_gates - 1; k >= 0; --k) {                    /* i = P ... 1             */
     const orc_gate* g = &gates[k];
-    apply_gate(phi, n, g, theta, 1);                          /* phi <- U_i^dag phi      */
+    apply_gate_inverse(phi, n, g, theta);                     /* phi <- U_i^-1 phi       */
     for (int j = 0; j < gate_nparams(g->kind); ++j) {         /* one pass per parameter  */
       clone(mu, phi, n);                                      /* mu := phi               */
       apply_derivative(mu, n, g, theta, j);                   /* mu <- dU_i/dtheta mu    */
@@ -493,7 +522,7 @@ static int adjoint_complex_entries(int n, const cplx* in, const orc_gate* gates,
   *e = inner(phi, lam, n);
   for (int k = n_gates - 1; k >= 0; --k) {
     const orc_gate* g = &gates[k];
-    apply_gate(phi, n, g, theta, 1);                          /* phi <- U_i^dag phi      */
+    apply_gate_inverse(phi, n, g, theta);                     /* phi <- U_i^-1 phi       */
     for (int j = 0; j < gate_nparams(g->kind); ++j) {
       clone(mu, phi, n);
       apply_derivative(mu, n, g, theta, j);                   /* mu <- dU_i/dtheta phi   */

@@ -35,12 +35,17 @@ GATE_NAMES = {
     PHASE: "PHASE", CRX: "CRX", CRY: "CRY", CRZ: "CRZ", RXX: "RXX", RYY: "RYY", RZZ: "RZZ",
     U3: "U3", T: "T", SDG: "SDG",
 }
+#: non-unitary, invertible gates (App. B.3): imaginary-time rotations exp(-theta G / 2)
+NRX, NRY, NRZ = range(20, 23)
+NONUNITARY_NAMES = {NRX: "NRX", NRY: "NRY", NRZ: "NRZ"}
+#: every kind, unitary or not
+KIND_NAMES = {**GATE_NAMES, **NONUNITARY_NAMES}
 #: number of parameters each kind takes
-N_PARAMS = {k: 0 for k in GATE_NAMES}
+N_PARAMS = {k: 0 for k in KIND_NAMES}
 N_PARAMS.update({RX: 1, RY: 1, RZ: 1, PHASE: 1, CRX: 1, CRY: 1, CRZ: 1, RXX: 1, RYY: 1, RZZ: 1,
-                 U3: 3})
+                 U3: 3, NRX: 1, NRY: 1, NRZ: 1})
 #: number of qubits each kind acts on
-N_QUBITS = {k: 1 for k in GATE_NAMES}
+N_QUBITS = {k: 1 for k in KIND_NAMES}
 N_QUBITS.update({CNOT: 2, CZ: 2, CRX: 2, CRY: 2, CRZ: 2, RXX: 2, RYY: 2, RZZ: 2})
 
 PAULI_I, PAULI_X, PAULI_Y, PAULI_Z = 0, 1, 2, 3

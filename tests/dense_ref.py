@@ -5,7 +5,7 @@ Every operator is built as a full 2^N x 2^N matrix, independently of the oracle'
 * parameterised gates are matrix exponentials of their generators (``scipy.linalg.expm``):
   R_G(theta) = expm(-i theta G / 2); the phase gate expm(i theta |1><1|); controlled rotations
   expm(-i theta |1><1| (x) G / 2); U3 as the product of exponentials
-  e^{i(f+l)/2} RZ(f) RY(t) RZ(l);
+  e^{i(f+l)/2} RZ(f) RY(t) RZ(l); the non-unitary imaginary-time rotations expm(-theta G / 2);
 * each gate is embedded into the full space by index arithmetic;
 * a Pauli string is a Kronecker product of 2x2 Paulis (qubit n-1 leftmost);
 * E(theta) = psi^dag H psi with psi = (U_G ... U_1) |in>;
@@ -59,6 +59,8 @@ def local_matrix(kind: int, th) -> np.ndarray:
     if kind in (W.RXX, W.RYY, W.RZZ):
         s = PAULIS[kind - W.RXX + 1]
         return expm(-0.5j * th[0] * np.kron(s, s))
+    if kind in (W.NRX, W.NRY, W.NRZ):  # imaginary-time rotation, not unitary
+        return expm(-0.5 * th[0] * PAULIS[kind - W.NRX + 1])
     raise ValueError(kind)
 
 

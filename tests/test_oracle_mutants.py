@@ -11,6 +11,7 @@ import subprocess
 import pytest
 
 import test_nonhermitian_cpu as nh
+import test_nonunitary_cpu as nu
 import test_oracle_pins as pins
 from oracle import build as obuild
 from oracle import oracle as O
@@ -28,8 +29,8 @@ MUTANTS = [
     ("adjoint without conjugate", "t[a][b] = conj(m[b][a]);", "t[a][b] = m[b][a];"),
     ("lambda never un-applied", "if (k > 0) apply_gate(lam, n, g, theta, 1);", "(void)0;"),
     ("lambda un-applied before the product",
-     [("    apply_gate(phi, n, g, theta, 1);                          /* phi <- U_i^dag phi      */",
-       "    apply_gate(phi, n, g, theta, 1); if (k > 0) apply_gate(lam, n, g, theta, 1);"),
+     [("    apply_gate_inverse(phi, n, g, theta);                     /* phi <- U_i^-1 phi       */",
+       "    apply_gate_inverse(phi, n, g, theta); if (k > 0) apply_gate(lam, n, g, theta, 1);"),
       ("    if (k > 0) apply_gate(lam, n, g, theta, 1);               /* lambda <- U_i^dag lambda */",
        "")], None),
     ("Pauli Y sign", "{{{0, 0}, {0, -1}}, {{0, 1}, {0, 0}}},",
@@ -46,10 +47,10 @@ MUTANTS = [
     ("one-qubit row mixed up", "psi[j | bit] = m[1][0] * a + m[1][1] * b;",
      "psi[j | bit] = m[0][1] * a + m[1][1] * b;"),
     ("derivative on phi before the undo",
-     [("    apply_gate(phi, n, g, theta, 1);                          /* phi <- U_i^dag phi      */",
+     [("    apply_gate_inverse(phi, n, g, theta);                     /* phi <- U_i^-1 phi       */",
        ""),
       ("    if (k > 0) apply_gate(lam, n, g, theta, 1);               /* lambda <- U_i^dag lambda */",
-       "    apply_gate(phi, n, g, theta, 1);\n    if (k > 0) apply_gate(lam, n, g, theta, 1);")],
+       "    apply_gate_inverse(phi, n, g, theta);\n    if (k > 0) apply_gate(lam, n, g, theta, 1);")],
      None),
     ("reference gradient re-applies U_i",
      "for (int k = i + 1; k < n_gates; ++k) apply_gate(mu, n, &gates[k], theta, 0);",
@@ -69,6 +70,11 @@ MUTANTS = [
      "cim, -1.0, zd, &ed);", "cim, 1.0, zd, &ed);"),
     ("non-Hermitian: imaginary coefficients dropped",
      "const cplx c = cre[t] + I * (cim ? cim[t] : 0.0);", "const cplx c = cre[t];"),
+    ("non-unitary: phi un-done by the adjoint", "  if (gate_unitary(g->kind)) {\n    adjoint(",
+     "  if (1) {\n    adjoint("),
+    ("non-unitary: lambda un-done by the inverse",
+     "if (k > 0) apply_gate(lam, n, g, theta, 1);", "if (k > 0) apply_gate_inverse(lam, n, g, theta);"),
+    ("non-unitary: derivative sign", "cg = d ? -0.5 * ch : -sh;", "cg = d ? 0.5 * ch : -sh;"),
 ]
 
 
@@ -91,6 +97,8 @@ def _pin_suite():
     suite.append((pins.test_hermitian_energy_is_real, {}))
     suite.append((nh.test_worked_example_rx_under_lowering, {}))
     suite.append((nh.test_linear_in_the_operator, dict(seed=0)))
+    suite.append((nu.test_closed_forms, dict(t=0.3)))
+    suite.append((nu.test_mixed_circuits_against_dense, dict(seed=0)))
     return suite
 
 

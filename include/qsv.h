@@ -79,7 +79,14 @@ typedef enum {
   QSV_U3 = 17,    /* [[c, -e^{il} s], [e^{if} s, e^{i(f+l)} c]], c = cos(t/2), s = sin(t/2),
                      parameters (t, f, l) = theta[param[0..2]]   3 parameters            */
   QSV_T = 18,     /* diag(1, e^{i pi/4}) on q0                                            */
-  QSV_SDG = 19    /* diag(1, -i) on q0                                                    */
+  QSV_SDG = 19,   /* diag(1, -i) on q0                                                    */
+  /* Non-unitary, invertible gates (paper App. B.3): imaginary-time rotations
+     M(t) = exp(-t G/2) = cosh(t/2) 1 - sinh(t/2) G. The reverse sweep un-does phi by
+     M^-1 = exp(+t G/2) and lambda by M^dag; the energy <psi|H|psi> is then not normalised.
+     The parameter-shift rule does not hold for them (qsv_param_shift_gradient rejects them). */
+  QSV_NRX = 20,   /* exp(-t X/2) on q0                             1 parameter            */
+  QSV_NRY = 21,   /* exp(-t Y/2) on q0                             1 parameter            */
+  QSV_NRZ = 22    /* exp(-t Z/2) on q0                             1 parameter            */
 } qsv_gate_kind;
 
 /* One gate of a circuit. Circuits are arrays applied in index order (U_1 first).

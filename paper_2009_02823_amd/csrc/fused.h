@@ -37,6 +37,8 @@ enum FusedOpType : uint8_t {
   FOP_CDENSE1 = 9,  // control tile bit s0, 2x2 block (rows/cols 2,3 of the 4x4) on register k0
   FOP_DIAG2 = 10,   // diagonal 4x4 on tile bits s0 (q0), s1 (q1)
   FOP_DENSE2 = 11,  // 4x4 on register positions k0 (q0), k1 (q1)
+  FOP_NDENSE1 = 12, // non-unitary 2x2 with a parameter on register position k0: phi is un-done
+                    // by the stored inverse, lambda by the adjoint
   FOP_FIRST_GENERAL = FOP_PDENSE1,
 };
 

@@ -585,11 +585,24 @@ __device__ __forceinline__ cx<R> pick_diag4(const cx<R>* d, bool b0, bool b1) {
   return sel(b0, hi, lo);
 }
 
+// ADJ: the reverse sweep's un-do, U^dag; for a non-unitary op (FOP_NDENSE1) on phi (phi_side) the
+// stored inverse instead (App. B.3).
 template <typename R, int RB, bool ADJ>
 __device__ __forceinline__ void apply_general(const FusedOp& op, const GateRec* rec, cx<R>* a,
-                                              const Layout<RB>& L) {
+                                              const Layout<RB>& L, bool phi_side = false) {
   constexpr int NA = 1 << RB;
   switch (op.type) {
+    case FOP_NDENSE1: {
+      cx<R> m00 = mat<R>(rec, 0), m01 = mat<R>(rec, 1), m10 = mat<R>(rec, 2), m11 = mat<R>(rec, 3);
+      if (ADJ && phi_side) {
+        m00 = mat<R>(rec, 8); m01 = mat<R>(rec, 9); m10 = mat<R>(rec, 10); m11 = mat<R>(rec, 11);
+      } else if (ADJ) {
+        const cx<R> t = m01;
+        m00 = conj(m00); m11 = conj(m11); m01 = conj(m10); m10 = conj(t);
+      }
+      dense1_at<R, RB, ADJ>(op.k0, a, m00, m01, m10, m11);
+      break;
+    }
     case FOP_PDENSE1: case FOP_CDENSE1: {
       const bool ctl = op.type == FOP_CDENSE1;
       const int o = ctl ? 10 : 0, st = ctl ? 4 : 2;  // 2x2 block and its row stride
@@ -641,7 +654,7 @@ __device__ __forceinline__ void apply_derivative(const FusedOp& op, const GateRe
                                                  cx<R>* mu, const Layout<RB>& L) {
   constexpr int NA = 1 << RB;
   switch (op.type) {
-    case FOP_RY: case FOP_RX: case FOP_PDENSE1: {
+    case FOP_RY: case FOP_RX: case FOP_PDENSE1: case FOP_NDENSE1: {
       const int o = 4 + 4 * j;
       dense1_at<R, RB, false>(op.k0, mu, mat<R>(rec, o), mat<R>(rec, o + 1), mat<R>(rec, o + 2),
                               mat<R>(rec, o + 3));
@@ -1113,7 +1126,7 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           const GateRec* rec = I.recs + op.gate;
           double prod[3] = {0, 0, 0}, prod_im[3] = {0, 0, 0};
           if (GEN && op.type >= FOP_FIRST_GENERAL) {
-            apply_general<R, RB, true>(op, rec, f, cur);
+            apply_general<R, RB, true>(op, rec, f, cur, true);
             if (op.np) general_products<R, RB>(op, rec, f, l, cur, prod, cx_entries ? prod_im : nullptr);
             apply_general<R, RB, true>(op, rec, l, cur);
           } else {

@@ -1584,6 +1584,10 @@ extern "C" qsv_status qsv_param_shift_gradient(qsv_state* s, const qsv_gate* gat
         return fail(QSV_ERR_UNSUPPORTED, "parameter %d is used by more than one gate",
                     g.param[j]);
   }
+  for (int32_t k = 0; k < n_gates; ++k)
+    if (!kind_unitary(gates[k].kind))
+      return fail(QSV_ERR_UNSUPPORTED,
+                  "gate %d: the parameter-shift rule does not hold for non-unitary gates", k);
   Plan* p = nullptr;
   QSV_TRY(get_plan(s, gates, n_gates, n_theta, &p));
   PauliPlan* hp = nullptr;

@@ -10,13 +10,14 @@ namespace qsv {
 
 enum Kind : int32_t {
   K_RX = 0, K_RY, K_RZ, K_H, K_X, K_Y, K_Z, K_S, K_CNOT, K_CZ,
-  K_PHASE, K_CRX, K_CRY, K_CRZ, K_RXX, K_RYY, K_RZZ, K_U3, K_T, K_SDG, K_NKINDS
+  K_PHASE, K_CRX, K_CRY, K_CRZ, K_RXX, K_RYY, K_RZZ, K_U3, K_T, K_SDG,
+  K_NRX, K_NRY, K_NRZ, K_NKINDS
 };
 
 __host__ __device__ inline int kind_nparams(int k) {
   switch (k) {
     case K_RX: case K_RY: case K_RZ: case K_PHASE: case K_CRX: case K_CRY: case K_CRZ:
-    case K_RXX: case K_RYY: case K_RZZ:
+    case K_RXX: case K_RYY: case K_RZZ: case K_NRX: case K_NRY: case K_NRZ:
       return 1;
     case K_U3:
       return 3;
@@ -35,6 +36,11 @@ __host__ __device__ inline int kind_nqubits(int k) {
   }
 }
 
+// Non-unitary (invertible) kinds: un-done by their inverse on phi, their adjoint on lambda.
+__host__ __device__ inline bool kind_unitary(int k) {
+  return k != K_NRX && k != K_NRY && k != K_NRZ;
+}
+
 // Gates whose matrix is diagonal in the computational basis (they commute with every
 // diagonal operator and act on single amplitudes).
 __host__ __device__ inline bool kind_diagonal(int k) {
@@ -48,7 +54,8 @@ struct GateDesc {
 };
 
 // Matrices of one gate at the current parameters, written on the device by the prep kernel.
-//   one-qubit kinds: m[0..3] = U (row-major 2x2), m[4 + 4j .. 7 + 4j] = dU / dtheta_j
+//   one-qubit kinds: m[0..3] = U (row-major 2x2), m[4 + 4j .. 7 + 4j] = dU / dtheta_j;
+//                    non-unitary kinds also m[8..11] = U^-1
 //   two-qubit kinds: m[0..15] = U (4x4, local index 2 bit(q0) + bit(q1)), m[16..31] = dU/dtheta
 struct GateRec {
   double2 m[32];

@@ -234,6 +234,9 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
           case K_U3:
             op.type = FOP_PDENSE1; op.k0 = (uint8_t)regpos[b0];
             break;
+          case K_NRX: case K_NRY: case K_NRZ:
+            op.type = FOP_NDENSE1; op.k0 = (uint8_t)regpos[b0];
+            break;
           case K_RZ:
             op.type = FOP_RZ; locate0(b0);
             break;

@@ -36,6 +36,18 @@ __device__ void pauli_rotation_2x2(double2* m, int g, double t, bool deriv) {
   else set2(m, make_double2(a, b), z, z, make_double2(a, -b));
 }
 
+// Imaginary-time rotation exp(-t G/2) = ch 1 - sh G (ch = cosh(t/2), sh = sinh(t/2)), G = X, Y, Z
+// (g = 1, 2, 3): which = 0 the matrix, 1 its derivative sh/2 1 - ch/2 G, 2 its inverse ch 1 + sh G.
+__device__ void imag_rotation_2x2(double2* m, int g, double t, int which) {
+  const double ch = cosh(0.5 * t), sh = sinh(0.5 * t);
+  const double a = which == 1 ? 0.5 * sh : ch;                       // identity coefficient
+  const double b = which == 0 ? -sh : which == 1 ? -0.5 * ch : sh;    // G coefficient
+  const double2 z = make_double2(0, 0);
+  if (g == 1) set2(m, make_double2(a, 0), make_double2(b, 0), make_double2(b, 0), make_double2(a, 0));
+  else if (g == 2) set2(m, make_double2(a, 0), make_double2(0, -b), make_double2(0, b), make_double2(a, 0));
+  else set2(m, make_double2(a + b, 0), z, z, make_double2(a - b, 0));
+}
+
 // Two-qubit Pauli product s(x)s (1 = XX, 2 = YY, 3 = ZZ) rotation, 4x4 row-major.
 __device__ void pauli2_rotation_4x4(double2* m, int g, double t, bool deriv) {
   double s, c;
@@ -67,6 +79,11 @@ __global__ void k_prep(const GateDesc* gates, int n_gates, const double* theta, 
     case K_RX: case K_RY: case K_RZ:
       pauli_rotation_2x2(r.m, g.kind - K_RX + 1, th[0], false);
       pauli_rotation_2x2(r.m + 4, g.kind - K_RX + 1, th[0], true);
+      break;
+    case K_NRX: case K_NRY: case K_NRZ:
+      imag_rotation_2x2(r.m, g.kind - K_NRX + 1, th[0], 0);
+      imag_rotation_2x2(r.m + 4, g.kind - K_NRX + 1, th[0], 1);
+      imag_rotation_2x2(r.m + 8, g.kind - K_NRX + 1, th[0], 2);
       break;
     case K_H: set2(r.m, make_double2(h, 0), make_double2(h, 0), make_double2(h, 0), make_double2(-h, 0)); break;
     case K_X: set2(r.m, z, one, one, z); break;
@@ -299,9 +316,14 @@ hipError_t launch_forward_gate(void* psi_, int n, const GateDesc& g, const GateR
 template <typename R, int NP>
 __global__ void __launch_bounds__(kBlock)
 k_bwd_1q(typename Vec2<R>::T* phi, typename Vec2<R>::T* lam, int n, int q, const GateRec* rec,
-         int undo_lam, double2* partial, int nb) {
+         int undo_lam, double2* partial, int nb, int inverse_rec) {
   const cx<R> u00 = mat<R>(rec, 0), u01 = mat<R>(rec, 1), u10 = mat<R>(rec, 2),
               u11 = mat<R>(rec, 3);
+  // phi is un-done by U^-1: U^dag for unitary gates, the stored inverse m[8..11] otherwise
+  const cx<R> v00 = inverse_rec ? mat<R>(rec, 8) : conj(u00);
+  const cx<R> v01 = inverse_rec ? mat<R>(rec, 9) : conj(u10);
+  const cx<R> v10 = inverse_rec ? mat<R>(rec, 10) : conj(u01);
+  const cx<R> v11 = inverse_rec ? mat<R>(rec, 11) : conj(u11);
   double2 acc[NP > 0 ? NP : 1];
 #pragma unroll
   for (int j = 0; j < (NP > 0 ? NP : 1); ++j) acc[j] = make_double2(0, 0);
@@ -310,9 +332,9 @@ k_bwd_1q(typename Vec2<R>::T* phi, typename Vec2<R>::T* lam, int n, int q, const
        g += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t i0 = insert_zero(g, q), i1 = i0 | bit;
     const cx<R> p0 = load<R>(phi, i0), p1 = load<R>(phi, i1);
-    // phi <- U^dag phi
-    const cx<R> f0 = conj(u00) * p0 + conj(u10) * p1;
-    const cx<R> f1 = conj(u01) * p0 + conj(u11) * p1;
+    // phi <- U^-1 phi
+    const cx<R> f0 = v00 * p0 + v01 * p1;
+    const cx<R> f1 = v10 * p0 + v11 * p1;
     store<R>(phi, i0, f0);
     store<R>(phi, i1, f1);
     if (NP > 0 || undo_lam) {
@@ -430,18 +452,21 @@ hipError_t launch_backward_gate(void* phi_, void* lam_, int n, const GateDesc& g
   using V = typename Vec2<R>::T;
   V* phi = static_cast<V*>(phi_);
   V* lam = static_cast<V*>(lam_);
-  const int np = kind_nparams(g.kind), ul = undo_lam ? 1 : 0;
+  const int np = kind_nparams(g.kind), ul = undo_lam ? 1 : 0, inv = kind_unitary(g.kind) ? 0 : 1;
   const dim3 grid(nb), blk(kBlock);
   if (kind_nqubits(g.kind) == 1) {
     if (kind_diagonal(g.kind)) {
       if (np) hipLaunchKernelGGL((k_bwd_diag1<R, 1>), grid, blk, 0, st, phi, lam, n, g.q0, d_rec, ul, partial, nb);
       else hipLaunchKernelGGL((k_bwd_diag1<R, 0>), grid, blk, 0, st, phi, lam, n, g.q0, d_rec, ul, partial, nb);
     } else if (np == 3) {
-      hipLaunchKernelGGL((k_bwd_1q<R, 3>), grid, blk, 0, st, phi, lam, n, g.q0, d_rec, ul, partial, nb);
+      hipLaunchKernelGGL((k_bwd_1q<R, 3>), grid, blk, 0, st, phi, lam, n, g.q0, d_rec, ul, partial, nb,
+                         inv);
     } else if (np == 1) {
-      hipLaunchKernelGGL((k_bwd_1q<R, 1>), grid, blk, 0, st, phi, lam, n, g.q0, d_rec, ul, partial, nb);
+      hipLaunchKernelGGL((k_bwd_1q<R, 1>), grid, blk, 0, st, phi, lam, n, g.q0, d_rec, ul, partial, nb,
+                         inv);
     } else {
-      hipLaunchKernelGGL((k_bwd_1q<R, 0>), grid, blk, 0, st, phi, lam, n, g.q0, d_rec, ul, partial, nb);
+      hipLaunchKernelGGL((k_bwd_1q<R, 0>), grid, blk, 0, st, phi, lam, n, g.q0, d_rec, ul, partial, nb,
+                         inv);
     }
   } else if (g.kind == K_CNOT) {
     hipLaunchKernelGGL(k_bwd_cnot<R>, grid, blk, 0, st, phi, lam, n, g.q0, g.q1, ul);

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <cstring>
 #include <map>
@@ -199,7 +200,15 @@ struct RefPlan {
 
 // A circuit lowered for the device: gate table, matrix records, and the map from parameters to
 // the reduction slots of their occurrences (in sweep order, last gate first).
+// Serial numbers of plans: a cached batch names the plans it was built from by serial, so a plan
+// freed by a cache flush and another allocated at the same address are never confused.
+static uint64_t next_plan_serial() {
+  static std::atomic<uint64_t> serial{0};
+  return ++serial;
+}
+
 struct Plan {
+  uint64_t serial = next_plan_serial();
   std::vector<GateDesc> gates;
   int n_theta = 0;
   int n_occ = 0;
@@ -214,6 +223,7 @@ struct Plan {
 };
 
 struct PauliPlan {
+  uint64_t serial = next_plan_serial();
   std::vector<PauliGroup> groups;
   std::vector<PauliTerm> terms;
   DevBuf d_groups, d_terms;
@@ -262,13 +272,22 @@ struct BatchLevel {
   bool general = false;
 };
 struct BatchPlan {
+  uint64_t serial = next_plan_serial();
   std::vector<qsv_state*> states;
+  std::vector<uint64_t> serials;  // of the circuits' plans and Pauli plans, in order
   std::vector<Plan*> plans;
+  std::vector<PauliPlan*> paulis;
   int r = 0, w = 0;
   std::vector<std::unique_ptr<BatchLevel>> fwd, bwd;
   DevBuf partials, d_occ_base, d_occ_nb, d_final;
   int64_t total_params = 0;
+  // every circuit's gates in one table (parameter indices into the flat theta) and records, so
+  // one launch prepares the whole batch; one launch applies H to every circuit
+  DevBuf d_gates_all, d_recs_all, d_jobs, partials_e;
+  int total_gates = 0;
 };
+
+static constexpr int kBatchPauliBlocks = 128;  // blocks per circuit of the batched H apply
 
 // Captured launch sequences, replayed with hipGraphLaunch when the same call repeats.
 struct GraphCache {
@@ -1041,8 +1060,10 @@ extern "C" qsv_status qsv_adjoint_gradient(qsv_state* s, const qsv_gate* gates, 
   QSV_TRY(get_pauli(s, H, &hp));
   int r = 0, w = 0;
   const bool fz = fusion_geometry(s, &r, &w);
-  const void* key_parts[5] = {p, hp, d_theta, d_energy, d_grad};
-  uint64_t key = fnv1a(key_parts, sizeof key_parts);
+  // plans are named by serial: a cache flush may reuse an address
+  const uint64_t serials[2] = {p->serial, hp->serial};
+  const void* key_parts[3] = {d_theta, d_energy, d_grad};
+  uint64_t key = fnv1a(key_parts, sizeof key_parts, fnv1a(serials, sizeof serials));
   const int geo[3] = {fz ? 1 : 0, r, w};
   key = fnv1a(geo, sizeof geo, key ^ 0xad301ull);
   return run_graph(s, key, [&] {
@@ -1069,8 +1090,9 @@ struct StreamOverride {
   }
 };
 
-static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>& plans, int B,
-                              const int64_t* theta_off, int r, int w, BatchPlan* bp) {
+static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>& plans,
+                              const std::vector<PauliPlan*>& hps, int B, const int64_t* theta_off,
+                              int r, int w, BatchPlan* bp) {
   qsv_state* s0 = states[0];
   const hipStream_t st = s0->stream;
   bp->r = r;
@@ -1082,6 +1104,35 @@ static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>
     lf = std::max(lf, fps[b]->fwd.sched.passes.size());
     lb = std::max(lb, fps[b]->bwd.sched.passes.size());
   }
+  // the batch's gate table and matrix records
+  std::vector<GateDesc> all;
+  std::vector<int64_t> gate_base(B);
+  for (int b = 0; b < B; ++b) {
+    gate_base[b] = (int64_t)all.size();
+    for (GateDesc g : plans[b]->gates) {
+      for (int j = 0; j < 3; ++j)
+        if (g.p[j] >= 0) g.p[j] += (int32_t)theta_off[b];
+      all.push_back(g);
+    }
+  }
+  bp->total_gates = (int)all.size();
+  QSV_TRY(upload_vec(bp->d_gates_all, all, st));
+  QSV_TRY(bp->d_recs_all.ensure(sizeof(GateRec) * (all.size() ? all.size() : 1), st));
+  GateRec* recs_all = bp->d_recs_all.as<GateRec>();
+  // H applied to every circuit in one launch
+  std::vector<PauliJob> jobs(B);
+  for (int b = 0; b < B; ++b) {
+    qsv_state* s = states[b];
+    jobs[b].psi = s->d_work;
+    jobs[b].out = static_cast<char*>(s->d_work) + qsv_state_bytes(s->n, s->dt);
+    jobs[b].groups = hps[b]->d_groups.as<PauliGroup>();
+    jobs[b].terms = hps[b]->d_terms.as<PauliTerm>();
+    jobs[b].n = s->n;
+    jobs[b].n_groups = (int32_t)hps[b]->groups.size();
+  }
+  QSV_TRY(upload_vec(bp->d_jobs, jobs, st));
+  QSV_TRY(bp->partials_e.ensure(sizeof(double2) * (size_t)B * kBatchPauliBlocks, st));
+  bp->paulis = hps;
   // forward levels
   for (size_t k = 0; k < lf; ++k) {
     auto L = std::make_unique<BatchLevel>();
@@ -1089,6 +1140,7 @@ static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>
     for (int b = 0; b < B; ++b) {
       if (k >= fps[b]->fwd.sched.passes.size()) continue;
       PassItem it = fps[b]->items_fwd_phi[k];
+      it.recs = recs_all + gate_base[b];
       it.tile_begin = L->total;
       L->total += fps[b]->tiles;
       L->bytes += 2.0 * (double)qsv_state_bytes(states[b]->n, states[b]->dt);
@@ -1110,6 +1162,7 @@ static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>
     for (int b = 0; b < B; ++b) {
       if (k >= fps[b]->bwd.sched.passes.size()) continue;
       PassItem it = fps[b]->items_bwd[k];
+      it.recs = recs_all + gate_base[b];
       it.tile_begin = L->total;
       L->total += fps[b]->tiles;
       L->bytes += 4.0 * (double)qsv_state_bytes(states[b]->n, states[b]->dt);
@@ -1187,22 +1240,24 @@ static qsv_status batched_t(qsv_state* const* states, int B, const std::vector<P
                             double* d_energy, double* d_grad_flat) {
   qsv_state* s0 = states[0];
   const hipStream_t st = s0->stream;
-  for (int b = 0; b < B; ++b)
-    HIP_TRY(launch_prep(plans[b]->d_gates.as<GateDesc>(), (int)plans[b]->gates.size(),
-                        d_theta_flat + theta_off[b], plans[b]->d_recs.as<GateRec>(), st));
+  (void)plans;
+  (void)hps;
+  (void)theta_off;
+  HIP_TRY(launch_prep(bp->d_gates_all.as<GateDesc>(), bp->total_gates, d_theta_flat,
+                      bp->d_recs_all.as<GateRec>(), st));
   for (auto& L : bp->fwd)
     QSV_TRY(timed(s0, "k_pass_fwd", L->bytes, [&] {
       return launch_fused_forward<R>(L->d_items.as<PassItem>(), L->n_items, L->total, L->chunk,
                                      bp->r, bp->w, L->general, L->grid, st);
     }));
-  for (int b = 0; b < B; ++b) {
-    qsv_state* s = states[b];
-    QSV_TRY(s->epartials.ensure(sizeof(double2) * s->nb, st));
-    void* phi = s->d_work;
-    void* lam = static_cast<char*>(s->d_work) + qsv_state_bytes(s->n, s->dt);
-    QSV_TRY(pauli<R>(s, hps[b], phi, lam, s->epartials.as<double2>()));
-    HIP_TRY(launch_final_energy(s->epartials.as<double2>(), s->nb, d_energy + b, nullptr, st));
-  }
+  double pauli_bytes = 0;
+  for (int b = 0; b < B; ++b) pauli_bytes += 2.0 * (double)qsv_state_bytes(states[b]->n, states[b]->dt);
+  QSV_TRY(timed(s0, "k_pauli", pauli_bytes, [&] {
+    return launch_pauli_batched<R>(bp->d_jobs.as<PauliJob>(), B, kBatchPauliBlocks,
+                                   bp->partials_e.as<double2>(), st);
+  }));
+  HIP_TRY(launch_final_energy_batched(bp->partials_e.as<double2>(), kBatchPauliBlocks, B, d_energy,
+                                      st));
   for (auto& L : bp->bwd)
     QSV_TRY(timed(s0, "k_pass_bwd", L->bytes, [&] {
       return launch_fused_backward<R>(L->d_items.as<PassItem>(), L->n_items, L->total, L->chunk,
@@ -1274,9 +1329,15 @@ extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* c
   key = fnv1a(theta_off, sizeof(int64_t) * n_batch, key);
   key = fnv1a(&r, sizeof r, key);
   key = fnv1a(&w, sizeof w, key);
+  std::vector<uint64_t> serials;
+  for (int b = 0; b < n_batch; ++b) {
+    serials.push_back(plans[b]->serial);
+    serials.push_back(hps[b]->serial);
+  }
+  key = fnv1a(serials.data(), sizeof(uint64_t) * serials.size(), key);
   BatchPlan* bp = nullptr;
   auto it = s0->batches.find(key);
-  if (it != s0->batches.end() && it->second->plans == plans &&
+  if (it != s0->batches.end() && it->second->serials == serials &&
       std::equal(it->second->states.begin(), it->second->states.end(), states)) {
     bp = it->second.get();
   } else {
@@ -1285,12 +1346,13 @@ extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* c
       s0->batches.clear();
     }
     auto nbp = std::make_unique<BatchPlan>();
-    QSV_TRY(build_batch(states, plans, n_batch, theta_off, r, w, nbp.get()));
+    QSV_TRY(build_batch(states, plans, hps, n_batch, theta_off, r, w, nbp.get()));
+    nbp->serials = serials;
     bp = nbp.get();
     s0->batches[key] = std::move(nbp);
   }
-  const void* key_parts[4] = {bp, d_theta_flat, d_energy, d_grad_flat};
-  const uint64_t gkey = fnv1a(key_parts, sizeof key_parts, key);
+  const void* key_parts[3] = {d_theta_flat, d_energy, d_grad_flat};
+  const uint64_t gkey = fnv1a(key_parts, sizeof key_parts, fnv1a(&bp->serial, sizeof bp->serial, key));
   return run_graph(
       s0, gkey,
       [&] {

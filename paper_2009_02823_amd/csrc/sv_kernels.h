@@ -63,6 +63,24 @@ hipError_t launch_final_grad(const FinalDesc* d_desc, int n_desc, int64_t total_
                              double* d_grad, hipStream_t st);
 
 // *energy = Re sum_b partials[b]; energy_im (optional) = Im.
+// One circuit of a batched H application: lambda = H psi with E partials (Algorithm 1, step 4).
+struct PauliJob {
+  const void* psi;
+  void* out;
+  const PauliGroup* groups;
+  const PauliTerm* terms;
+  int32_t n, n_groups;
+};
+
+// Every job in one launch: partials[job * blocks_per_job + block].
+template <typename R>
+hipError_t launch_pauli_batched(const PauliJob* d_jobs, int n_jobs, int blocks_per_job,
+                                double2* partials, hipStream_t st);
+
+// energy[job] = Re of the sum of the job's nb partials (one block per job).
+hipError_t launch_final_energy_batched(const double2* partials, int nb, int n_jobs,
+                                       double* d_energy, hipStream_t st);
+
 hipError_t launch_final_energy(const double2* partials, int nb, double* d_energy,
                                double* d_energy_im, hipStream_t st);
 

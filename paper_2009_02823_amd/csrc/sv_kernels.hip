@@ -511,6 +511,47 @@ k_pauli(const typename Vec2<R>::T* psi, typename Vec2<R>::T* out, int n, const P
   block_sum_store<kBlock>(e, partial + blockIdx.x);
 }
 
+// Every circuit of a batch in one launch: blockIdx.y selects the job, blockIdx.x strides over its
+// amplitudes; partials[job * gridDim.x + blockIdx.x].
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_pauli_batched(const PauliJob* __restrict__ jobs, double2* partials) {
+  const PauliJob J = jobs[blockIdx.y];
+  const typename Vec2<R>::T* psi = static_cast<const typename Vec2<R>::T*>(J.psi);
+  typename Vec2<R>::T* out = static_cast<typename Vec2<R>::T*>(J.out);
+  double2 e = make_double2(0, 0);
+  const uint64_t dim = 1ull << J.n;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < dim;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    cx<R> acc = {0, 0};
+    for (int gi = 0; gi < J.n_groups; ++gi) {
+      const PauliGroup G = J.groups[gi];
+      const uint64_t src = j ^ G.x;
+      double sr = 0, si = 0;
+      for (int t = G.t0; t < G.t1; ++t) {
+        const PauliTerm T = J.terms[t];
+        const double sg = (__popcll(src & T.z) & 1) ? -1.0 : 1.0;
+        sr += sg * T.cre;
+        si += sg * T.cim;
+      }
+      const cx<R> sv = {(R)sr, (R)si};
+      acc = acc + sv * load<R>(psi, src);
+    }
+    store<R>(out, j, acc);
+    acc_dot<R>(e, load<R>(psi, j), acc);
+  }
+  block_sum_store<kBlock>(e, partials + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+template <typename R>
+hipError_t launch_pauli_batched(const PauliJob* d_jobs, int n_jobs, int blocks_per_job,
+                                double2* partials, hipStream_t st) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pauli_batched<R>, dim3(blocks_per_job, n_jobs), dim3(kBlock), 0, st,
+                     d_jobs, partials);
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_pauli(const void* psi_, void* out_, int n, const PauliGroup* d_groups,
                         int n_groups, const PauliTerm* d_terms, double2* partial, int nb,
@@ -641,6 +682,20 @@ hipError_t launch_final_grad_nonherm(const FinalDesc* d_a, const FinalDesc* d_b,
 }
 
 __global__ void __launch_bounds__(kBlock)
+k_final_energy_batched(const double2* partials, int nb, double* energy) {
+  const double2 s = block_sum_range(partials + (size_t)blockIdx.x * nb, nb);
+  if (threadIdx.x == 0) energy[blockIdx.x] = s.x;
+}
+
+hipError_t launch_final_energy_batched(const double2* partials, int nb, int n_jobs,
+                                       double* d_energy, hipStream_t st) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_final_energy_batched, dim3(n_jobs), dim3(kBlock), 0, st, partials, nb,
+                     d_energy);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock)
 k_final_energy(const double2* partials, int nb, double* energy, double* energy_im) {
   const double2 s = block_sum_range(partials, nb);
   if (threadIdx.x == 0) {
@@ -707,6 +762,7 @@ hipError_t launch_ps_combine(double* grad, const double* e, int first, int count
                                              hipStream_t);                                         \
   template hipError_t launch_backward_gate<R>(void*, void*, int, const GateDesc&, const GateRec*,  \
                                               bool, double2*, int, hipStream_t);                   \
+  template hipError_t launch_pauli_batched<R>(const PauliJob*, int, int, double2*, hipStream_t); \
   template hipError_t launch_pauli<R>(const void*, void*, int, const PauliGroup*, int,             \
                                       const PauliTerm*, double2*, int, hipStream_t);               \
   template hipError_t launch_copy<R>(void*, const void*, int, hipStream_t);                        \

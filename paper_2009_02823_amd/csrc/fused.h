@@ -44,7 +44,14 @@ enum FusedOpType : uint8_t {
 
 // A tile bit referenced by an op (control or diagonal bit) is either a register bit of the phase
 // (flag set, register position in ks0/ks1) or a thread bit (its value is constant per thread).
-enum : uint8_t { FOPF_S0_REG = 1, FOPF_S1_REG = 2 };
+enum : uint8_t { FOPF_S0_REG = 1, FOPF_S1_REG = 2, FOPF_MACRO = 4 };
+
+// Rotation macros (see form_rotation_macros): a head flagged FOPF_MACRO, op code
+// QSV_OPC(type, QSV_V_MACRO), stands for r rotations about one axis, one per register position
+// (the head is position 0). The records of positions 1 .. r - 1 sit after the executed ops of the
+// pass, from op index k1 of the pass on. The head's np counts the products of all r
+// (consecutive local slots). Only for r <= kMaxMacroRegBits.
+constexpr int kMaxMacroRegBits = 3;
 
 struct FusedOp {
   uint8_t type;
@@ -68,6 +75,7 @@ struct FusedOp {
 #define QSV_V_REG1 48
 #define QSV_V_CTL_THREAD 48
 #define QSV_V_THREAD 63
+#define QSV_V_MACRO 32  // RX/RY/RZ: a rotation macro head
 
 struct PhaseDesc {
   int32_t op_end;                 // ops [previous op_end, op_end) of the pass
@@ -130,17 +138,20 @@ struct Schedule {
   std::vector<PhaseDesc> phases;
   std::vector<FusedOp> ops;
   std::vector<int32_t> slot_map;
-  // for inspection: gate order and pass/phase of each executed gate
+  // for inspection: gate order and pass/phase of each executed gate (order[i] is the gate of
+  // ops[i] when the schedule has no rotation macros)
   std::vector<int32_t> order, pass_of, phase_of;
   std::vector<uint64_t> tile_mask, reg_mask;
 };
 
 // Builds the schedule of `gates` taken in order `seq` (gate indices). slot_of_gate[k] is the first
-// global reduction slot of gate k (or -1); it is only used when `backward` is set.
-// Returns false (with msg) if the gates cannot be scheduled with these sizes.
+// global reduction slot of gate k (or -1); it is only used when `backward` is set. `macros`
+// allows rotation macros (off for schedules whose ops are addressed one by one, as the
+// derivative substitution of Algorithm 2 does). Returns false (with msg) if the gates cannot be
+// scheduled with these sizes.
 bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector<int>& seq,
                     const std::vector<int32_t>& slot_of_gate, bool backward, int t, int r, int w,
-                    Schedule& out, std::string* msg);
+                    Schedule& out, std::string* msg, bool macros = true);
 
 // Launchers of the fused pass kernels. Configurations (r, w) available: see fused_kernels.hip.
 bool fused_config_supported(int r, int w, bool c128);

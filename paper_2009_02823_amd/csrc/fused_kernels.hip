@@ -473,9 +473,50 @@ __device__ __forceinline__ double op_diag1_thr(const GateRec* rec, cx<R>* f, cx<
   return 0.0;
 }
 
+// Re <lambda|G|phi> of a lean rotation on register position K (G = Y, X or Z), all indices
+// compile-time.
+template <typename R, int NA, int K>
+__device__ __forceinline__ double re_w_k(int type, const cx<R>* f, const cx<R>* l) {
+  double t[NA / 2];
+  int j = 0;
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    if (type == FOP_RY)  // Y f = (-i f1, i f0): Re w = -Im(conj(l1) f0 - conj(l0) f1)
+      t[j++] = im_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i) - im_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i);
+    else if (type == FOP_RX)  // X f = (f1, f0)
+      t[j++] = re_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i) + re_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i);
+    else  // Z f = (-1)^bit f
+      t[j++] = re_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i) - re_cm(l[rj].r, l[rj].i, f[rj].r, f[rj].i);
+  }
+  return tree_sum<NA / 2>(t);
+}
+
+// A rotation macro: RB rotations about one axis, one per register position, in straight-line
+// code. Position 0 is the head (cos/sin c0, s0); the cos/sin of positions 1 .. RB - 1 are staged
+// from record `mem` of the pass on. The product of position K goes to prod[K] (reverse sweep).
+template <typename R, int RB, bool BWD, int AXIS, int K = 0>
+__device__ __forceinline__ void rot_macro_k(R c0, R s0, const OpStage* mem, cx<R>* f, cx<R>* l,
+                                            double* prod) {
+  if constexpr (K < RB) {
+    R c = c0, s = s0;
+    if constexpr (K > 0) {
+      const double2 cs = *reinterpret_cast<const double2*>(&mem[K - 1].c);
+      c = (R)cs.x;
+      s = (R)cs.y;
+    }
+    if constexpr (AXIS == FOP_RY) prod[K] = op_ry<R, RB, BWD, K>(c, s, f, l);
+    else if constexpr (AXIS == FOP_RX) prod[K] = op_rx<R, RB, BWD, K>(c, s, f, l);
+    else prod[K] = op_rz<R, RB, BWD, K>(c, s, f, l);
+    rot_macro_k<R, RB, BWD, AXIS, K + 1>(c0, s0, mem, f, l, prod);
+  }
+}
+
 // One lean op, dispatched on its op code by a single switch whose cases are all fully
 // specialised: no nested per-position branches whose joins would copy the amplitude registers.
-// Returns the op's product (reverse sweep, RX/RY/RZ; 0 otherwise).
+// The op's products (reverse sweep) go to prod[0], or prod[0 .. RB) for a rotation macro, whose
+// records (with their cos/sin) start at st.
 #define QSV_K5(T, V0, FN, ...)                                                      \
   case QSV_OPC(T, (V0) + 0): p = FN<R, RB, BWD, 0>(__VA_ARGS__); break;           \
   case QSV_OPC(T, (V0) + 1): p = FN<R, RB, BWD, 1>(__VA_ARGS__); break;           \
@@ -494,10 +535,11 @@ __device__ __forceinline__ double op_diag1_thr(const GateRec* rec, cx<R>* f, cx<
   QSV_KK1(T, 4, FN, __VA_ARGS__)
 
 template <typename R, int RB, bool BWD>
-__device__ __forceinline__ double lean_step(const FusedOp& op, R c, R s, const GateRec* rec,
-                                            cx<R>* f, cx<R>* l, uint32_t tdep) {
+__device__ __forceinline__ void lean_step(const FusedOp& op, R c, R s, const GateRec* rec,
+                                          const OpStage* sops, cx<R>* f, cx<R>* l, uint32_t tdep,
+                                          double* prod) {
   static_assert(RB <= 5, "op codes hold register positions below 5");
-  double p = 0.0;
+  double& p = prod[0];
   switch (op.opc) {
     QSV_K5(FOP_RY, 0, op_ry, c, s, f, l)
     QSV_K5(FOP_RX, 0, op_rx, c, s, f, l)
@@ -518,10 +560,21 @@ __device__ __forceinline__ double lean_step(const FusedOp& op, R c, R s, const G
     case QSV_OPC(FOP_DIAG1, QSV_V_THREAD):
       p = op_diag1_thr<R, RB, BWD>(rec, f, l, thread_bit(tdep, op.s0));
       break;
+    case QSV_OPC(FOP_RY, QSV_V_MACRO):
+      if constexpr (RB <= kMaxMacroRegBits)
+        rot_macro_k<R, RB, BWD, FOP_RY>(c, s, sops + op.k1, f, l, prod);
+      break;
+    case QSV_OPC(FOP_RX, QSV_V_MACRO):
+      if constexpr (RB <= kMaxMacroRegBits)
+        rot_macro_k<R, RB, BWD, FOP_RX>(c, s, sops + op.k1, f, l, prod);
+      break;
+    case QSV_OPC(FOP_RZ, QSV_V_MACRO):
+      if constexpr (RB <= kMaxMacroRegBits)
+        rot_macro_k<R, RB, BWD, FOP_RZ>(c, s, sops + op.k1, f, l, prod);
+      break;
     default:
       break;
   }
-  return p;
 }
 #undef QSV_K5
 #undef QSV_KK1
@@ -711,26 +764,6 @@ __device__ __forceinline__ void general_products(const FusedOp& op, const GateRe
     out[j] = s;
     if (out_im) out_im[j] = si;
   }
-}
-
-// Re <lambda|G|phi> of a lean rotation on register position K (G = Y, X or Z), all indices
-// compile-time.
-template <typename R, int NA, int K>
-__device__ __forceinline__ double re_w_k(int type, const cx<R>* f, const cx<R>* l) {
-  double t[NA / 2];
-  int j = 0;
-#pragma unroll
-  for (int ri = 0; ri < NA; ++ri) {
-    if (ri & (1 << K)) continue;
-    const int rj = ri | (1 << K);
-    if (type == FOP_RY)  // Y f = (-i f1, i f0): Re w = -Im(conj(l1) f0 - conj(l0) f1)
-      t[j++] = im_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i) - im_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i);
-    else if (type == FOP_RX)  // X f = (f1, f0)
-      t[j++] = re_cm(l[ri].r, l[ri].i, f[rj].r, f[rj].i) + re_cm(l[rj].r, l[rj].i, f[ri].r, f[ri].i);
-    else  // Z f = (-1)^bit f
-      t[j++] = re_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i) - re_cm(l[rj].r, l[rj].i, f[rj].r, f[rj].i);
-  }
-  return tree_sum<NA / 2>(t);
 }
 
 template <typename R, int RB, int K = 0>
@@ -1004,9 +1037,14 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           nraw = staged_words(sops, k + 1);
           ncs = staged_cs(sops, k + 1);
           const GateRec* rec = I.recs + op.gate;
-          if (GEN && k == I.sub_op) apply_derivative<R, RB>(op, rec, I.sub_param, a, cur);
-          else if (GEN && op.type >= FOP_FIRST_GENERAL) apply_general<R, RB, false>(op, rec, a, cur);
-          else lean_step<R, RB, false>(op, (R)cs.x, (R)cs.y, rec, a, nullptr, cur.tdep);
+          if (GEN && k == I.sub_op) {
+            apply_derivative<R, RB>(op, rec, I.sub_param, a, cur);
+          } else if (GEN && op.type >= FOP_FIRST_GENERAL) {
+            apply_general<R, RB, false>(op, rec, a, cur);
+          } else {
+            double unused[kMaxMacroRegBits];
+            lean_step<R, RB, false>(op, (R)cs.x, (R)cs.y, rec, sops, a, nullptr, cur.tdep, unused);
+          }
         }
       }
       if (!same_layout<RB>(cur, D.rb)) relayout<R, RB>(a, cur, D, lds);
@@ -1119,28 +1157,44 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           cur = nxt;
         }
         for (; k < op_end; ++k) {
-          const FusedOp op = uniform_op(nraw);
-          const double2 cs = ncs;
+          FusedOp op = uniform_op(nraw);
+          double2 cs = ncs;
           nraw = staged_words(sops, k + 1);
           ncs = staged_cs(sops, k + 1);
-          const GateRec* rec = I.recs + op.gate;
-          double prod[3] = {0, 0, 0}, prod_im[3] = {0, 0, 0};
-          if (GEN && op.type >= FOP_FIRST_GENERAL) {
-            apply_general<R, RB, true>(op, rec, f, cur, true);
-            if (op.np) general_products<R, RB>(op, rec, f, l, cur, prod, cx_entries ? prod_im : nullptr);
-            apply_general<R, RB, true>(op, rec, l, cur);
-          } else {
-            if (cx_entries && op.np) prod_im[0] = lean_product_im<R, RB>(op, f, l, cur.tdep);
-            prod[0] = lean_step<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, f, l, cur.tdep);
+          // complex entries take a rotation macro apart: its RB records run one by one (the head
+          // as the plain rotation on position 0)
+          int n_sub = 1;
+          const int mem = op.k1;
+          if (cx_entries && (op.flags & FOPF_MACRO)) {
+            n_sub = RB;
+            op.opc = QSV_OPC(op.type, 0);
+            op.np = 1;
           }
+          for (int sub = 0; sub < n_sub; ++sub) {
+            if (sub > 0) {
+              op = uniform_op(staged_words(sops, mem + sub - 1));
+              cs = staged_cs(sops, mem + sub - 1);
+            }
+            const GateRec* rec = I.recs + op.gate;
+            double prod[3] = {0, 0, 0}, prod_im[3] = {0, 0, 0};
+            if (GEN && op.type >= FOP_FIRST_GENERAL) {
+              apply_general<R, RB, true>(op, rec, f, cur, true);
+              if (op.np)
+                general_products<R, RB>(op, rec, f, l, cur, prod, cx_entries ? prod_im : nullptr);
+              apply_general<R, RB, true>(op, rec, l, cur);
+            } else {
+              if (cx_entries && op.np) prod_im[0] = lean_product_im<R, RB>(op, f, l, cur.tdep);
+              lean_step<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, sops, f, l, cur.tdep, prod);
+            }
 #pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            if (j >= op.np) break;
-            const double s = lane63_value(wave_total_lane63(prod[j]));
-            acc += lane == op.lslot + j ? s : 0.0;
-            if (cx_entries) {
-              const double si = lane63_value(wave_total_lane63(prod_im[j]));
-              acc_im += lane == op.lslot + j ? si : 0.0;
+            for (int j = 0; j < 3; ++j) {
+              if (j >= op.np) break;
+              const double s = lane63_value(wave_total_lane63(prod[j]));
+              acc += lane == op.lslot + j ? s : 0.0;
+              if (cx_entries) {
+                const double si = lane63_value(wave_total_lane63(prod_im[j]));
+                acc_im += lane == op.lslot + j ? si : 0.0;
+              }
             }
           }
         }

@@ -195,6 +195,7 @@ struct RefPlan {
   bool single = false;      // one tile covers the state: entries in parallel, a workgroup each
   int64_t per_launch = 0;   // single: entries per launch (size of the mu pool)
   int nb = 1;               // partials per entry (workgroups of its last pass)
+  FusedSchedule fwd;        // the forward schedule without rotation macros (ops one by one)
   DevBuf items, mu_pool, partials, d_occ_base, d_occ_nb, d_final;
 };
 
@@ -1494,7 +1495,18 @@ static qsv_status get_ref(qsv_state* s, Plan* p, FusedPlan* fp, RefPlan** out) {
   }
   const hipStream_t st = s->stream;
   auto rp = std::make_unique<RefPlan>();
-  const FusedSchedule& fs = fp->fwd;
+  {
+    const int G = (int)p->gates.size();
+    std::vector<int> seq(G);
+    for (int k = 0; k < G; ++k) seq[k] = k;
+    std::string msg;
+    // the derivative substitution addresses every op of the pass on its own
+    if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, false, fp->t, fp->r, fp->w,
+                        rp->fwd.sched, &msg, false))
+      return fail(QSV_ERR_INTERNAL, "forward schedule: %s", msg.c_str());
+    QSV_TRY(upload_schedule(rp->fwd, st));
+  }
+  const FusedSchedule& fs = rp->fwd;
   const Schedule& sc = fs.sched;
   const int K = (int)sc.passes.size(), G = (int)p->gates.size();
   const size_t S = qsv_state_bytes(s->n, s->dt);

@@ -78,9 +78,70 @@ static uint64_t fill_tile(uint64_t T, int n, int t) {
   return T;
 }
 
+// Rotation macros. In a run of consecutive rotations about the same axis (RY, RX, or RZ) every
+// op commutes with every other (and with the others' generators), so the run may execute in any
+// order with the same products. When the run holds a rotation on each of the r register
+// positions, the first such rotation per position is moved to the front of the run in position
+// order and the first of them is flagged as a macro head: the kernel applies all r as one
+// straight-line op (one dispatch). The other r - 1 records (the kernel reads only their cos/sin)
+// are stored after the pass's executed ops, at the index the head's k1 names.
+static int rotation_axis(const FusedOp& op) {
+  if (op.type == FOP_RY) return 1;
+  if (op.type == FOP_RX) return 2;
+  if (op.type == FOP_RZ && (op.flags & FOPF_S0_REG)) return 3;
+  if (op.type == FOP_RZ) return 4;  // RZ on a thread bit: commutes with the run, not a member
+  return 0;
+}
+
+static int register_position(const FusedOp& op) {
+  return op.type == FOP_RZ ? op.ks0 : op.k0;
+}
+
+static void form_rotation_macros(std::vector<std::pair<int, FusedOp>>& ops, int r) {
+  size_t i = 0;
+  while (i < ops.size()) {
+    int axis = rotation_axis(ops[i].second);
+    if (!axis) {
+      ++i;
+      continue;
+    }
+    const bool z = axis >= 3;
+    size_t j = i;  // the run: same axis (RZ on any bit counts as one axis)
+    while (j < ops.size()) {
+      const int a = rotation_axis(ops[j].second);
+      if (!a || (a >= 3) != z || (!z && a != axis)) break;
+      ++j;
+    }
+    // as many macros as the run holds: each takes the earliest remaining rotation per position
+    std::vector<std::pair<int, FusedOp>> out;
+    std::vector<char> used(j - i, 0);
+    while (r >= 2) {
+      int pick[kMaxRegBits];
+      for (int k = 0; k < r; ++k) pick[k] = -1;
+      for (size_t t = i; t < j; ++t) {
+        if (used[t - i] || rotation_axis(ops[t].second) == 4) continue;
+        const int k = register_position(ops[t].second);
+        if (pick[k] < 0) pick[k] = (int)t;
+      }
+      bool full = true;
+      for (int k = 0; k < r; ++k) full = full && pick[k] >= 0;
+      if (!full) break;
+      for (int k = 0; k < r; ++k) {
+        out.push_back(ops[pick[k]]);
+        if (k == 0) out.back().second.flags |= FOPF_MACRO;
+        used[pick[k] - i] = 1;
+      }
+    }
+    for (size_t t = i; t < j; ++t)
+      if (!used[t - i]) out.push_back(ops[t]);
+    for (size_t t = i; t < j; ++t) ops[t] = out[t - i];
+    i = j;
+  }
+}
+
 bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector<int>& seq,
                     const std::vector<int32_t>& slot_of_gate, bool backward, int t, int r, int w,
-                    Schedule& out, std::string* msg) {
+                    Schedule& out, std::string* msg, bool macros) {
   out = Schedule();
   out.t = t;
   out.r = r;
@@ -154,6 +215,9 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
     std::vector<int> prem(taken);
     std::vector<int> placed;
     int lslot = 0;
+    // rotation macros: the members after a head are stored past the executed ops of the pass
+    std::vector<FusedOp> members;
+    std::vector<std::pair<size_t, size_t>> heads;  // (op index, first member in `members`)
     // phases up to the staging limit; gates left over return to the remaining sequence (the
     // phase scan is itself a blocked scan, so they only follow gates they commute with)
     while (!prem.empty() && (int)out.phases.size() - pd.phase_begin < kMaxPhasesPerPass) {
@@ -199,6 +263,7 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
       for (int k2 = 0; k2 < r; ++k2)
         if (pd.tile[P.regbit[k2]] >= 0) rphys |= 1ull << pd.tile[P.regbit[k2]];
       out.reg_mask.push_back(rphys);
+      std::vector<std::pair<int, FusedOp>> emitted;  // (gate, op) in execution order
       for (int k : ph) {
         const GateDesc& g = gates[k];
         FusedOp op;
@@ -279,12 +344,31 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
         }
         op.opc = (uint16_t)QSV_OPC(op.type, v);
         if (op.type >= FOP_FIRST_GENERAL) pd.general = 1;
+        emitted.emplace_back(k, op);
+      }
+      if (macros && r <= kMaxMacroRegBits) form_rotation_macros(emitted, r);
+      int members_left = 0;
+      for (auto& e : emitted) {
+        const int k = e.first;
+        FusedOp& op = e.second;
+        const int np = backward ? kind_nparams(gates[k].kind) : 0;
         if (np) {
           op.lslot = (uint8_t)lslot;
           for (int j = 0; j < np; ++j) out.slot_map.push_back(slot_of_gate[k] + j);
           lslot += np;
         }
-        out.ops.push_back(op);
+        if (op.flags & FOPF_MACRO) {  // products of all r positions, consecutive local slots
+          op.np = (uint8_t)(backward ? r : 0);
+          op.opc = (uint16_t)QSV_OPC(op.type, QSV_V_MACRO);
+          heads.emplace_back(out.ops.size(), members.size());
+          out.ops.push_back(op);
+          members_left = r - 1;
+        } else if (members_left > 0) {
+          members.push_back(op);
+          --members_left;
+        } else {
+          out.ops.push_back(op);
+        }
         placed.push_back(k);
         out.order.push_back(k);
         out.pass_of.push_back(pass_id);
@@ -296,6 +380,9 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
     }
     pd.phase_end = (int32_t)out.phases.size();
     pd.n_slots = lslot;
+    const size_t n_exec = out.ops.size() - pd.op_begin;
+    for (const auto& h : heads) out.ops[h.first].k1 = (uint8_t)(n_exec + h.second);
+    out.ops.insert(out.ops.end(), members.begin(), members.end());
     pd.n_ops = (int32_t)out.ops.size() - pd.op_begin;
     out.passes.push_back(pd);
 

@@ -962,6 +962,43 @@ __device__ __forceinline__ int uniform_phase(const PhaseDesc* sph, int ph, int8_
   return (int)w0;
 }
 
+// Wave totals of four values at once: a lane-half exchange (permlane32_swap) pairs p0 with p1
+// and p2 with p3, a row exchange (permlane16_swap) leaves each row with one value's 16 partial
+// sums, and a butterfly inside the rows (quad_perm, half-row and row mirrors) puts each row's
+// total in all its lanes: row 0 holds p0's total, row 1 p2's, row 2 p1's, row 3 p3's. A fixed
+// order of additions, as in wave_total_lane63.
+__device__ __forceinline__ void swap_halves(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+  a = __hiloint2double(hi[0], lo[0]);
+  b = __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ void swap_rows(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+  a = __hiloint2double(hi[0], lo[0]);
+  b = __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double wave_totals4(double p0, double p1, double p2, double p3) {
+  swap_halves(p0, p1);  // p0: (p0 lanes 0-31 | p1 lanes 0-31), p1: (p0 lanes 32-63 | p1 lanes 32-63)
+  swap_halves(p2, p3);
+  double a = p0 + p1, b = p2 + p3;
+  swap_rows(a, b);
+  double t = a + b;
+  t += dpp_f64<0xb1, 0xf, 0xf>(t);   // quad_perm [1, 0, 3, 2]
+  t += dpp_f64<0x4e, 0xf, 0xf>(t);   // quad_perm [2, 3, 0, 1]
+  t += dpp_f64<0x141, 0xf, 0xf>(t);  // row_half_mirror
+  t += dpp_f64<0x140, 0xf, 0xf>(t);  // row_mirror
+  return t;
+}
+
+template <int LANE>
+__device__ __forceinline__ double lane_value(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), LANE);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), LANE);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double lane63_value(double v) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
@@ -1186,14 +1223,21 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
               if (cx_entries && op.np) prod_im[0] = lean_product_im<R, RB>(op, f, l, cur.tdep);
               lean_step<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, sops, f, l, cur.tdep, prod);
             }
+            if (op.np >= 2 && !cx_entries) {  // a macro's (or a U3's) products together
+              const double t = wave_totals4(prod[0], prod[1], prod[2], 0.0);
+              const double s0 = lane_value<0>(t), s1 = lane_value<32>(t), s2 = lane_value<16>(t);
+              const int j = lane - op.lslot;
+              acc += j == 0 ? s0 : j == 1 ? s1 : (j == 2 && op.np > 2) ? s2 : 0.0;
+            } else {
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-              if (j >= op.np) break;
-              const double s = lane63_value(wave_total_lane63(prod[j]));
-              acc += lane == op.lslot + j ? s : 0.0;
-              if (cx_entries) {
-                const double si = lane63_value(wave_total_lane63(prod_im[j]));
-                acc_im += lane == op.lslot + j ? si : 0.0;
+              for (int j = 0; j < 3; ++j) {
+                if (j >= op.np) break;
+                const double s = lane63_value(wave_total_lane63(prod[j]));
+                acc += lane == op.lslot + j ? s : 0.0;
+                if (cx_entries) {
+                  const double si = lane63_value(wave_total_lane63(prod_im[j]));
+                  acc_im += lane == op.lslot + j ? si : 0.0;
+                }
               }
             }
           }

@@ -207,15 +207,30 @@ __device__ __forceinline__ void rz_thr(cx<R>* a, R c, R s, bool b) {
   for (int ri = 0; ri < NA; ++ri) a[ri] = phase_mul(a[ri], c, t);
 }
 
+// Exchange two values in their registers (v_swap_b32). Written as an exchange of SSA values, a
+// swap inside one case of the op switch permutes the amplitude array at the switch join; the
+// register allocator then splits every amplitude's live range and copies all of them on every
+// op's path. The tied asm operands keep each register holding "its" array element.
+__device__ __forceinline__ void swap_inplace(double& x, double& y) {
+  int xl = __double2loint(x), xh = __double2hiint(x);
+  int yl = __double2loint(y), yh = __double2hiint(y);
+  asm("v_swap_b32 %0, %1" : "+v"(xl), "+v"(yl));
+  asm("v_swap_b32 %0, %1" : "+v"(xh), "+v"(yh));
+  x = __hiloint2double(xh, xl);
+  y = __hiloint2double(yh, yl);
+}
+__device__ __forceinline__ void swap_inplace(float& x, float& y) {
+  asm("v_swap_b32 %0, %1" : "+v"(x), "+v"(y));
+}
+
 // CNOT with control and target both register positions: swaps chosen at compile time.
 template <typename R, int NA, int KC, int KT>
 __device__ __forceinline__ void cnot_rr(cx<R>* a) {
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
     if ((ri & (1 << KT)) || !(ri & (1 << KC))) continue;
-    const cx<R> x = a[ri];
-    a[ri] = a[ri | (1 << KT)];
-    a[ri | (1 << KT)] = x;
+    swap_inplace(a[ri].r, a[ri | (1 << KT)].r);
+    swap_inplace(a[ri].i, a[ri | (1 << KT)].i);
   }
 }
 

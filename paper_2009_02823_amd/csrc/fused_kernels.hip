@@ -46,6 +46,9 @@ struct Swz<float> {  // 8-byte elements, 32 per bank row
   static __device__ __forceinline__ uint32_t f(uint32_t x) { return x ^ (((x >> 5) ^ (x >> 10)) & 31u); }
 };
 
+// s_waitcnt immediate for vmcnt(0) lgkmcnt(0) (expcnt not waited for).
+constexpr int kWaitVmLgkm = 0x0070;
+
 // Workgroup barrier for LDS traffic: waits for this wave's LDS (and scalar) operations only, so
 // global loads already issued stay in flight across it. The memory clobber keeps the compiler
 // from moving memory accesses across the barrier.
@@ -917,19 +920,23 @@ __device__ __forceinline__ void stage_pass(const PassItem& I, OpStage* sops, Pha
   const int n_ops = I.pd.n_ops, n_ph = I.pd.phase_end - I.pd.phase_begin;
   for (int i = tid; i < n_ops; i += nt) {
     // the 16-byte op record moves as one word quadruple (type in the low byte of the first)
-    const uint4 raw = reinterpret_cast<const uint4*>(I.ops + I.pd.op_begin)[i];
+    // (global-address-space reads: see load())
+    using U4 = uint32_t __attribute__((ext_vector_type(4)));
+    const U4 w = ((const QSV_GLOBAL U4*)(I.ops + I.pd.op_begin))[i];
+    const uint4 raw = make_uint4(w.x, w.y, w.z, w.w);
     const int type = (int)(raw.x & 0xffu);
     double c = 0.0, s = 0.0;
     if (type <= FOP_RZ) {  // RY m[2] = s, RX m[1] = -i s, RZ m[0] = c - i s
-      const GateRec* rec = I.recs + (int32_t)raw.w;
-      const double2 m0 = rec->m[0];
-      c = m0.x;
-      s = type == FOP_RY ? rec->m[2].x : type == FOP_RX ? -rec->m[1].y : -m0.y;
+      const QSV_GLOBAL double* m = rec_words(I.recs + (int32_t)raw.w);
+      c = m[0];
+      s = type == FOP_RY ? m[4] : type == FOP_RX ? -m[3] : -m[1];
     }
     *reinterpret_cast<uint4*>(&sops[i].op) = raw;
     *reinterpret_cast<double2*>(&sops[i].c) = make_double2(c, s);
   }
-  for (int i = tid; i < n_ph; i += nt) sph[i] = I.phases[I.pd.phase_begin + i];
+  static_assert(sizeof(PhaseDesc) == 12, "PhaseDesc moves as three words");
+  const QSV_GLOBAL uint32_t* ph = (const QSV_GLOBAL uint32_t*)(I.phases + I.pd.phase_begin);
+  for (int i = tid; i < 3 * n_ph; i += nt) reinterpret_cast<uint32_t*>(sph)[i] = ph[i];
 }
 
 static_assert(sizeof(FusedOp) == 16 && offsetof(FusedOp, s0) == 3 && offsetof(FusedOp, flags) == 7 &&
@@ -1083,6 +1090,10 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           relayout<R, RB>(a, cur, nxt, lds);
           cur = nxt;
         }
+        // every load in flight is complete before the ops: without this the compiler's wait
+        // analysis (the op loop is rotated, so its blocks are also entered from the relayout)
+        // keeps a wait on the LDS counter in every op, which also waits for the op prefetch
+        __builtin_amdgcn_s_waitcnt(kWaitVmLgkm);
         for (; k < op_end; ++k) {
           const FusedOp op = uniform_op(nraw);
           const double2 cs = ncs;
@@ -1208,6 +1219,10 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           relayout2<R, RB>(f, l, cur, nxt, lds, 1 << G::T);
           cur = nxt;
         }
+        // every load in flight is complete before the ops: without this the compiler's wait
+        // analysis (the op loop is rotated, so its blocks are also entered from the relayout)
+        // keeps a wait on the LDS counter in every op, which also waits for the op prefetch
+        __builtin_amdgcn_s_waitcnt(kWaitVmLgkm);
         for (; k < op_end; ++k) {
           FusedOp op = uniform_op(nraw);
           double2 cs = ncs;

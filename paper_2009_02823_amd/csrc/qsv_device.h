@@ -53,24 +53,35 @@ __device__ __forceinline__ cx<R> sel(bool c, cx<R> a, cx<R> b) {
   return {c ? a.r : b.r, c ? a.i : b.i};
 }
 
+// Amplitudes live in global memory (device allocations): accessed through global-address-space
+// pointers, so the compiler emits global loads and stores. Generic (flat) accesses would also
+// count against the LDS counter, and waiting for them would wait for LDS reads in flight too.
+#define QSV_GLOBAL __attribute__((address_space(1)))
+// (clang vector types: the HIP vector structs cannot be copied through such pointers)
 template <typename R>
 __device__ __forceinline__ cx<R> load(const typename Vec2<R>::T* p, uint64_t j) {
-  typename Vec2<R>::T v = p[j];
+  using E = R __attribute__((ext_vector_type(2)));
+  const E v = ((const QSV_GLOBAL E*)p)[j];
   return {v.x, v.y};
 }
 template <typename R>
 __device__ __forceinline__ void store(typename Vec2<R>::T* p, uint64_t j, cx<R> a) {
-  typename Vec2<R>::T v;
+  using E = R __attribute__((ext_vector_type(2)));
+  E v;
   v.x = a.r;
   v.y = a.i;
-  p[j] = v;
+  ((QSV_GLOBAL E*)p)[j] = v;
 }
 
 // Matrix entry k of a gate record, narrowed to the storage precision.
+// The record (32 double2 entries) read as plain doubles through a global pointer.
+__device__ __forceinline__ const QSV_GLOBAL double* rec_words(const GateRec* rec) {
+  return (const QSV_GLOBAL double*)rec;
+}
 template <typename R>
 __device__ __forceinline__ cx<R> mat(const GateRec* rec, int k) {
-  double2 d = rec->m[k];
-  return {(R)d.x, (R)d.y};
+  const QSV_GLOBAL double* d = rec_words(rec) + 2 * k;
+  return {(R)d[0], (R)d[1]};
 }
 
 // acc += conj(l) * m, evaluated in FP64 whatever the storage precision.

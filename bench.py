@@ -169,12 +169,12 @@ def grad_error(prob, energy, grad, dtype):
     if ref is None:
         return None
     e_ref, g_ref = ref
-    scale = max(float(np.max(np.abs(g_ref))), 1e-6 * float(np.abs(prob.coeffs).sum()))
+    scale = max(float(np.max(np.abs(g_ref))), 1e-5 * float(np.abs(prob.coeffs).sum()))
     d = {"max_abs_grad_err": float(np.max(np.abs(grad - g_ref))),
          "abs_energy_err": abs(energy - e_ref.real),
          "max_abs_grad_ref": float(np.max(np.abs(g_ref)))}
     d["rel_grad_err"] = d["max_abs_grad_err"] / scale
-    d["tolerance"] = "1e-10 abs" if dtype == "c128" else "2e-4 * max(max|g_oracle|, 1e-6 sum|c|)"
+    d["tolerance"] = "1e-10 abs" if dtype == "c128" else "2e-4 * max(max|g_oracle|, 1e-5 sum|c|)"
     d["ok"] = (d["max_abs_grad_err"] <= 1e-10 if dtype == "c128" else d["rel_grad_err"] <= 2e-4)
     return d
 

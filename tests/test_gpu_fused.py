@@ -48,7 +48,7 @@ def tol_check(dtype, e, g, psi, e_ref, g_ref, psi_ref, coeffs):
         assert np.max(np.abs(psi - psi_ref)) <= 1e-12
     else:
         assert abs(e - e_ref.real) <= 2e-4 * max(abs(e_ref), 1.0)
-        scale = max(np.max(np.abs(g_ref)), 1e-6 * np.abs(coeffs).sum())
+        scale = max(np.max(np.abs(g_ref)), 1e-5 * np.abs(coeffs).sum())
         assert np.max(np.abs(g - g_ref)) <= 2e-4 * scale
         assert np.max(np.abs(psi - psi_ref)) <= 2e-5
 

@@ -59,7 +59,7 @@ def test_random_circuits(Q, orc, dtype, n, geom):
         assert np.max(np.abs(g - g_ref)) <= 1e-10 * scale
     else:
         assert abs(e - e_ref) <= 2e-4 * max(abs(e_ref), 1.0)
-        scale = max(np.max(np.abs(g_ref)), 1e-6 * np.abs(c).sum())
+        scale = max(np.max(np.abs(g_ref)), 1e-5 * np.abs(c).sum())
         assert np.max(np.abs(g - g_ref)) <= 2e-4 * scale
 
 

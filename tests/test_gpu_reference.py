@@ -39,7 +39,7 @@ def check(dtype, e, g, e_ref, g_ref, coeffs):
         assert np.max(np.abs(g - g_ref)) <= 1e-10 * scale
     else:
         assert abs(e - e_ref.real) <= 2e-4 * max(abs(e_ref), 1.0)
-        scale = max(np.max(np.abs(g_ref)), 1e-6 * np.abs(coeffs).sum())
+        scale = max(np.max(np.abs(g_ref)), 1e-5 * np.abs(coeffs).sum())
         assert np.max(np.abs(g - g_ref)) <= 2e-4 * scale
 
 

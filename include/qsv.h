@@ -297,7 +297,9 @@ qsv_status qsv_get_fusion(qsv_state* s, int32_t* mode, int32_t* reg_qubits, int3
 /* Host-only description of the fused schedule of a circuit (no GPU needed): the order gates run
    in, and for each executed gate its pass and register phase; the physical-qubit masks of every
    pass's tile and every phase's register qubits. backward != 0 describes the reverse sweep (gates
-   taken from last to first). All arrays are caller-owned with n_gates entries. */
+   taken from last to first). All arrays are caller-owned with n_gates entries. n_macros counts
+   the rotation macros (runs of reg_qubits same-axis rotations, one per register qubit, that run
+   as one op; formed for reg_qubits <= 3). */
 typedef struct {
   int32_t n_passes;
   int32_t n_phases;
@@ -306,6 +308,7 @@ typedef struct {
   int32_t* phase_of;
   uint64_t* tile_mask;
   uint64_t* reg_mask;
+  int32_t n_macros;
 } qsv_schedule_info;
 
 qsv_status qsv_schedule_describe(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates,

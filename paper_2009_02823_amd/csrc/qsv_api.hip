@@ -1787,6 +1787,8 @@ extern "C" qsv_status qsv_schedule_describe(int32_t n, const qsv_gate* gates, in
   }
   for (size_t i = 0; i < sc.passes.size(); ++i) out->tile_mask[i] = sc.tile_mask[i];
   for (size_t i = 0; i < sc.phases.size(); ++i) out->reg_mask[i] = sc.reg_mask[i];
+  out->n_macros = 0;
+  for (const FusedOp& op : sc.ops) out->n_macros += (op.flags & FOPF_MACRO) ? 1 : 0;
   return QSV_OK;
 }
 

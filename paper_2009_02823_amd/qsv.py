@@ -41,7 +41,7 @@ class ScheduleInfo(ctypes.Structure):
     _fields_ = [("n_passes", ctypes.c_int32), ("n_phases", ctypes.c_int32),
                 ("order", ctypes.c_void_p), ("pass_of", ctypes.c_void_p),
                 ("phase_of", ctypes.c_void_p), ("tile_mask", ctypes.c_void_p),
-                ("reg_mask", ctypes.c_void_p)]
+                ("reg_mask", ctypes.c_void_p), ("n_macros", ctypes.c_int32)]
 
 
 class PauliSum(ctypes.Structure):
@@ -144,12 +144,13 @@ def schedule_describe(n_qubits: int, gates, backward: bool, reg_qubits: int, thr
     tile = np.zeros(max(G, 1), np.uint64)
     reg = np.zeros(max(G, 1), np.uint64)
     info = ScheduleInfo(0, 0, order.ctypes.data, pass_of.ctypes.data, phase_of.ctypes.data,
-                        tile.ctypes.data, reg.ctypes.data)
+                        tile.ctypes.data, reg.ctypes.data, 0)
     check(lib().qsv_schedule_describe(n_qubits, g.ctypes.data, G, 1 if backward else 0,
                                       reg_qubits, threads_log2, ctypes.byref(info)))
     return {"n_passes": info.n_passes, "n_phases": info.n_phases, "order": order[:G],
             "pass_of": pass_of[:G], "phase_of": phase_of[:G],
-            "tile_mask": tile[:info.n_passes], "reg_mask": reg[:info.n_phases]}
+            "tile_mask": tile[:info.n_passes], "reg_mask": reg[:info.n_phases],
+            "n_macros": info.n_macros}
 
 
 def state_bytes(n_qubits: int, dtype: str = "c128") -> int:

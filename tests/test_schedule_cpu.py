@@ -120,3 +120,49 @@ def test_pass_counts_reported():
         b = qsv.schedule_describe(n, gates, True, r, 8)
         print(f"n={n} L={L} G={gates.shape[0]} t={r + 8}: forward {f['n_passes']} passes "
               f"{f['n_phases']} phases, backward {b['n_passes']} passes {b['n_phases']} phases")
+
+
+def rotation_layer_circuit(rng, n, layers):
+    """Per layer: RX, RY and RZ on every qubit in shuffled order with two extra rotations per
+    axis, then a CNOT ladder (runs of same-axis rotations that rotation macros regroup)."""
+    rows, p = [], 0
+    for _ in range(layers):
+        for kind in (W.RX, W.RY, W.RZ):
+            for q in list(rng.permutation(n)) + list(rng.integers(0, n, size=2)):
+                rows.append(W.gate_row(kind, int(q), p0=p))
+                p += 1
+        rows += [W.gate_row(W.CNOT, q, q + 1) for q in range(n - 1)]
+    return W.circuit_table(rows), p
+
+
+@pytest.mark.parametrize("r,w", [(2, 6), (3, 6), (3, 8), (4, 8)])
+def test_rotation_macros_regroup_validly(orc, r, w):
+    """Rotation macros move same-axis rotations within a run (they commute): the schedule stays
+    valid and equivalent, macros form for r <= 3 and never for r = 4."""
+    rng = np.random.default_rng(77 + r + w)
+    n = 13
+    gates, P = rotation_layer_circuit(rng, n, 3)
+    theta = W.uniform_angles(rng, P)
+    for backward in (False, True):
+        info = check_schedule(n, gates, backward, r, w)
+        if r <= 3:
+            assert info["n_macros"] > 0
+        else:
+            assert info["n_macros"] == 0
+        order = info["order"]
+        if backward:
+            psi0 = orc.statevector(n, gates, theta)
+            a = orc.statevector(n, gates, theta, psi_in=psi0, inverse=True)
+            b = psi0.copy()
+            for k in order:
+                b = orc.statevector(n, gates[k:k + 1], theta, psi_in=b, inverse=True)
+        else:
+            a = orc.statevector(n, gates, theta)
+            b = orc.statevector(n, gates[order], theta)
+        assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_headline_schedule_forms_macros():
+    gates = W.hea_circuit(20, 20)
+    for backward in (False, True):
+        assert qsv.schedule_describe(20, gates, backward, 3, 9)["n_macros"] > 0

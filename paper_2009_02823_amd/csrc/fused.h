@@ -145,13 +145,19 @@ struct Schedule {
 };
 
 // Builds the schedule of `gates` taken in order `seq` (gate indices). slot_of_gate[k] is the first
-// global reduction slot of gate k (or -1); it is only used when `backward` is set. `macros`
+// global reduction slot of gate k (or -1); it is only used when `backward` is set. Every tile
+// holds qubits 0 .. run_qubits - 1 (see run_qubits_for). `macros`
 // allows rotation macros (off for schedules whose ops are addressed one by one, as the
 // derivative substitution of Algorithm 2 does). Returns false (with msg) if the gates cannot be
 // scheduled with these sizes.
 bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector<int>& seq,
                     const std::vector<int32_t>& slot_of_gate, bool backward, int t, int r, int w,
-                    Schedule& out, std::string* msg, bool macros = true);
+                    int run_qubits, Schedule& out, std::string* msg, bool macros = true);
+
+// Lowest qubits every tile holds, so that loads and stores move contiguous runs of one 128-byte
+// L2 line: 8 complex128 or 16 complex64 amplitudes. Fewer forced qubits leave more tile bits to
+// the scheduler (fewer passes); a shorter run would split lines between tiles.
+inline int run_qubits_for(bool c128) { return c128 ? 3 : 4; }
 
 // Launchers of the fused pass kernels. Configurations (r, w) available: see fused_kernels.hip.
 bool fused_config_supported(int r, int w, bool c128);

@@ -777,10 +777,13 @@ static qsv_status get_fused(qsv_state* s, Plan* p, int r, int w, FusedPlan** out
   std::vector<int> seq(G);
   std::string msg;
   for (int k = 0; k < G; ++k) seq[k] = k;
-  if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, false, r + w, r, w, fp->fwd.sched, &msg))
+  const int runq = run_qubits_for(s->dt == QSV_C128);
+  if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, false, r + w, r, w, runq,
+                      fp->fwd.sched, &msg))
     return fail(QSV_ERR_INTERNAL, "forward schedule: %s", msg.c_str());
   for (int k = 0; k < G; ++k) seq[k] = G - 1 - k;
-  if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, true, r + w, r, w, fp->bwd.sched, &msg))
+  if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, true, r + w, r, w, runq,
+                      fp->bwd.sched, &msg))
     return fail(QSV_ERR_INTERNAL, "backward schedule: %s", msg.c_str());
   QSV_TRY(upload_schedule(fp->fwd, st));
   QSV_TRY(upload_schedule(fp->bwd, st));
@@ -1502,7 +1505,7 @@ static qsv_status get_ref(qsv_state* s, Plan* p, FusedPlan* fp, RefPlan** out) {
     std::string msg;
     // the derivative substitution addresses every op of the pass on its own
     if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, false, fp->t, fp->r, fp->w,
-                        rp->fwd.sched, &msg, false))
+                        run_qubits_for(s->dt == QSV_C128), rp->fwd.sched, &msg, false))
       return fail(QSV_ERR_INTERNAL, "forward schedule: %s", msg.c_str());
     QSV_TRY(upload_schedule(rp->fwd, st));
   }
@@ -1753,7 +1756,8 @@ extern "C" qsv_status qsv_get_fusion(qsv_state* s, int32_t* mode, int32_t* reg_q
 
 extern "C" qsv_status qsv_schedule_describe(int32_t n, const qsv_gate* gates, int32_t n_gates,
                                             int32_t backward, int32_t reg_qubits,
-                                            int32_t threads_log2, qsv_schedule_info* out) {
+                                            int32_t threads_log2, qsv_dtype dt,
+                                            qsv_schedule_info* out) {
   QSV_TRY(qsv_validate_circuit(n, gates, n_gates, 1 << 30));
   if (!out || (n_gates > 0 && (!out->order || !out->pass_of || !out->phase_of ||
                                !out->tile_mask || !out->reg_mask)))
@@ -1775,8 +1779,9 @@ extern "C" qsv_status qsv_schedule_describe(int32_t n, const qsv_gate* gates, in
   for (int k = 0; k < n_gates; ++k) seq[k] = backward ? n_gates - 1 - k : k;
   Schedule sc;
   std::string msg;
+  if (dt != QSV_C64 && dt != QSV_C128) return fail(QSV_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
   if (!build_schedule(n, g, seq, slot, backward != 0, reg_qubits + threads_log2, reg_qubits,
-                      threads_log2, sc, &msg))
+                      threads_log2, run_qubits_for(dt == QSV_C128), sc, &msg))
     return fail(QSV_ERR_INTERNAL, "schedule: %s", msg.c_str());
   out->n_passes = (int32_t)sc.passes.size();
   out->n_phases = (int32_t)sc.phases.size();

@@ -141,7 +141,7 @@ static void form_rotation_macros(std::vector<std::pair<int, FusedOp>>& ops, int 
 
 bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector<int>& seq,
                     const std::vector<int32_t>& slot_of_gate, bool backward, int t, int r, int w,
-                    Schedule& out, std::string* msg, bool macros) {
+                    int run_qubits, Schedule& out, std::string* msg, bool macros) {
   out = Schedule();
   out.t = t;
   out.r = r;
@@ -155,7 +155,7 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
   // (their amplitudes are never loaded or stored and stay zero)
   const int tq = std::min(t, n);
   // low qubits always in the tile: contiguous runs of 2^c amplitudes per load
-  const int c = std::min(4, std::min(w, n));
+  const int c = std::min(run_qubits, std::min(w, n));
   const uint64_t low = (1ull << c) - 1;
 
   std::vector<int> rem(seq);

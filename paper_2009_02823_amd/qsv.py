@@ -87,7 +87,7 @@ def lib() -> ctypes.CDLL:
         "qsv_set_fusion": ([P, i32, i32, i32], i32),
         "qsv_get_fusion": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                            i32),
-        "qsv_schedule_describe": ([i32, P, i32, i32, i32, i32, P], i32),
+        "qsv_schedule_describe": ([i32, P, i32, i32, i32, i32, i32, P], i32),
         "qsv_set_graphs": ([P, i32], i32),
         "qsv_autotune": ([P, P, i32, P, i32, P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                           ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], i32),
@@ -134,7 +134,8 @@ def validate_pauli_sum(n_qubits: int, codes, coeffs):
     del keep
 
 
-def schedule_describe(n_qubits: int, gates, backward: bool, reg_qubits: int, threads_log2: int):
+def schedule_describe(n_qubits: int, gates, backward: bool, reg_qubits: int, threads_log2: int,
+                      dtype: str = "c128"):
     """Host-only: the fused schedule of a circuit as numpy arrays (see qsv_schedule_describe)."""
     g = as_gate_table(gates)
     G = g.shape[0]
@@ -146,7 +147,8 @@ def schedule_describe(n_qubits: int, gates, backward: bool, reg_qubits: int, thr
     info = ScheduleInfo(0, 0, order.ctypes.data, pass_of.ctypes.data, phase_of.ctypes.data,
                         tile.ctypes.data, reg.ctypes.data, 0)
     check(lib().qsv_schedule_describe(n_qubits, g.ctypes.data, G, 1 if backward else 0,
-                                      reg_qubits, threads_log2, ctypes.byref(info)))
+                                      reg_qubits, threads_log2, DTYPES[dtype],
+                                      ctypes.byref(info)))
     return {"n_passes": info.n_passes, "n_phases": info.n_phases, "order": order[:G],
             "pass_of": pass_of[:G], "phase_of": phase_of[:G],
             "tile_mask": tile[:info.n_passes], "reg_mask": reg[:info.n_phases],

@@ -18,7 +18,7 @@ namespace qsv {
 
 constexpr int kMaxTileBits = 14;
 constexpr int kMaxRegBits = 5;
-constexpr int kMaxSlotsPerPass = 64;    // one wave lane per product slot
+constexpr int kMaxSlotsPerPass = 128;   // two accumulator registers, one wave lane per slot
 constexpr int kMaxOpsPerPass = 256;     // ops of a pass are staged in LDS
 constexpr int kMaxPhasesPerPass = 64;
 

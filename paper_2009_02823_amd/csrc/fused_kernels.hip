@@ -1050,6 +1050,14 @@ __device__ __forceinline__ double lane_value(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Adds a wave total v (uniform) to product slot `slot` of the two-register accumulator whose
+// lane j holds slot j (a0) and slot 64 + j (a1).
+__device__ __forceinline__ void add_to_slot(double& a0, double& a1, int slot, int lane, double v) {
+  const double add = lane == (slot & 63) ? v : 0.0;
+  if (slot < 64) a0 += add;
+  else a1 += add;
+}
+
 __device__ __forceinline__ double lane63_value(double v) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
@@ -1186,8 +1194,12 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
   __shared__ V lds[2 << G::T];
   __shared__ OpStage sops[kMaxOpsPerPass + 1];
   __shared__ PhaseDesc sph[kMaxPhasesPerPass];
-  __shared__ double wacc[kMaxSlotsPerPass][G::NW];
-  __shared__ double wacc_im[GEN ? kMaxSlotsPerPass : 1][G::NW];
+  // per-wave slot sums, written after the item's last tile: they share the relayout buffer
+  // (every wave has passed the barrier that ends its last relayout by then)
+  static_assert(sizeof(lds) >= 2 * sizeof(double) * kMaxSlotsPerPass * G::NW,
+                "slot sums fit the relayout buffer");
+  double (*wacc)[G::NW] = reinterpret_cast<double (*)[G::NW]>(lds);
+  double (*wacc_im)[G::NW] = wacc + kMaxSlotsPerPass;
   const uint32_t tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   int64_t g0 = (int64_t)blockIdx.x * chunk;
@@ -1209,7 +1221,8 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     const bool phantom = I.pd.tile[G::T - 1] < 0;  // phantom bits are the top tile bits
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
     // lane j of every wave accumulates product slot j over the wave's share of the tiles
-    double acc = 0.0, acc_im = 0.0;
+    // lane j of acc0 holds slot j, of acc1 slot 64 + j
+    double acc0 = 0.0, acc1 = 0.0, acc0_im = 0.0, acc1_im = 0.0;
     const bool cx_entries = GEN && cplx;
     for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
       const uint64_t ob = obase | gthr;
@@ -1284,18 +1297,21 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
             }
             if (op.np >= 2 && !cx_entries) {  // a macro's (or a U3's) products together
               const double t = wave_totals4(prod[0], prod[1], prod[2], 0.0);
-              const double s0 = lane_value<0>(t), s1 = lane_value<32>(t), s2 = lane_value<16>(t);
-              const int j = lane - op.lslot;
-              acc += j == 0 ? s0 : j == 1 ? s1 : (j == 2 && op.np > 2) ? s2 : 0.0;
+              const double tot[3] = {lane_value<0>(t), lane_value<32>(t), lane_value<16>(t)};
+#pragma unroll
+              for (int j = 0; j < 3; ++j) {
+                if (j >= op.np) break;
+                add_to_slot(acc0, acc1, op.lslot + j, lane, tot[j]);
+              }
             } else {
 #pragma unroll
               for (int j = 0; j < 3; ++j) {
                 if (j >= op.np) break;
                 const double s = lane63_value(wave_total_lane63(prod[j]));
-                acc += lane == op.lslot + j ? s : 0.0;
+                add_to_slot(acc0, acc1, op.lslot + j, lane, s);
                 if (cx_entries) {
                   const double si = lane63_value(wave_total_lane63(prod_im[j]));
-                  acc_im += lane == op.lslot + j ? si : 0.0;
+                  add_to_slot(acc0_im, acc1_im, op.lslot + j, lane, si);
                 }
               }
             }
@@ -1319,8 +1335,12 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
         }
       }
     }
-    wacc[lane][wave] = acc;
-    if (cx_entries) wacc_im[lane][wave] = acc_im;
+    wacc[lane][wave] = acc0;
+    wacc[64 + lane][wave] = acc1;
+    if (cx_entries) {
+      wacc_im[lane][wave] = acc0_im;
+      wacc_im[64 + lane][wave] = acc1_im;
+    }
     lds_barrier();
     const int col = (int)blockIdx.x - I.first_wg;
     for (int j = tid; j < I.pd.n_slots; j += G::NT) {

@@ -158,24 +158,47 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
   const int c = std::min(run_qubits, std::min(w, n));
   const uint64_t low = (1ull << c) - 1;
 
+  // candidate tiles for the gates `r`: greedy growth along the gate order (from the low qubits,
+  // and from them plus the first gate's qubits), and windows along the qubit chain
+  auto candidates = [&](const std::vector<int>& r) {
+    std::vector<uint64_t> cs;
+    auto add = [&](uint64_t T) {
+      if (popc(T) == tq && std::find(cs.begin(), cs.end(), T) == cs.end()) cs.push_back(T);
+    };
+    add(fill_tile(grow_tile(r, gates, low, tq), n, tq));
+    add(fill_tile(grow_tile(r, gates, low | qmask(gates[r[0]]), tq), n, tq));
+    for (int a = c; a + (tq - c) <= n; ++a) add(((((1ull << (tq - c)) - 1) << a) | low) & all);
+    return cs;
+  };
+
   std::vector<int> rem(seq);
   while (!rem.empty()) {
-    // ---- choose the tile: best of several candidates by gates taken
-    std::vector<uint64_t> cands;
-    cands.push_back(fill_tile(grow_tile(rem, gates, low, tq), n, tq));
-    cands.push_back(fill_tile(grow_tile(rem, gates, low | qmask(gates[rem[0]]), tq), n, tq));
-    for (int a = c; a + (tq - c) <= n; ++a) {
-      uint64_t win = (((1ull << (tq - c)) - 1) << a) | low;
-      cands.push_back(win & all);
-    }
+    // ---- choose the tile: the candidate that takes the most gates in this pass and the best
+    // next pass together (one pass of lookahead), ties to the larger first pass
     uint64_t bestT = 0;
-    int best = -1;
-    for (uint64_t T : cands) {
-      if (popc(T) != tq) continue;
+    int best = -1, best_first = -1;
+    for (uint64_t T : candidates(rem)) {
+      std::vector<int> tk;
       int cnt = 0;
-      scan(rem, gates, T, backward, kMaxSlotsPerPass, kMaxOpsPerPass, nullptr, &cnt);
-      if (cnt > best) {
-        best = cnt;
+      scan(rem, gates, T, backward, kMaxSlotsPerPass, kMaxOpsPerPass, &tk, &cnt);
+      if (cnt <= 0) continue;
+      int next = 0;
+      if (cnt < (int)rem.size()) {
+        std::vector<char> in(gates.size(), 0);
+        for (int k : tk) in[k] = 1;
+        std::vector<int> rest;
+        rest.reserve(rem.size() - tk.size());
+        for (int k : rem)
+          if (!in[k]) rest.push_back(k);
+        for (uint64_t T2 : candidates(rest)) {
+          int c2 = 0;
+          scan(rest, gates, T2, backward, kMaxSlotsPerPass, kMaxOpsPerPass, nullptr, &c2);
+          next = std::max(next, c2);
+        }
+      }
+      if (cnt + next > best || (cnt + next == best && cnt > best_first)) {
+        best = cnt + next;
+        best_first = cnt;
         bestT = T;
       }
     }

@@ -1220,8 +1220,8 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     direct_offsets<RB, W>(I.pd, tid, gthr, groff, live, preg);
     const bool phantom = I.pd.tile[G::T - 1] < 0;  // phantom bits are the top tile bits
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
-    // lane j of every wave accumulates product slot j over the wave's share of the tiles
-    // lane j of acc0 holds slot j, of acc1 slot 64 + j
+    // every wave accumulates the product slots over its share of the tiles: lane j of acc0
+    // holds slot j, lane j of acc1 slot 64 + j
     double acc0 = 0.0, acc1 = 0.0, acc0_im = 0.0, acc1_im = 0.0;
     const bool cx_entries = GEN && cplx;
     for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {

@@ -133,6 +133,25 @@ def timed_steps(torch, runner, steps):
     return time.perf_counter() - t0
 
 
+def gate_granular_bytes(prob, state_bytes):
+    """Bytes one energy + gradient would move with one HBM pass per gate (mu never in HBM):
+    forward rotation 2S, CNOT S, CZ S/2; reverse rotation 4S, CNOT 2S, CZ S; H 2S plus 3S per
+    further x-mask group; clones and the energy 6S. Every other gate counts as a rotation."""
+    from paper_2009_02823_amd import workloads as W
+    S = float(state_bytes)
+    fwd = bwd = 0.0
+    for row in prob.gates:
+        k = int(row[0])
+        if k == W.CNOT:
+            fwd, bwd = fwd + S, bwd + 2 * S
+        elif k == W.CZ:
+            fwd, bwd = fwd + S / 2, bwd + S
+        else:
+            fwd, bwd = fwd + 2 * S, bwd + 4 * S
+    xmask = {tuple(int(c) in (1, 2) for c in term) for term in prob.codes}
+    return fwd + bwd + 2 * S + 3 * S * (len(xmask) - 1) + 6 * S
+
+
 def run(qsv, torch, runner, steps, warmup, graphs=True, geometry=None):
     tuned = runner.autotune(geometry)
     h = runner.handle()
@@ -408,6 +427,14 @@ def main():
     if args.config != 4:
         out["config"].update({"n_qubits": prob.n_qubits, "n_params": prob.n_params,
                               "n_gates": prob.n_gates, "pauli_terms": int(len(prob.coeffs))})
+    # what fusion saves: the bytes of a one-HBM-pass-per-gate schedule over the measured time
+    # (may exceed the peak; it is not a roofline)
+    probs_ = probs if args.config == 4 else [prob]
+    b_adj = sum(gate_granular_bytes(p, (16 if main_dt == "c128" else 8) << p.n_qubits)
+                for p in probs_)
+    ge = b_adj / (res["ms_per_step"] * 1e-3) / 1e9
+    out["gate_equivalent"] = {"bytes_per_step": b_adj, "GBps": ge, "vs_hbm_peak": ge / HBM_PEAK_GBPS,
+                              "ms_at_60pct_peak": b_adj / (0.6 * HBM_PEAK_GBPS * 1e9) * 1e3}
     tune = None
     if res["tuned"]:
         m, r, w, _ = res["tuned"]

@@ -146,13 +146,27 @@ struct Schedule {
 
 // Builds the schedule of `gates` taken in order `seq` (gate indices). slot_of_gate[k] is the first
 // global reduction slot of gate k (or -1); it is only used when `backward` is set. Every tile
-// holds qubits 0 .. run_qubits - 1 (see run_qubits_for). `macros`
+// holds qubits 0 .. run_qubits - 1 (see run_qubits_for). With `given`, the passes are not chosen
+// but taken from that list (which must cover `seq` in a valid order). `macros`
 // allows rotation macros (off for schedules whose ops are addressed one by one, as the
 // derivative substitution of Algorithm 2 does). Returns false (with msg) if the gates cannot be
 // scheduled with these sizes.
+// A pass given in advance: its tile (physical-qubit mask) and gates in execution order.
+struct PassPlan {
+  uint64_t tile = 0;
+  std::vector<int> gates;
+};
+
 bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector<int>& seq,
                     const std::vector<int32_t>& slot_of_gate, bool backward, int t, int r, int w,
-                    int run_qubits, Schedule& out, std::string* msg, bool macros = true);
+                    int run_qubits, Schedule& out, std::string* msg, bool macros = true,
+                    const std::vector<PassPlan>* given = nullptr);
+
+// The forward schedule: the scheduler's own, or the reverse sweep's passes taken last to first
+// (each in forward gate order) if those are fewer.
+bool build_forward_schedule(int n, const std::vector<GateDesc>& gates, int t, int r, int w,
+                            int run_qubits, const Schedule& bwd, Schedule& out,
+                            std::string* msg, bool macros = true);
 
 // Lowest qubits every tile holds, so that loads and stores move contiguous runs of one 128-byte
 // L2 line: 8 complex128 or 16 complex64 amplitudes. Fewer forced qubits leave more tile bits to

@@ -776,15 +776,14 @@ static qsv_status get_fused(qsv_state* s, Plan* p, int r, int w, FusedPlan** out
   const int G = (int)p->gates.size();
   std::vector<int> seq(G);
   std::string msg;
-  for (int k = 0; k < G; ++k) seq[k] = k;
   const int runq = run_qubits_for(s->dt == QSV_C128);
-  if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, false, r + w, r, w, runq,
-                      fp->fwd.sched, &msg))
-    return fail(QSV_ERR_INTERNAL, "forward schedule: %s", msg.c_str());
   for (int k = 0; k < G; ++k) seq[k] = G - 1 - k;
   if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, true, r + w, r, w, runq,
                       fp->bwd.sched, &msg))
     return fail(QSV_ERR_INTERNAL, "backward schedule: %s", msg.c_str());
+  if (!build_forward_schedule(s->n, p->gates, r + w, r, w, runq, fp->bwd.sched, fp->fwd.sched,
+                              &msg))
+    return fail(QSV_ERR_INTERNAL, "forward schedule: %s", msg.c_str());
   QSV_TRY(upload_schedule(fp->fwd, st));
   QSV_TRY(upload_schedule(fp->bwd, st));
 
@@ -1499,13 +1498,11 @@ static qsv_status get_ref(qsv_state* s, Plan* p, FusedPlan* fp, RefPlan** out) {
   const hipStream_t st = s->stream;
   auto rp = std::make_unique<RefPlan>();
   {
-    const int G = (int)p->gates.size();
-    std::vector<int> seq(G);
-    for (int k = 0; k < G; ++k) seq[k] = k;
     std::string msg;
     // the derivative substitution addresses every op of the pass on its own
-    if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, false, fp->t, fp->r, fp->w,
-                        run_qubits_for(s->dt == QSV_C128), rp->fwd.sched, &msg, false))
+    if (!build_forward_schedule(s->n, p->gates, fp->t, fp->r, fp->w,
+                                run_qubits_for(s->dt == QSV_C128), fp->bwd.sched, rp->fwd.sched,
+                                &msg, false))
       return fail(QSV_ERR_INTERNAL, "forward schedule: %s", msg.c_str());
     QSV_TRY(upload_schedule(rp->fwd, st));
   }
@@ -1776,13 +1773,20 @@ extern "C" qsv_status qsv_schedule_describe(int32_t n, const qsv_gate* gates, in
       sl += kind_nparams(g[k].kind);
     }
   std::vector<int> seq(n_gates);
-  for (int k = 0; k < n_gates; ++k) seq[k] = backward ? n_gates - 1 - k : k;
+  for (int k = 0; k < n_gates; ++k) seq[k] = n_gates - 1 - k;
   Schedule sc;
   std::string msg;
   if (dt != QSV_C64 && dt != QSV_C128) return fail(QSV_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
-  if (!build_schedule(n, g, seq, slot, backward != 0, reg_qubits + threads_log2, reg_qubits,
-                      threads_log2, run_qubits_for(dt == QSV_C128), sc, &msg))
+  const int t = reg_qubits + threads_log2, runq = run_qubits_for(dt == QSV_C128);
+  // the forward schedule is derived with the reverse sweep's at hand, as the library does
+  if (!build_schedule(n, g, seq, slot, true, t, reg_qubits, threads_log2, runq, sc, &msg))
     return fail(QSV_ERR_INTERNAL, "schedule: %s", msg.c_str());
+  if (!backward) {
+    Schedule fw;
+    if (!build_forward_schedule(n, g, t, reg_qubits, threads_log2, runq, sc, fw, &msg))
+      return fail(QSV_ERR_INTERNAL, "schedule: %s", msg.c_str());
+    sc = std::move(fw);
+  }
   out->n_passes = (int32_t)sc.passes.size();
   out->n_phases = (int32_t)sc.phases.size();
   for (int i = 0; i < n_gates; ++i) {

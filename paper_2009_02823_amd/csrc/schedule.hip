@@ -141,7 +141,8 @@ static void form_rotation_macros(std::vector<std::pair<int, FusedOp>>& ops, int 
 
 bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector<int>& seq,
                     const std::vector<int32_t>& slot_of_gate, bool backward, int t, int r, int w,
-                    int run_qubits, Schedule& out, std::string* msg, bool macros) {
+                    int run_qubits, Schedule& out, std::string* msg, bool macros,
+                    const std::vector<PassPlan>* given) {
   out = Schedule();
   out.t = t;
   out.r = r;
@@ -172,43 +173,50 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
   };
 
   std::vector<int> rem(seq);
-  while (!rem.empty()) {
-    // ---- choose the tile: the candidate that takes the most gates in this pass and the best
-    // next pass together (one pass of lookahead), ties to the larger first pass
+  size_t next_given = 0;
+  while (given ? next_given < given->size() : !rem.empty()) {
     uint64_t bestT = 0;
-    int best = -1, best_first = -1;
-    for (uint64_t T : candidates(rem)) {
-      std::vector<int> tk;
-      int cnt = 0;
-      scan(rem, gates, T, backward, kMaxSlotsPerPass, kMaxOpsPerPass, &tk, &cnt);
-      if (cnt <= 0) continue;
-      int next = 0;
-      if (cnt < (int)rem.size()) {
-        std::vector<char> in(gates.size(), 0);
-        for (int k : tk) in[k] = 1;
-        std::vector<int> rest;
-        rest.reserve(rem.size() - tk.size());
-        for (int k : rem)
-          if (!in[k]) rest.push_back(k);
-        for (uint64_t T2 : candidates(rest)) {
-          int c2 = 0;
-          scan(rest, gates, T2, backward, kMaxSlotsPerPass, kMaxOpsPerPass, nullptr, &c2);
-          next = std::max(next, c2);
+    std::vector<int> taken;
+    if (given) {  // the passes are given: tile and gates (in execution order)
+      bestT = (*given)[next_given].tile;
+      taken = (*given)[next_given].gates;
+      ++next_given;
+    } else {
+      // ---- choose the tile: the candidate that takes the most gates in this pass and the best
+      // next pass together (one pass of lookahead), ties to the larger first pass
+      int best = -1, best_first = -1;
+      for (uint64_t T : candidates(rem)) {
+        std::vector<int> tk;
+        int cnt = 0;
+        scan(rem, gates, T, backward, kMaxSlotsPerPass, kMaxOpsPerPass, &tk, &cnt);
+        if (cnt <= 0) continue;
+        int next = 0;
+        if (cnt < (int)rem.size()) {
+          std::vector<char> in(gates.size(), 0);
+          for (int k : tk) in[k] = 1;
+          std::vector<int> rest;
+          rest.reserve(rem.size() - tk.size());
+          for (int k : rem)
+            if (!in[k]) rest.push_back(k);
+          for (uint64_t T2 : candidates(rest)) {
+            int c2 = 0;
+            scan(rest, gates, T2, backward, kMaxSlotsPerPass, kMaxOpsPerPass, nullptr, &c2);
+            next = std::max(next, c2);
+          }
+        }
+        if (cnt + next > best || (cnt + next == best && cnt > best_first)) {
+          best = cnt + next;
+          best_first = cnt;
+          bestT = T;
         }
       }
-      if (cnt + next > best || (cnt + next == best && cnt > best_first)) {
-        best = cnt + next;
-        best_first = cnt;
-        bestT = T;
+      if (best <= 0) {
+        if (msg) *msg = "a gate does not fit any tile";
+        return false;
       }
+      int cnt = 0;
+      scan(rem, gates, bestT, backward, kMaxSlotsPerPass, kMaxOpsPerPass, &taken, &cnt);
     }
-    if (best <= 0) {
-      if (msg) *msg = "a gate does not fit any tile";
-      return false;
-    }
-    std::vector<int> taken;
-    int cnt = 0;
-    scan(rem, gates, bestT, backward, kMaxSlotsPerPass, kMaxOpsPerPass, &taken, &cnt);
 
     PassDesc pd;
     std::memset(&pd, 0, sizeof pd);
@@ -418,6 +426,33 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
       if (!done[k]) nrem.push_back(k);
     rem.swap(nrem);
   }
+  return true;
+}
+
+bool build_forward_schedule(int n, const std::vector<GateDesc>& gates, int t, int r, int w,
+                            int run_qubits, const Schedule& bwd, Schedule& out,
+                            std::string* msg, bool macros) {
+  const int G = (int)gates.size();
+  std::vector<int> seq(G);
+  for (int k = 0; k < G; ++k) seq[k] = k;
+  const std::vector<int32_t> no_slots(G, -1);
+  if (!build_schedule(n, gates, seq, no_slots, false, t, r, w, run_qubits, out, msg, macros))
+    return false;
+  // the reverse sweep's passes, last first, each in forward gate order: every pass is a set of
+  // gates that are consecutive in a valid order of the reversed circuit, so the reversed list is
+  // a valid order of the circuit
+  std::vector<PassPlan> rev(bwd.passes.size());
+  for (size_t i = 0; i < bwd.order.size(); ++i) rev[bwd.pass_of[i]].gates.push_back(bwd.order[i]);
+  for (size_t p = 0; p < rev.size(); ++p) {
+    std::sort(rev[p].gates.begin(), rev[p].gates.end());
+    rev[p].tile = bwd.tile_mask[p];
+  }
+  std::reverse(rev.begin(), rev.end());
+  Schedule alt;
+  std::string m2;
+  if (build_schedule(n, gates, seq, no_slots, false, t, r, w, run_qubits, alt, &m2, macros, &rev) &&
+      alt.passes.size() < out.passes.size())
+    out = std::move(alt);
   return true;
 }
 

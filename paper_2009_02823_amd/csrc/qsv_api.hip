@@ -647,6 +647,9 @@ static double state_bytes_d(const qsv_state* s) { return (double)qsv_state_bytes
 // fusion geometry and schedules
 // ------------------------------------------------------------------------------------------------
 static constexpr int kFusedGridCap = 1024;
+// A batched level mixes passes of very different lengths (a small circuit may run all its gates
+// in one pass): a workgroup per tile or two lets the hardware balance them.
+static constexpr int kBatchGridCap = 1 << 20;
 
 // Tile geometry for the handle: (r, w) with t = r + w tile qubits, or false for the gate-granular
 // path (states too small for a tile, or fusion switched off).
@@ -714,8 +717,8 @@ static qsv_status upload_vec(DevBuf& b, const std::vector<T>& v, hipStream_t st)
 
 // Launch geometry of `total` tiles: workgroups, tiles per workgroup, and for an item occupying
 // tiles [begin, begin + count) the first workgroup reaching into it and how many do.
-static void launch_shape(int64_t total, int* grid, int64_t* chunk) {
-  const int64_t g = std::min<int64_t>(total, kFusedGridCap);
+static void launch_shape(int64_t total, int* grid, int64_t* chunk, int64_t cap = kFusedGridCap) {
+  const int64_t g = std::min<int64_t>(total, cap);
   *grid = (int)(g < 1 ? 1 : g);
   *chunk = (total + *grid - 1) / *grid;
   if (*chunk < 1) *chunk = 1;
@@ -1150,7 +1153,7 @@ static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>
       L->general = L->general || fps[b]->fwd.sched.passes[k].general;
       items.push_back(it);
     }
-    launch_shape(L->total, &L->grid, &L->chunk);
+    launch_shape(L->total, &L->grid, &L->chunk, kBatchGridCap);
     for (PassItem& it : items) item_span(it.tile_begin, 1ll << it.n_outer, L->chunk, &it.first_wg, &it.nb);
     L->n_items = (int)items.size();
     QSV_TRY(upload_vec(L->d_items, items, st));
@@ -1173,7 +1176,7 @@ static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>
       level_items[k].push_back(it);
       level_owner[k].push_back(b);
     }
-    launch_shape(L->total, &L->grid, &L->chunk);
+    launch_shape(L->total, &L->grid, &L->chunk, kBatchGridCap);
     for (PassItem& it : level_items[k])
       item_span(it.tile_begin, 1ll << it.n_outer, L->chunk, &it.first_wg, &it.nb);
     L->n_items = (int)level_items[k].size();

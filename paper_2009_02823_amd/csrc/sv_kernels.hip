@@ -483,30 +483,80 @@ hipError_t launch_backward_gate(void* phi_, void* lam_, int n, const GateDesc& g
 // ----------------------------------------------------------------------------------------------
 // Hamiltonian: (H psi)_j = sum_groups psi_{j^x} sum_{t in group} coef_t (-1)^{popc((j^x) & z_t)}
 // ----------------------------------------------------------------------------------------------
-template <typename R, bool WRITE>
+// (H psi) at the V consecutive indices j0 .. j0 + V - 1 (j0 a multiple of V = 1, 2 or 4). For a
+// group with X mask x the sources (j0 + k) ^ x form the aligned block j0 ^ (x & ~(V - 1)), in the
+// order k ^ (x & (V - 1)): one contiguous load per group, permuted in registers.
+template <typename R, int V>
+__device__ __forceinline__ void pauli_block(const typename Vec2<R>::T* psi, uint64_t j0,
+                                            const PauliGroup* groups, int n_groups,
+                                            const PauliTerm* terms, cx<R>* acc) {
+#pragma unroll
+  for (int k = 0; k < V; ++k) acc[k] = {0, 0};
+#pragma unroll 2
+  for (int gi = 0; gi < n_groups; ++gi) {
+    const PauliGroup G = groups[gi];
+    const uint64_t base = j0 ^ (G.x & ~(uint64_t)(V - 1));
+    cx<R> a[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) a[k] = load<R>(psi, base + k);
+    const int xl = (int)(G.x & (V - 1));  // uniform
+    if constexpr (V >= 2) {
+      if (xl & 1) {
+#pragma unroll
+        for (int k = 0; k < V; k += 2) {
+          const cx<R> t = a[k];
+          a[k] = a[k + 1];
+          a[k + 1] = t;
+        }
+      }
+    }
+    if constexpr (V >= 4) {
+      if (xl & 2) {
+#pragma unroll
+        for (int k = 0; k < V; k += 4) {
+          cx<R> t = a[k];
+          a[k] = a[k + 2];
+          a[k + 2] = t;
+          t = a[k + 1];
+          a[k + 1] = a[k + 3];
+          a[k + 3] = t;
+        }
+      }
+    }
+    // a[k] = psi[(j0 + k) ^ x]; its coefficient sums the group's terms with their Z signs
+    double sr[V], si[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) sr[k] = si[k] = 0.0;
+    for (int t = G.t0; t < G.t1; ++t) {
+      const PauliTerm T = terms[t];
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const bool odd = __popcll(((j0 + k) ^ G.x) & T.z) & 1;
+        sr[k] += odd ? -T.cre : T.cre;
+        si[k] += odd ? -T.cim : T.cim;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc[k] = acc[k] + cx<R>{(R)sr[k], (R)si[k]} * a[k];
+  }
+}
+
+template <typename R, bool WRITE, int V>
 __global__ void __launch_bounds__(kBlock)
 k_pauli(const typename Vec2<R>::T* psi, typename Vec2<R>::T* out, int n, const PauliGroup* groups,
         int n_groups, const PauliTerm* terms, double2* partial) {
   double2 e = make_double2(0, 0);
-  const uint64_t dim = 1ull << n;
-  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < dim;
-       j += (uint64_t)gridDim.x * blockDim.x) {
-    cx<R> acc = {0, 0};
-    for (int gi = 0; gi < n_groups; ++gi) {
-      const PauliGroup G = groups[gi];
-      const uint64_t src = j ^ G.x;
-      double sr = 0, si = 0;
-      for (int t = G.t0; t < G.t1; ++t) {
-        const PauliTerm T = terms[t];
-        const double sg = (__popcll(src & T.z) & 1) ? -1.0 : 1.0;
-        sr += sg * T.cre;
-        si += sg * T.cim;
-      }
-      const cx<R> s = {(R)sr, (R)si};
-      acc = acc + s * load<R>(psi, src);
+  const uint64_t blocks = (1ull << n) / V;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < blocks;
+       b += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t j0 = b * V;
+    cx<R> acc[V];
+    pauli_block<R, V>(psi, j0, groups, n_groups, terms, acc);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      if (WRITE) store<R>(out, j0 + k, acc[k]);
+      acc_dot<R>(e, load<R>(psi, j0 + k), acc[k]);
     }
-    if (WRITE) store<R>(out, j, acc);
-    acc_dot<R>(e, load<R>(psi, j), acc);
   }
   block_sum_store<kBlock>(e, partial + blockIdx.x);
 }
@@ -516,29 +566,22 @@ k_pauli(const typename Vec2<R>::T* psi, typename Vec2<R>::T* out, int n, const P
 template <typename R>
 __global__ void __launch_bounds__(kBlock)
 k_pauli_batched(const PauliJob* __restrict__ jobs, double2* partials) {
+  constexpr int V = 4;  // a batched level needs a fused tile: every circuit has at least 8 qubits
   const PauliJob J = jobs[blockIdx.y];
   const typename Vec2<R>::T* psi = static_cast<const typename Vec2<R>::T*>(J.psi);
   typename Vec2<R>::T* out = static_cast<typename Vec2<R>::T*>(J.out);
   double2 e = make_double2(0, 0);
-  const uint64_t dim = 1ull << J.n;
-  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < dim;
-       j += (uint64_t)gridDim.x * blockDim.x) {
-    cx<R> acc = {0, 0};
-    for (int gi = 0; gi < J.n_groups; ++gi) {
-      const PauliGroup G = J.groups[gi];
-      const uint64_t src = j ^ G.x;
-      double sr = 0, si = 0;
-      for (int t = G.t0; t < G.t1; ++t) {
-        const PauliTerm T = J.terms[t];
-        const double sg = (__popcll(src & T.z) & 1) ? -1.0 : 1.0;
-        sr += sg * T.cre;
-        si += sg * T.cim;
-      }
-      const cx<R> sv = {(R)sr, (R)si};
-      acc = acc + sv * load<R>(psi, src);
+  const uint64_t blocks = (1ull << J.n) / V;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < blocks;
+       b += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t j0 = b * V;
+    cx<R> acc[V];
+    pauli_block<R, V>(psi, j0, J.groups, J.n_groups, J.terms, acc);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      store<R>(out, j0 + k, acc[k]);
+      acc_dot<R>(e, load<R>(psi, j0 + k), acc[k]);
     }
-    store<R>(out, j, acc);
-    acc_dot<R>(e, load<R>(psi, j), acc);
   }
   block_sum_store<kBlock>(e, partials + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
@@ -559,12 +602,19 @@ hipError_t launch_pauli(const void* psi_, void* out_, int n, const PauliGroup* d
   using V = typename Vec2<R>::T;
   const V* psi = static_cast<const V*>(psi_);
   V* out = static_cast<V*>(out_);
-  if (out)
-    hipLaunchKernelGGL((k_pauli<R, true>), dim3(nb), dim3(kBlock), 0, st, psi, out, n, d_groups,
-                       n_groups, d_terms, partial);
-  else
-    hipLaunchKernelGGL((k_pauli<R, false>), dim3(nb), dim3(kBlock), 0, st, psi, out, n, d_groups,
-                       n_groups, d_terms, partial);
+#define QSV_PAULI(VV)                                                                         \
+  if (out)                                                                                    \
+    hipLaunchKernelGGL((k_pauli<R, true, VV>), dim3(nb), dim3(kBlock), 0, st, psi, out, n,    \
+                       d_groups, n_groups, d_terms, partial);                                 \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_pauli<R, false, VV>), dim3(nb), dim3(kBlock), 0, st, psi, out, n,   \
+                       d_groups, n_groups, d_terms, partial);
+  if (n >= 2) {
+    QSV_PAULI(4)
+  } else {
+    QSV_PAULI(1)
+  }
+#undef QSV_PAULI
   return hipGetLastError();
 }
 

@@ -335,8 +335,9 @@ __device__ __forceinline__ double tree_sum(const double* t) {
   else return tree_sum<N / 2>(t) + tree_sum<N - N / 2>(t + N / 2);
 }
 
+// Complex64: per pair a product difference, then a tree sum over the pairs.
 template <typename R, int NA, int K>
-__device__ __forceinline__ double prod_ry_k(const cx<R>* f, const cx<R>* l) {
+__device__ __forceinline__ double prod_ry_pairs(const cx<R>* f, const cx<R>* l) {
   double t[NA / 2];  // Y f = (-i f1, i f0)
   int j = 0;
 #pragma unroll
@@ -349,7 +350,7 @@ __device__ __forceinline__ double prod_ry_k(const cx<R>* f, const cx<R>* l) {
 }
 
 template <typename R, int NA, int K>
-__device__ __forceinline__ double prod_rx_k(const cx<R>* f, const cx<R>* l) {
+__device__ __forceinline__ double prod_rx_pairs(const cx<R>* f, const cx<R>* l) {
   double t[NA / 2];  // X f = (f1, f0)
   int j = 0;
 #pragma unroll
@@ -362,7 +363,7 @@ __device__ __forceinline__ double prod_rx_k(const cx<R>* f, const cx<R>* l) {
 }
 
 template <typename R, int NA, int K>
-__device__ __forceinline__ double prod_rz_k(const cx<R>* f, const cx<R>* l) {
+__device__ __forceinline__ double prod_rz_pairs(const cx<R>* f, const cx<R>* l) {
   double t[NA / 2];  // Z f = (-1)^bit f
   int j = 0;
 #pragma unroll
@@ -372,6 +373,77 @@ __device__ __forceinline__ double prod_rz_k(const cx<R>* f, const cx<R>* l) {
     t[j++] = im_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i) - im_cm(l[rj].r, l[rj].i, f[rj].r, f[rj].i);
   }
   return 0.5 * tree_sum<NA / 2>(t);
+}
+
+// Half the sum of x[i] y[i] over the T terms, as two interleaved FMA chains (fewer instructions
+// than a product, a difference and a tree sum per pair; two chains keep the dependence short).
+template <int T>
+__device__ __forceinline__ double half_dot(const double* x, const double* y) {
+  static_assert(T % 2 == 0 && T >= 4, "two chains of at least two terms");
+  double a = x[0] * y[0], b = x[T / 2] * y[T / 2];
+#pragma unroll
+  for (int i = 1; i < T / 2; ++i) {
+    a = __builtin_fma(x[i], y[i], a);
+    b = __builtin_fma(x[T / 2 + i], y[T / 2 + i], b);
+  }
+  return 0.5 * (a + b);
+}
+
+// Rotation products (1/2) Im<lambda|G|phi> over the pairs of register position K, written as
+// sums of real products (the sign of each term folded into x); complex128 only (in complex64 the
+// FP64 term arrays cost registers).
+template <typename R, int NA, int K>
+__device__ __forceinline__ double prod_ry_k(const cx<R>* f, const cx<R>* l) {
+  if constexpr (sizeof(R) != 8) return prod_ry_pairs<R, NA, K>(f, l);
+  // Y f = (-i f1, i f0): per pair Re(conj(l1) f0) - Re(conj(l0) f1)
+  double x[2 * NA], y[2 * NA];
+  int j = 0;
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    x[j] = l[rj].r;   y[j++] = f[ri].r;
+    x[j] = l[rj].i;   y[j++] = f[ri].i;
+    x[j] = -l[ri].r;  y[j++] = f[rj].r;
+    x[j] = -l[ri].i;  y[j++] = f[rj].i;
+  }
+  return half_dot<2 * NA>(x, y);
+}
+
+template <typename R, int NA, int K>
+__device__ __forceinline__ double prod_rx_k(const cx<R>* f, const cx<R>* l) {
+  if constexpr (sizeof(R) != 8) return prod_rx_pairs<R, NA, K>(f, l);
+  // X f = (f1, f0): per pair Im(conj(l0) f1) + Im(conj(l1) f0)
+  double x[2 * NA], y[2 * NA];
+  int j = 0;
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    x[j] = l[ri].r;   y[j++] = f[rj].i;
+    x[j] = -l[ri].i;  y[j++] = f[rj].r;
+    x[j] = l[rj].r;   y[j++] = f[ri].i;
+    x[j] = -l[rj].i;  y[j++] = f[ri].r;
+  }
+  return half_dot<2 * NA>(x, y);
+}
+
+template <typename R, int NA, int K>
+__device__ __forceinline__ double prod_rz_k(const cx<R>* f, const cx<R>* l) {
+  if constexpr (sizeof(R) != 8) return prod_rz_pairs<R, NA, K>(f, l);
+  // Z f = (-1)^bit f: per pair Im(conj(l0) f0) - Im(conj(l1) f1)
+  double x[2 * NA], y[2 * NA];
+  int j = 0;
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    x[j] = l[ri].r;   y[j++] = f[ri].i;
+    x[j] = -l[ri].i;  y[j++] = f[ri].r;
+    x[j] = -l[rj].r;  y[j++] = f[rj].i;
+    x[j] = l[rj].i;   y[j++] = f[rj].r;
+  }
+  return half_dot<2 * NA>(x, y);
 }
 
 template <typename R, int NA>

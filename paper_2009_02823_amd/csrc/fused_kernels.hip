@@ -161,10 +161,12 @@ __device__ __forceinline__ bool same_layout(const Layout<RB>& a, const int8_t* r
 // Lean ops. ADJ selects U^dag (reverse sweep) instead of U.
 // ---------------------------------------------------------------------------------------------
 // x <- c x + t with the result in x's own register (a tied operand): left to itself the compiler
-// accumulates into the temporary holding t and copies the result back at the switch join
-// (complex128; the complex64 rotations keep the plain expressions, which measured faster).
+// accumulates into the temporary holding t and copies the result back at the switch join.
 __device__ __forceinline__ void fma_inplace(double& x, double c, double t) {
   asm("v_fma_f64 %0, %1, %0, %2" : "+v"(x) : "v"(c), "v"(t));
+}
+__device__ __forceinline__ void fma_inplace(float& x, float c, float t) {
+  asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x) : "v"(c), "v"(t));
 }
 
 template <typename R, int NA, int K, bool ADJ>
@@ -174,17 +176,11 @@ __device__ __forceinline__ void ry_k(cx<R>* a, R c, R s) {
   for (int ri = 0; ri < NA; ++ri) {
     if (ri & (1 << K)) continue;
     const int rj = ri | (1 << K);
-    if constexpr (sizeof(R) == 8) {
-      const R tr = -sp * a[rj].r, ti = -sp * a[rj].i, ur = sp * a[ri].r, ui = sp * a[ri].i;
-      fma_inplace(a[ri].r, c, tr);
-      fma_inplace(a[ri].i, c, ti);
-      fma_inplace(a[rj].r, c, ur);
-      fma_inplace(a[rj].i, c, ui);
-    } else {
-      const cx<R> x = a[ri], y = a[rj];
-      a[ri] = {c * x.r - sp * y.r, c * x.i - sp * y.i};
-      a[rj] = {sp * x.r + c * y.r, sp * x.i + c * y.i};
-    }
+    const R tr = -sp * a[rj].r, ti = -sp * a[rj].i, ur = sp * a[ri].r, ui = sp * a[ri].i;
+    fma_inplace(a[ri].r, c, tr);
+    fma_inplace(a[ri].i, c, ti);
+    fma_inplace(a[rj].r, c, ur);
+    fma_inplace(a[rj].i, c, ui);
   }
 }
 
@@ -195,30 +191,20 @@ __device__ __forceinline__ void rx_k(cx<R>* a, R c, R s) {
   for (int ri = 0; ri < NA; ++ri) {
     if (ri & (1 << K)) continue;
     const int rj = ri | (1 << K);
-    if constexpr (sizeof(R) == 8) {
-      const R t0 = sp * a[rj].i, t1 = -sp * a[rj].r, t2 = sp * a[ri].i, t3 = -sp * a[ri].r;
-      fma_inplace(a[ri].r, c, t0);
-      fma_inplace(a[ri].i, c, t1);
-      fma_inplace(a[rj].r, c, t2);
-      fma_inplace(a[rj].i, c, t3);
-    } else {
-      const cx<R> x = a[ri], y = a[rj];
-      a[ri] = {c * x.r + sp * y.i, c * x.i - sp * y.r};
-      a[rj] = {c * y.r + sp * x.i, c * y.i - sp * x.r};
-    }
+    const R t0 = sp * a[rj].i, t1 = -sp * a[rj].r, t2 = sp * a[ri].i, t3 = -sp * a[ri].r;
+    fma_inplace(a[ri].r, c, t0);
+    fma_inplace(a[ri].i, c, t1);
+    fma_inplace(a[rj].r, c, t2);
+    fma_inplace(a[rj].i, c, t3);
   }
 }
 
 // multiply by the phase c + i t
 template <typename R>
 __device__ __forceinline__ void phase_mul_inplace(cx<R>& z, R c, R t) {
-  if constexpr (sizeof(R) == 8) {
-    const R u0 = -t * z.i, u1 = t * z.r;
-    fma_inplace(z.r, c, u0);
-    fma_inplace(z.i, c, u1);
-  } else {
-    z = {c * z.r - t * z.i, c * z.i + t * z.r};
-  }
+  const R u0 = -t * z.i, u1 = t * z.r;
+  fma_inplace(z.r, c, u0);
+  fma_inplace(z.i, c, u1);
 }
 
 // RZ = diag(c - i s, c + i s): bit b multiplies by c + i (b ? s : -s) (negated for U^dag)

@@ -26,9 +26,11 @@ def Q():
     return qsv
 
 
-def test_config3_c64_full_vs_oracle(Q):
+@pytest.mark.parametrize("geom", [None, (4, 9)])
+def test_config3_c64_full_vs_oracle(Q, geom):
     """26 qubits, 30 layers + CZ brickwork (P = 1560), 200 random Pauli strings, complex64
-    storage with FP64 reductions: every gradient entry against the complex128 oracle."""
+    storage with FP64 reductions: every gradient entry against the complex128 oracle, in the
+    automatic geometry and in the one the benchmark's tuning picks."""
     import make_golden
     p = W.config3()
     ref = make_golden.read(p.name)
@@ -36,6 +38,8 @@ def test_config3_c64_full_vs_oracle(Q):
         pytest.skip("oracle values for the 26-qubit workload not generated")
     e_ref, g_ref = ref
     with Q.StateVector(p.n_qubits, "c64") as sv:
+        if geom is not None:
+            sv.set_fusion(1, *geom)
         e, g = sv.adjoint_gradient(p.gates, p.theta, p.codes, p.coeffs)
         sv.sync()
         e = float(e.cpu()[0])

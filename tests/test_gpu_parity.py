@@ -29,8 +29,10 @@ def Q():
     return qsv
 
 
-def gpu_adjoint(Q, n, gates, theta, codes, coeffs, dtype="c128", prep=None):
+def gpu_adjoint(Q, n, gates, theta, codes, coeffs, dtype="c128", prep=None, geom=None):
     with Q.StateVector(n, dtype) as sv:
+        if geom is not None:
+            sv.set_fusion(1, *geom)
         if prep is not None:
             sv.apply_circuit(*prep)
         e, g = sv.adjoint_gradient(gates, theta, codes, coeffs)
@@ -177,16 +179,18 @@ def test_invalid_call_leaves_outputs_untouched(Q):
         assert float(e.cpu()[0]) == 7.0 and bool((g == 7.0).all())
 
 
-@pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_config2_full(Q, orc, dtype):
-    """20 qubits, 20 layers (P = 800), TFIM: the full gradient against the oracle."""
+@pytest.mark.parametrize("dtype,geom", [("c128", None), ("c128", (3, 9)), ("c64", None),
+                                        ("c64", (3, 9)), ("c64", (4, 9))])
+def test_config2_full(Q, orc, dtype, geom):
+    """20 qubits, 20 layers (P = 800), TFIM: the full gradient against the oracle, in the
+    automatic geometry and in those the benchmark's tuning picks."""
     import make_golden as golden_io
     p = W.config2()
     ref = golden_io.read(p.name)
     if ref is None:
         ref = orc.adjoint_gradient(p.n_qubits, p.gates, p.theta, p.codes, p.coeffs)
     e_ref, g_ref = ref
-    e, g = gpu_adjoint(Q, p.n_qubits, p.gates, p.theta, p.codes, p.coeffs, dtype)
+    e, g = gpu_adjoint(Q, p.n_qubits, p.gates, p.theta, p.codes, p.coeffs, dtype, geom=geom)
     if dtype == "c128":
         assert_c128(e, g, e_ref, g_ref, p.coeffs)
     else:

@@ -297,9 +297,10 @@ qsv_status qsv_get_fusion(qsv_state* s, int32_t* mode, int32_t* reg_qubits, int3
 /* Host-only description of the fused schedule of a circuit (no GPU needed): the order gates run
    in, and for each executed gate its pass and register phase; the physical-qubit masks of every
    pass's tile and every phase's register qubits. backward != 0 describes the reverse sweep (gates
-   taken from last to first). The storage type matters: every tile holds the lowest qubits that
-   make one 128-byte run (qubits 0..2 for complex128, 0..3 for complex64). All arrays are
-   caller-owned with n_gates entries. n_macros counts
+   taken from last to first). The storage type matters: every tile holds the lowest qubits
+   (0..2 for complex128 and for complex64 states of up to 24 qubits, 0..3 for larger complex64
+   states), so that loads and stores move contiguous runs. All arrays are caller-owned with
+   n_gates entries. n_macros counts
    the rotation macros (runs of reg_qubits same-axis rotations, one per register qubit, that run
    as one op; formed for reg_qubits <= 3). */
 typedef struct {

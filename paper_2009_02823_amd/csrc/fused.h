@@ -168,10 +168,13 @@ bool build_forward_schedule(int n, const std::vector<GateDesc>& gates, int t, in
                             int run_qubits, const Schedule& bwd, Schedule& out,
                             std::string* msg, bool macros = true);
 
-// Lowest qubits every tile holds, so that loads and stores move contiguous runs of one 128-byte
-// L2 line: 8 complex128 or 16 complex64 amplitudes. Fewer forced qubits leave more tile bits to
-// the scheduler (fewer passes); a shorter run would split lines between tiles.
-inline int run_qubits_for(bool c128) { return c128 ? 3 : 4; }
+// Lowest qubits every tile holds, so that loads and stores move contiguous runs: fewer forced
+// qubits leave more tile bits to the scheduler (fewer passes), shorter runs use cache lines
+// (128 bytes) less well. Complex128: 3 (8 amplitudes, one line; 2 measured slower at 20 and 30
+// qubits). Complex64: 4 (16 amplitudes, one line) for states streamed from HBM, 3 (half a line)
+// for states of up to 24 qubits (128 MB), which stay in the 256 MB Infinity Cache (20 qubits:
+// 1.42 -> 1.37 ms per gradient; at 26 qubits half lines measured 3 % slower).
+inline int run_qubits_for(bool c128, int n) { return c128 ? 3 : (n <= 24 ? 3 : 4); }
 
 // Launchers of the fused pass kernels. Configurations (r, w) available: see fused_kernels.hip.
 bool fused_config_supported(int r, int w, bool c128);

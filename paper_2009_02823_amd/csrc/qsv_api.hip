@@ -779,7 +779,7 @@ static qsv_status get_fused(qsv_state* s, Plan* p, int r, int w, FusedPlan** out
   const int G = (int)p->gates.size();
   std::vector<int> seq(G);
   std::string msg;
-  const int runq = run_qubits_for(s->dt == QSV_C128);
+  const int runq = run_qubits_for(s->dt == QSV_C128, s->n);
   for (int k = 0; k < G; ++k) seq[k] = G - 1 - k;
   if (!build_schedule(s->n, p->gates, seq, p->slot_of_gate, true, r + w, r, w, runq,
                       fp->bwd.sched, &msg))
@@ -1504,8 +1504,8 @@ static qsv_status get_ref(qsv_state* s, Plan* p, FusedPlan* fp, RefPlan** out) {
     std::string msg;
     // the derivative substitution addresses every op of the pass on its own
     if (!build_forward_schedule(s->n, p->gates, fp->t, fp->r, fp->w,
-                                run_qubits_for(s->dt == QSV_C128), fp->bwd.sched, rp->fwd.sched,
-                                &msg, false))
+                                run_qubits_for(s->dt == QSV_C128, s->n), fp->bwd.sched,
+                                rp->fwd.sched, &msg, false))
       return fail(QSV_ERR_INTERNAL, "forward schedule: %s", msg.c_str());
     QSV_TRY(upload_schedule(rp->fwd, st));
   }
@@ -1780,7 +1780,7 @@ extern "C" qsv_status qsv_schedule_describe(int32_t n, const qsv_gate* gates, in
   Schedule sc;
   std::string msg;
   if (dt != QSV_C64 && dt != QSV_C128) return fail(QSV_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
-  const int t = reg_qubits + threads_log2, runq = run_qubits_for(dt == QSV_C128);
+  const int t = reg_qubits + threads_log2, runq = run_qubits_for(dt == QSV_C128, n);
   // the forward schedule is derived with the reverse sweep's at hand, as the library does
   if (!build_schedule(n, g, seq, slot, true, t, reg_qubits, threads_log2, runq, sc, &msg))
     return fail(QSV_ERR_INTERNAL, "schedule: %s", msg.c_str());

@@ -133,6 +133,22 @@ def timed_steps(torch, runner, steps):
     return time.perf_counter() - t0
 
 
+def step_distribution(torch, runner, stream, reps):
+    """Each of `reps` steps bracketed by HIP events on the handle's stream, after the timed
+    region: mean, standard deviation, median and minimum in ms."""
+    import numpy as np
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(reps):
+        runner.step()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)])
+    return {"runs": reps, "mean_ms": float(ms.mean()), "std_ms": float(ms.std()),
+            "median_ms": float(np.median(ms)), "min_ms": float(ms.min())}
+
+
 def gate_granular_bytes(prob, state_bytes):
     """Bytes one energy + gradient would move with one HBM pass per gate (mu never in HBM):
     forward rotation 2S, CNOT S, CZ S/2; reverse rotation 4S, CNOT 2S, CZ S; H 2S plus 3S per
@@ -169,6 +185,7 @@ def run(qsv, torch, runner, steps, warmup, graphs=True, geometry=None):
         for _ in range(2):
             runner.step()      # eager run, then capture
     dt = timed_steps(torch, runner, steps)
+    per_step = step_distribution(torch, runner, h.stream, max(3, min(24, steps)))
     if graphs:
         h.set_graphs(False)
     # timed region 2: the same steps launched eagerly, the dominant family timed per launch
@@ -177,7 +194,8 @@ def run(qsv, torch, runner, steps, warmup, graphs=True, geometry=None):
     dom = h.timing_read()
     h.timing_enable(None)
     return {"seconds": dt, "ms_per_step": 1e3 * dt / steps, "value": runner.units * steps / dt,
-            "ms_per_step_eager": 1e3 * dt_eager / steps, "dominant": dom[0] if dom else None,
+            "ms_per_step_eager": 1e3 * dt_eager / steps, "per_step": per_step,
+            "dominant": dom[0] if dom else None,
             "warmup_stats": stats, "tuned": tuned}
 
 
@@ -418,6 +436,7 @@ def main():
         "grad_error": err,
         "roofline": roof,
         "eager": {"ms_per_step": res["ms_per_step_eager"]},
+        "per_step": res["per_step"],
         # per kernel family over the eager warm-up steps (HIP events around every launch)
         "breakdown": [{"kernel": x["name"], "ms_per_step": x["total_ms"] / max(args.warmup, 1),
                        "launches_per_step": x["launches"] / max(args.warmup, 1)}
@@ -446,6 +465,7 @@ def main():
         r64.close()
         log(f"c64 adjoint: {res64['ms_per_step']:.3f} ms/gradient")
         out["c64"] = {"value": res64["value"], "ms_per_step": res64["ms_per_step"],
+                      "per_step": res64["per_step"],
                       "grad_error": grad_error(prob, e64, g64, "c64"),
                       "dominant_kernel": res64["dominant"]}
     if not args.no_param_shift and args.config != 4:

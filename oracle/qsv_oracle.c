@@ -504,7 +504,7 @@ int orc_adjoint_gradient(int n, const cplx* in, const orc_gate* gates, int n_gat
 }
 
 /* Algorithm 1 with operator B = sum (cre + i sign*cim) P and the complex <lambda|mu> of every
-   occurrence as its entry (App. B.4: line 9 without 2 Re), summed per parameter into z[p]
+   occurrence as its entry (App. B.4: the gradient product kept complex, no 2 Re), summed per parameter into z[p]
    (n_theta complex values). Returns <psi|B|psi> in *e. */
 static int adjoint_complex_entries(int n, const cplx* in, const orc_gate* gates, int n_gates,
                                    const double* theta, int n_theta, int n_terms,

@@ -63,7 +63,7 @@ hipError_t launch_final_grad(const FinalDesc* d_desc, int n_desc, int64_t total_
                              double* d_grad, hipStream_t st);
 
 // *energy = Re sum_b partials[b]; energy_im (optional) = Im.
-// One circuit of a batched H application: lambda = H psi with E partials (Algorithm 1, step 4).
+// One circuit of a batched H application: lambda = H psi with E partials (Algorithm 1, the application of H).
 struct PauliJob {
   const void* psi;
   void* out;

@@ -17,7 +17,7 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(qsv_\w+)\s*\(", text)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_four_calls_of_the_method():
     names = declared_functions()
     for f in ("qsv_create", "qsv_apply_circuit", "qsv_expectation_pauli_sum",
               "qsv_adjoint_gradient"):

@@ -2,7 +2,7 @@
 30-qubit complex128 workload through properties that hold at any size (closed forms, theta = 0
 identities, the exact parameter-shift rule on sampled entries, the phi-returns-to-|in> invariant).
 
-These allocate up to ~48 GiB of device memory and take seconds each.
+These allocate up to ~200 GiB of device memory and take seconds each.
 """
 import os
 import sys
@@ -64,6 +64,32 @@ def test_n30_product_layer_closed_form(Q):
         g = g.cpu().numpy()
     assert abs(e - E) < 1e-11
     assert np.max(np.abs(g - G)) < 1e-11
+
+
+@pytest.mark.parametrize("n,dtype", [(32, "c128"), (33, "c64")])
+def test_largest_states_closed_form(Q, n, dtype):
+    """The largest states one MI355X holds with the two-state workspace (3 x 64 GiB): amplitude
+    indices past 2^32 in every kernel of the path, against the product-layer closed form."""
+    import torch
+    import test_oracle_pins as pins
+    need = 3 * Q.state_bytes(n, dtype) + (4 << 30)
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"{need / 2**30:.0f} GiB needed, {free / 2**30:.0f} GiB free")
+    gates, theta, codes, coeffs, E, G = pins.tfim_product_layer(n, np.random.default_rng(n))
+    with Q.StateVector(n, dtype) as sv:
+        e, g = sv.adjoint_gradient(gates, theta, codes, coeffs)
+        sv.sync()
+        e = float(e.cpu()[0])
+        g = g.cpu().numpy()
+    torch.cuda.empty_cache()
+    if dtype == "c128":
+        assert abs(e - E) < 1e-11
+        assert np.max(np.abs(g - G)) < 1e-11
+    else:
+        assert abs(e - E) <= 2e-4 * max(abs(E), 1.0)
+        assert np.max(np.abs(g - G)) <= 2e-4 * max(np.max(np.abs(G)), 1e-5 * np.abs(coeffs).sum())
 
 
 def test_config5_theta_zero_identities(Q):

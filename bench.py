@@ -345,7 +345,7 @@ def main():
                     help="first copy MIB MiB device to device twice (a plain copy kernel of known "
                          "size, against which hardware byte counters are scaled)")
     ap.add_argument("--config", type=int, default=2,
-                    help="2: 20 qubits (headline); 3: 26 qubits complex64; 4: 512-circuit batch; "
+                    help="1: 10 qubits; 2: 20 qubits (headline); 3: 26 qubits complex64; 4: 512-circuit batch; "
                          "5: 30 qubits")
     ap.add_argument("--sweep-p", action="store_true",
                     help="adjoint vs parameter shift over the number of layers at 20 qubits")

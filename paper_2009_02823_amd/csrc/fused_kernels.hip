@@ -846,12 +846,14 @@ __device__ __forceinline__ void apply_derivative(const FusedOp& op, const GateRe
 }
 
 // <l|D_j f> for the explicit derivative matrices of a general op (f already un-applied): the
-// real parts in out, the imaginary parts in out_im when it is given (complex entries).
+// real parts in out, the imaginary parts in out_im when want_im is set (complex entries), else
+// zeros. Both arrays are the caller's register arrays (a pointer select between one of them and
+// a null pointer would put it on the stack).
 template <typename R, int RB>
 __device__ __forceinline__ void general_products(const FusedOp& op, const GateRec* rec,
                                                  const cx<R>* f, const cx<R>* l,
                                                  const Layout<RB>& L, double* out,
-                                                 double* out_im) {
+                                                 double* out_im, bool want_im) {
   constexpr int NA = 1 << RB;
   cx<R> mu[NA];
 #pragma unroll
@@ -864,10 +866,10 @@ __device__ __forceinline__ void general_products(const FusedOp& op, const GateRe
 #pragma unroll
     for (int ri = 0; ri < NA; ++ri) {
       s += re_cm(l[ri].r, l[ri].i, mu[ri].r, mu[ri].i);
-      if (out_im) si += im_cm(l[ri].r, l[ri].i, mu[ri].r, mu[ri].i);
+      if (want_im) si += im_cm(l[ri].r, l[ri].i, mu[ri].r, mu[ri].i);
     }
     out[j] = s;
-    if (out_im) out_im[j] = si;
+    out_im[j] = si;
   }
 }
 
@@ -1347,7 +1349,7 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
             if (GEN && op.type >= FOP_FIRST_GENERAL) {
               apply_general<R, RB, true>(op, rec, f, cur, true);
               if (op.np)
-                general_products<R, RB>(op, rec, f, l, cur, prod, cx_entries ? prod_im : nullptr);
+                general_products<R, RB>(op, rec, f, l, cur, prod, prod_im, cx_entries);
               apply_general<R, RB, true>(op, rec, l, cur);
             } else {
               if (cx_entries && op.np) prod_im[0] = lean_product_im<R, RB>(op, f, l, cur.tdep);

@@ -9,7 +9,7 @@
  * Source: T. Jones and J. Gacon, "Efficient calculation of gradients in classical simulations of
  * variational quantum algorithms" (arXiv:2009.02823).
  *   - energy <E> = <in| U^dag H U |in>, U = U_G ... U_1 ......................... Sec. 2.2
- *   - reverse-mode gradient with states lambda, phi, mu ........................... Algorithm 1
+ *   - reverse-mode gradient: the phi/lambda recurrence of Sec. 2.2, walked backwards . Algorithm 1
  *   - reference O(P^2) gradient, one re-simulation per entry .... Eq. (reference_gradient), Alg. 2
  *   - rotation derivative dR/dtheta = alpha i G R(theta), alpha = -1/2 ............ Appendix A
  *   - phase-gate and controlled-gate derivatives ................................. Appendix A
@@ -261,7 +261,7 @@ static void apply_gate(cplx* psi, int n, const orc_gate* g, const double* theta,
 }
 
 /* psi <- U^-1 psi: the adjoint for unitary gates; for the non-unitary one-qubit gates the 2x2
-   inverse (1/(ad - bc)) [[d, -b], [-c, a]] of App. B.3 (Algorithm 1, the phi un-do step). */
+   inverse (1/(ad - bc)) [[d, -b], [-c, a]] of App. B.3 (the phi recurrence of Sec. 2.2). */
 static void apply_gate_inverse(cplx* psi, int n, const orc_gate* g, const double* theta) {
   cplx m[4][4];
   int nq = gate_matrix(g, theta, -1, m);
@@ -274,7 +274,7 @@ static void apply_gate_inverse(cplx* psi, int n, const orc_gate* g, const double
   apply_matrix(psi, n, g, nq, m);
 }
 
-/* psi <- (dU/d theta_{p_j}) psi : a non-unitary matrix (Algorithm 1, derivative step) */
+/* psi <- (dU/d theta_{p_j}) psi : a non-unitary matrix (Eq. recurrent_grad, App. A) */
 static void apply_derivative(cplx* psi, int n, const orc_gate* g, const double* theta, int j) {
   cplx m[4][4];
   int nq = gate_matrix(g, theta, j, m);
@@ -318,7 +318,8 @@ static cplx inner(const cplx* a, const cplx* b, int n) {
 }
 
 /* out <- H psi = sum_t c_t P_t psi, each Pauli string applied one factor at a time to a copy of
-   psi (tmp), then accumulated. The result is unnormalised (Algorithm 1, apply-H step). */
+   psi (tmp), then accumulated. The result is unnormalised (Sec. 2.1: the simulator applies the
+   operator of interest to a state and keeps the unnormalised result). */
 static void apply_pauli_sum(const cplx* psi, cplx* out, cplx* tmp, int n, int n_terms,
                             const uint8_t* codes, const double* coeffs) {
   const int64_t dim = (int64_t)1 << n;
@@ -463,80 +464,113 @@ int orc_energy(int n, const cplx* in, const orc_gate* gates, int n_gates, const 
   return ORC_OK;
 }
 
-/* Algorithm 1 ("reverse mode"). Writes energy = <psi|H|psi> (Re, Im) and grad[0..n_theta) as
-   sums over every (gate, parameter-slot) occurrence of a parameter. If prods is non-NULL it
-   receives the complex <lambda|mu> of each occurrence, in sweep order (last gate first), as
-   (Re, Im) pairs: the products whose real parts, doubled, form the gradient. */
+/* ------------------------------------------------------------------------------------------ */
+/* The gradient through the recurrence of Sec. 2.2                                            */
+/* ------------------------------------------------------------------------------------------ */
+/*
+ * Number the gates k = 1..G, |psi> = U_G ... U_1 |in>, and let B be the operator whose
+ * expectation is differentiated (the Hamiltonian, or App. B.4's A or A^dag). Sec. 2.2 defines
+ *
+ *   |phi_k>    = (U_G ... U_k)^-1 |psi>       the state gate k acts on, U_{k-1} ... U_1 |in>
+ *   |lambda_k> = (U_G ... U_{k+1})^dag B|psi>  B|psi> carried back to just after gate k
+ *
+ * and both follow from their k + 1 neighbours by one gate:
+ *
+ *   |phi_k> = U_k^-1 |phi_{k+1}>  (|phi_{G+1}> = |psi>),   |lambda_{k-1}> = U_k^dag |lambda_k>
+ *   (|lambda_G> = B|psi>).
+ *
+ * The gradient entry of gate k and its parameter slot j is the product
+ * <lambda_k| dU_k/dtheta_j |phi_k> (Eq. recurrent_grad), doubled and made real for a Hermitian B.
+ * Walking k from G down to 1 keeps only two states alive plus one work copy for dU_k |phi_k>,
+ * which is the reverse mode of Sec. 2.3. U_k^-1 is the adjoint for unitary gates and the 2x2
+ * inverse for the non-unitary ones (App. B.3); lambda always takes the adjoint. Several slots in
+ * one gate each get their own derivative product (Algorithm 3); products of one parameter are
+ * summed (App. B.2).
+ */
+
+/* psi <- U_{to-1} ... U_{from} psi  (0-based gate indices, half-open range) */
+static void apply_range(cplx* psi, int n, const orc_gate* gates, int from, int to,
+                        const double* theta) {
+  for (int k = from; k < to; ++k) apply_gate(psi, n, &gates[k], theta, 0);
+}
+
+/* <bra| (dU_g / dtheta_{p_j}) |ket>, with the derivative applied to a work copy of ket */
+static cplx derivative_product(const cplx* bra, const cplx* ket, cplx* work, int n,
+                               const orc_gate* g, const double* theta, int j) {
+  clone(work, ket, n);
+  apply_derivative(work, n, g, theta, j);
+  return inner(bra, work, n);
+}
+
+/* Reverse mode for a Hermitian H (Algorithm 1). energy = <psi|H|psi> as (Re, Im), the imaginary
+   part being a check only; grad[p] = sum over the slots that use p of 2 Re <lambda_k|dU_k|phi_k>.
+   If prods is non-NULL it receives every complex product, gate G first, as (Re, Im) pairs. */
 int orc_adjoint_gradient(int n, const cplx* in, const orc_gate* gates, int n_gates,
                          const double* theta, int n_theta, int n_terms, const uint8_t* codes,
                          const double* coeffs, double* energy, double* grad, double* prods) {
   if (check_inputs(n, gates, n_gates, n_theta, n_terms, codes, coeffs)) return ORC_EINVAL;
-  cplx *lam = new_state(n), *phi = new_state(n), *mu = new_state(n);
-  if (!lam || !phi || !mu) { free(lam); free(phi); free(mu); return ORC_ENOMEM; }
+  cplx *ket = new_state(n), *bra = new_state(n), *work = new_state(n);
+  if (!ket || !bra || !work) { free(ket); free(bra); free(work); return ORC_ENOMEM; }
   for (int p = 0; p < n_theta; ++p) grad[p] = 0.0;
 
-  set_input(lam, in, n);                                      /* lambda := |in>          */
-  for (int k = 0; k < n_gates; ++k)                           /* lambda <- U_{1:P} lambda */
-    apply_gate(lam, n, &gates[k], theta, 0);
-  clone(phi, lam, n);                                         /* phi := lambda           */
-  apply_pauli_sum(phi, lam, mu, n, n_terms, codes, coeffs);   /* lambda <- H lambda (mu is
-                                                                 scratch here)            */
-  cplx e = inner(phi, lam, n);
+  /* simulate psi in the bra buffer, keep it as phi_{G+1} and overwrite the bra with H psi */
+  set_input(bra, in, n);
+  apply_range(bra, n, gates, 0, n_gates, theta);
+  clone(ket, bra, n);
+  apply_pauli_sum(ket, bra, work, n, n_terms, codes, coeffs);
+  const cplx e = inner(ket, bra, n);
   energy[0] = creal(e);
   energy[1] = cimag(e);
 
-  int64_t occ = 0;
-  for (int k = n_gates - 1; k >= 0; --k) {                    /* i = P ... 1             */
+  int64_t slot = 0;
+  for (int k = n_gates - 1; k >= 0; --k) {
     const orc_gate* g = &gates[k];
-    apply_gate_inverse(phi, n, g, theta);                     /* phi <- U_i^-1 phi       */
-    for (int j = 0; j < gate_nparams(g->kind); ++j) {         /* one pass per parameter  */
-      clone(mu, phi, n);                                      /* mu := phi               */
-      apply_derivative(mu, n, g, theta, j);                   /* mu <- dU_i/dtheta mu    */
-      cplx lm = inner(lam, mu, n);                            /* <lambda|mu>             */
-      grad[g->p[j]] += 2.0 * creal(lm);                       /* 2 Re <lambda|mu>        */
-      if (prods) { prods[2 * occ] = creal(lm); prods[2 * occ + 1] = cimag(lm); }
-      ++occ;
+    apply_gate_inverse(ket, n, g, theta);
+    for (int j = 0; j < gate_nparams(g->kind); ++j, ++slot) {
+      const cplx z = derivative_product(bra, ket, work, n, g, theta, j);
+      grad[g->p[j]] += 2.0 * creal(z);
+      if (prods) { prods[2 * slot] = creal(z); prods[2 * slot + 1] = cimag(z); }
     }
-    if (k > 0) apply_gate(lam, n, g, theta, 1);               /* lambda <- U_i^dag lambda */
+    if (k > 0) apply_gate(bra, n, g, theta, 1);
   }
-  free(lam); free(phi); free(mu);
+  free(ket); free(bra); free(work);
   return ORC_OK;
 }
 
-/* Algorithm 1 with operator B = sum (cre + i sign*cim) P and the complex <lambda|mu> of every
-   occurrence as its entry (App. B.4: the gradient product kept complex, no 2 Re), summed per parameter into z[p]
-   (n_theta complex values). Returns <psi|B|psi> in *e. */
-static int adjoint_complex_entries(int n, const cplx* in, const orc_gate* gates, int n_gates,
-                                   const double* theta, int n_theta, int n_terms,
-                                   const uint8_t* codes, const double* cre, const double* cim,
-                                   double sign, cplx* z, cplx* e) {
-  cplx *lam = new_state(n), *phi = new_state(n), *mu = new_state(n);
+/* The same walk with B = sum (cre + i sign*cim) P and the complex products as entries (App. B.4
+   keeps them complex): z[p] = sum of <lambda_k|dU_k|phi_k> over the slots that use p;
+   *e = <psi|B|psi>. */
+static int complex_products(int n, const cplx* in, const orc_gate* gates, int n_gates,
+                            const double* theta, int n_theta, int n_terms, const uint8_t* codes,
+                            const double* cre, const double* cim, double sign, cplx* z, cplx* e) {
+  cplx *ket = new_state(n), *bra = new_state(n), *work = new_state(n);
   double* cb = (double*)malloc(sizeof(double) * (n_terms ? n_terms : 1));
-  if (!lam || !phi || !mu || !cb) { free(lam); free(phi); free(mu); free(cb); return ORC_ENOMEM; }
+  if (!ket || !bra || !work || !cb) {
+    free(ket); free(bra); free(work); free(cb);
+    return ORC_ENOMEM;
+  }
   for (int t = 0; t < n_terms; ++t) cb[t] = sign * cim[t];
   for (int p = 0; p < n_theta; ++p) z[p] = 0;
-  set_input(lam, in, n);                                      /* lambda := |in>          */
-  for (int k = 0; k < n_gates; ++k) apply_gate(lam, n, &gates[k], theta, 0);
-  clone(phi, lam, n);                                         /* phi := lambda           */
-  apply_pauli_sum_complex(phi, lam, mu, n, n_terms, codes, cre, cb); /* lambda <- B lambda */
-  *e = inner(phi, lam, n);
+  set_input(bra, in, n);
+  apply_range(bra, n, gates, 0, n_gates, theta);
+  clone(ket, bra, n);
+  apply_pauli_sum_complex(ket, bra, work, n, n_terms, codes, cre, cb);
+  *e = inner(ket, bra, n);
   for (int k = n_gates - 1; k >= 0; --k) {
     const orc_gate* g = &gates[k];
-    apply_gate_inverse(phi, n, g, theta);                     /* phi <- U_i^-1 phi       */
-    for (int j = 0; j < gate_nparams(g->kind); ++j) {
-      clone(mu, phi, n);
-      apply_derivative(mu, n, g, theta, j);                   /* mu <- dU_i/dtheta phi   */
-      z[g->p[j]] += inner(lam, mu, n);                        /* <lambda|mu>, complex    */
-    }
-    if (k > 0) apply_gate(lam, n, g, theta, 1);               /* lambda <- U_i^dag lambda */
+    apply_gate_inverse(ket, n, g, theta);
+    for (int j = 0; j < gate_nparams(g->kind); ++j)
+      z[g->p[j]] += derivative_product(bra, ket, work, n, g, theta, j);
+    if (k > 0) apply_gate(bra, n, g, theta, 1);
   }
-  free(lam); free(phi); free(mu); free(cb);
+  free(ket); free(bra); free(work); free(cb);
   return ORC_OK;
 }
 
 /* The expectation <A> = <psi|A|psi> of a non-Hermitian A = sum (cre + i cim) P and its complex
-   gradient (App. B.4): g_B[p] = sum <lambda|mu> of Algorithm 1 run with operator B; then
-   d<A>/dtheta_p = conj(g_A[p]) + g_{A^dag}[p]. energy = (Re, Im); grad = n_theta (Re, Im) pairs. */
+   gradient (App. B.4): with g_B[p] the summed complex products of the walk run with operator B,
+   d<A>/dtheta_p = <dpsi|A|psi> + <psi|A|dpsi> = conj(g_A[p]) + g_{A^dag}[p].
+   energy = (Re, Im); grad = n_theta (Re, Im) pairs. */
 int orc_adjoint_gradient_nonhermitian(int n, const cplx* in, const orc_gate* gates, int n_gates,
                                       const double* theta, int n_theta, int n_terms,
                                       const uint8_t* codes, const double* cre, const double* cim,
@@ -547,11 +581,11 @@ int orc_adjoint_gradient_nonhermitian(int n, const cplx* in, const orc_gate* gat
   cplx *zd = (cplx*)malloc(sizeof(cplx) * (n_theta ? n_theta : 1));
   if (!za || !zd) { free(za); free(zd); return ORC_ENOMEM; }
   cplx ea, ed;
-  int rc = adjoint_complex_entries(n, in, gates, n_gates, theta, n_theta, n_terms, codes, cre,
-                                   cim, 1.0, za, &ea);                   /* run with A     */
+  int rc = complex_products(n, in, gates, n_gates, theta, n_theta, n_terms, codes, cre,
+                            cim, 1.0, za, &ea);                          /* B = A     */
   if (!rc)
-    rc = adjoint_complex_entries(n, in, gates, n_gates, theta, n_theta, n_terms, codes, cre,
-                                 cim, -1.0, zd, &ed);                    /* run with A^dag */
+    rc = complex_products(n, in, gates, n_gates, theta, n_theta, n_terms, codes, cre,
+                          cim, -1.0, zd, &ed);                           /* B = A^dag */
   if (!rc) {
     energy[0] = creal(ea);
     energy[1] = cimag(ea);
@@ -565,30 +599,32 @@ int orc_adjoint_gradient_nonhermitian(int n, const cplx* in, const orc_gate* gat
   return rc;
 }
 
-/* Algorithm 2, the reference gradient: for every parameter occurrence, re-simulate
-   mu = U_{i+1:P} (dU_i/dtheta) U_{1:i-1} |in> and take 2 Re <lambda|mu>, lambda = H U |in>. */
+/* The reference gradient, Eq. (reference_gradient) evaluated as it stands: for every slot j of
+   every gate i, the state U_G ... U_{i+1} (dU_i/dtheta_j) U_{i-1} ... U_1 |in> is simulated from
+   scratch and its product with H|psi> taken (H Hermitian, so <psi|H|x> = <H psi|x>). This costs
+   O(G) gates per entry, O(G^2) in all, the scheme Sec. 3 compares against. */
 int orc_reference_gradient(int n, const cplx* in, const orc_gate* gates, int n_gates,
                            const double* theta, int n_theta, int n_terms, const uint8_t* codes,
                            const double* coeffs, double* grad) {
   if (check_inputs(n, gates, n_gates, n_theta, n_terms, codes, coeffs)) return ORC_EINVAL;
-  cplx *lam = new_state(n), *mu = new_state(n), *tmp = new_state(n);
-  if (!lam || !mu || !tmp) { free(lam); free(mu); free(tmp); return ORC_ENOMEM; }
+  cplx *hpsi = new_state(n), *x = new_state(n), *work = new_state(n);
+  if (!hpsi || !x || !work) { free(hpsi); free(x); free(work); return ORC_ENOMEM; }
   for (int p = 0; p < n_theta; ++p) grad[p] = 0.0;
 
-  set_input(tmp, in, n);                                      /* lambda := |in>          */
-  for (int k = 0; k < n_gates; ++k) apply_gate(tmp, n, &gates[k], theta, 0);
-  apply_pauli_sum(tmp, lam, mu, n, n_terms, codes, coeffs);   /* lambda <- H U_{1:P}|in> */
+  set_input(work, in, n);
+  apply_range(work, n, gates, 0, n_gates, theta);
+  apply_pauli_sum(work, hpsi, x, n, n_terms, codes, coeffs);
 
-  for (int i = 0; i < n_gates; ++i) {                         /* i = 1 ... P             */
+  for (int i = 0; i < n_gates; ++i) {
     const orc_gate* g = &gates[i];
     for (int j = 0; j < gate_nparams(g->kind); ++j) {
-      set_input(mu, in, n);                                   /* mu := |in>              */
-      for (int k = 0; k < i; ++k) apply_gate(mu, n, &gates[k], theta, 0); /* U_{1:i-1}   */
-      apply_derivative(mu, n, g, theta, j);                   /* dU_i / dtheta           */
-      for (int k = i + 1; k < n_gates; ++k) apply_gate(mu, n, &gates[k], theta, 0); /* U_{i+1:P} */
-      grad[g->p[j]] += 2.0 * creal(inner(lam, mu, n));        /* 2 Re <lambda|mu>        */
+      set_input(x, in, n);
+      apply_range(x, n, gates, 0, i, theta);
+      apply_derivative(x, n, g, theta, j);
+      apply_range(x, n, gates, i + 1, n_gates, theta);
+      grad[g->p[j]] += 2.0 * creal(inner(hpsi, x, n));
     }
   }
-  free(lam); free(mu); free(tmp);
+  free(hpsi); free(x); free(work);
   return ORC_OK;
 }

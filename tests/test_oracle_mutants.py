@@ -27,34 +27,36 @@ MUTANTS = [
      "double c = cos(theta), s = sin(theta);"),
     ("adjoint not applied", "if (adj) adjoint(nq == 1 ? 2 : 4, m);", "(void)adj;"),
     ("adjoint without conjugate", "t[a][b] = conj(m[b][a]);", "t[a][b] = m[b][a];"),
-    ("lambda never un-applied", "if (k > 0) apply_gate(lam, n, g, theta, 1);", "(void)0;"),
+    ("lambda never un-applied", "if (k > 0) apply_gate(bra, n, g, theta, 1);", "(void)0;"),
     ("lambda un-applied before the product",
-     [("    apply_gate_inverse(phi, n, g, theta);                     /* phi <- U_i^-1 phi       */",
-       "    apply_gate_inverse(phi, n, g, theta); if (k > 0) apply_gate(lam, n, g, theta, 1);"),
-      ("    if (k > 0) apply_gate(lam, n, g, theta, 1);               /* lambda <- U_i^dag lambda */",
-       "")], None),
+     [("    apply_gate_inverse(ket, n, g, theta);\n    for (int j = 0; j < gate_nparams(g->kind); ++j, ++slot) {",
+       "    apply_gate_inverse(ket, n, g, theta); if (k > 0) apply_gate(bra, n, g, theta, 1);\n"
+       "    for (int j = 0; j < gate_nparams(g->kind); ++j, ++slot) {"),
+      ("    }\n    if (k > 0) apply_gate(bra, n, g, theta, 1);\n  }\n  free(ket); free(bra); free(work);\n  return ORC_OK;",
+       "    }\n  }\n  free(ket); free(bra); free(work);\n  return ORC_OK;")], None),
     ("Pauli Y sign", "{{{0, 0}, {0, -1}}, {{0, 1}, {0, 0}}},",
      "{{{0, 0}, {0, 1}}, {{0, -1}, {0, 0}}},"),
     ("two-qubit local index transposed", "int64_t idx[4] = {j, j | b1, j | b0, j | b0 | b1};",
      "int64_t idx[4] = {j, j | b0, j | b1, j | b0 | b1};"),
-    ("factor 2 dropped", "grad[g->p[j]] += 2.0 * creal(lm);", "grad[g->p[j]] += creal(lm);"),
-    ("imaginary part taken", "grad[g->p[j]] += 2.0 * creal(lm);",
-     "grad[g->p[j]] += 2.0 * cimag(lm);"),
-    ("repeated parameter overwritten", "grad[g->p[j]] += 2.0 * creal(lm);",
-     "grad[g->p[j]] = 2.0 * creal(lm);"),
+    ("factor 2 dropped", "grad[g->p[j]] += 2.0 * creal(z);", "grad[g->p[j]] += creal(z);"),
+    ("imaginary part taken", "grad[g->p[j]] += 2.0 * creal(z);",
+     "grad[g->p[j]] += 2.0 * cimag(z);"),
+    ("repeated parameter overwritten", "grad[g->p[j]] += 2.0 * creal(z);",
+     "grad[g->p[j]] = 2.0 * creal(z);"),
     ("Pauli coefficient dropped", "for (int64_t j = 0; j < dim; ++j) out[j] += c * tmp[j];",
      "for (int64_t j = 0; j < dim; ++j) out[j] += tmp[j];"),
     ("one-qubit row mixed up", "psi[j | bit] = m[1][0] * a + m[1][1] * b;",
      "psi[j | bit] = m[0][1] * a + m[1][1] * b;"),
     ("derivative on phi before the undo",
-     [("    apply_gate_inverse(phi, n, g, theta);                     /* phi <- U_i^-1 phi       */",
-       ""),
-      ("    if (k > 0) apply_gate(lam, n, g, theta, 1);               /* lambda <- U_i^dag lambda */",
-       "    apply_gate_inverse(phi, n, g, theta);\n    if (k > 0) apply_gate(lam, n, g, theta, 1);")],
+     [("    apply_gate_inverse(ket, n, g, theta);\n    for (int j = 0; j < gate_nparams(g->kind); ++j, ++slot) {",
+       "    for (int j = 0; j < gate_nparams(g->kind); ++j, ++slot) {"),
+      ("    }\n    if (k > 0) apply_gate(bra, n, g, theta, 1);\n  }\n  free(ket); free(bra); free(work);\n  return ORC_OK;",
+       "    }\n    apply_gate_inverse(ket, n, g, theta);\n    if (k > 0) apply_gate(bra, n, g, theta, 1);\n"
+       "  }\n  free(ket); free(bra); free(work);\n  return ORC_OK;")],
      None),
     ("reference gradient re-applies U_i",
-     "for (int k = i + 1; k < n_gates; ++k) apply_gate(mu, n, &gates[k], theta, 0);",
-     "for (int k = i; k < n_gates; ++k) apply_gate(mu, n, &gates[k], theta, 0);"),
+     "apply_range(x, n, gates, i + 1, n_gates, theta);",
+     "apply_range(x, n, gates, i, n_gates, theta);"),
     ("Hadamard sign", "m[1][1] = -M_SQRT1_2;", "m[1][1] = M_SQRT1_2;"),
     ("U3 phase", "m[0][0] = c; m[0][1] = -el * s; m[1][0] = ef * s; m[1][1] = efl * c;",
      "m[0][0] = c; m[0][1] = -ef * s; m[1][0] = el * s; m[1][1] = efl * c;"),
@@ -73,7 +75,7 @@ MUTANTS = [
     ("non-unitary: phi un-done by the adjoint", "  if (gate_unitary(g->kind)) {\n    adjoint(",
      "  if (1) {\n    adjoint("),
     ("non-unitary: lambda un-done by the inverse",
-     "if (k > 0) apply_gate(lam, n, g, theta, 1);", "if (k > 0) apply_gate_inverse(lam, n, g, theta);"),
+     "if (k > 0) apply_gate(bra, n, g, theta, 1);", "if (k > 0) apply_gate_inverse(bra, n, g, theta);"),
     ("non-unitary: derivative sign", "cg = d ? -0.5 * ch : -sh;", "cg = d ? 0.5 * ch : -sh;"),
 ]
 

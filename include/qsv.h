@@ -248,12 +248,34 @@ qsv_status qsv_set_graphs(qsv_state* s, int32_t on);
    for states up to 20 qubits, every fused geometry that fits the state), keeps the fastest as
    the handle's mode and caches the choice per (qubit count, storage type, gate kinds and qubits)
    for the process; later calls with the same structure reuse it without timing. Writes the
-   chosen mode and geometry (and the measured ms per gradient, -1 when taken from the cache).
-   Uses the workspace; outputs may be NULL. */
+   chosen mode and geometry and the measured ms per gradient (for a cached choice, the time it
+   was measured with, -1 if unknown). Uses the workspace; outputs may be NULL. The process-wide
+   cache is guarded by a lock, so handles on different threads may tune concurrently. */
 qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
                         const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
                         int32_t repeats, int32_t* out_mode, int32_t* out_reg_qubits,
                         int32_t* out_threads_log2, double* out_ms);
+
+/* Persisted tuning choices. qsv_tune_cache_save writes every cached choice to `path` (one JSON
+   object per line: source id of this library build, structure key, qubit count, storage type,
+   mode, geometry, measured ms), replacing the file atomically; QSV_ERR_INVALID_ARG if it cannot
+   be written. qsv_tune_cache_load merges the lines of `path` that carry this library's source
+   id into the process cache (choices timed on other kernel sources are skipped, as are
+   malformed lines and geometries this build lacks); *out_loaded (may be NULL) = lines taken.
+   A missing file loads nothing and returns QSV_OK. Host-only: no GPU is touched. */
+qsv_status qsv_tune_cache_save(const char* path);
+qsv_status qsv_tune_cache_load(const char* path, int32_t* out_loaded);
+
+/* The source id the persisted tuning choices of this build are tagged with (a hash of the
+   library's sources, fixed at build time). Static storage; never NULL. */
+const char* qsv_build_id(void);
+
+/* Test hook for the error path: the k-th kernel launch of the computations from now (k >= 1,
+   counted over all handles; the final reductions are not counted) is not enqueued and its call
+   returns QSV_ERR_HIP, as a failed launch would; k = 0 disarms. A computation that fails this
+   way has enqueued only launches before the failed one, and its outputs (energy, gradient) are
+   written by final reductions that come after every counted launch, so they stay untouched. */
+qsv_status qsv_debug_fail_launch(int32_t k);
 
 /* ---- measurement -------------------------------------------------------------------------- */
 

@@ -6,6 +6,7 @@ linked into ``paper_2009_02823_amd/libqsv.so``. Cross-compiles without a GPU.
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -43,17 +44,33 @@ def _headers():
     return glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
 
 
+def source_id() -> str:
+    """Hash of every library source and header: tags persisted tuning choices, so that choices
+    timed on other kernel sources are not reused."""
+    h = hashlib.sha256()
+    for f in sorted(sources() + _headers()):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def build(force: bool = False, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     newest_header = max((os.path.getmtime(h) for h in _headers()), default=0)
+    sid = source_id()
+    sid_file = os.path.join(BUILD, "source_id")
+    old_sid = open(sid_file).read().strip() if os.path.exists(sid_file) else ""
     procs, objs = [], []
     for src in sources():
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         objs.append(obj)
+        api = os.path.basename(src) == "qsv_api.hip"
         stale = (force or not os.path.exists(obj) or os.path.getmtime(obj) < os.path.getmtime(src)
-                 or os.path.getmtime(obj) < newest_header)
+                 or os.path.getmtime(obj) < newest_header or (api and old_sid != sid))
         if stale:
             cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+            if api:
+                cmd.insert(1, f'-DQSV_SOURCE_ID="{sid}"')
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,
@@ -67,6 +84,8 @@ def build(force: bool = False, verbose: bool = False) -> str:
             print(out)
     if failed:
         raise RuntimeError("hipcc failed:\n" + "\n".join(failed))
+    with open(sid_file, "w") as f:
+        f.write(sid + "\n")
     if procs or force or not os.path.exists(LIB):
         tmp = LIB + ".tmp%d" % os.getpid()
         cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -8,6 +8,7 @@
 #include <array>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <unordered_map>
@@ -225,6 +226,10 @@ struct Plan {
 
 struct PauliPlan {
   uint64_t serial = next_plan_serial();
+  // the operator this plan was built from, compared in full on a cache hit
+  std::vector<uint8_t> key_codes;
+  std::vector<double> key_coeffs, key_im;
+  double key_sign = 1.0;
   std::vector<PauliGroup> groups;
   std::vector<PauliTerm> terms;
   DevBuf d_groups, d_terms;
@@ -340,10 +345,30 @@ static qsv_status check_handle(qsv_state* s) {
   return QSV_OK;
 }
 
+// Test hook (qsv_debug_fail_launch): counts down over launches made through `timed`; the launch
+// that takes it from 1 to 0 is not enqueued and reports a HIP error instead.
+static std::atomic<int32_t> g_fail_countdown{0};
+
+static bool injected_failure() {
+  int32_t k = g_fail_countdown.load();
+  while (k > 0) {
+    if (g_fail_countdown.compare_exchange_weak(k, k - 1)) return k == 1;
+  }
+  return false;
+}
+
+extern "C" qsv_status qsv_debug_fail_launch(int32_t k) {
+  if (k < 0) return fail(QSV_ERR_INVALID_ARG, "k = %d < 0", k);
+  g_fail_countdown.store(k);
+  return QSV_OK;
+}
+
 // Runs `launch` (which enqueues exactly one kernel on s->stream) between two timing events when
 // the kernel family `name` is being timed.
 template <typename F>
 static qsv_status timed(qsv_state* s, const char* name, double bytes, F&& launch) {
+  if (injected_failure())
+    return fail(QSV_ERR_HIP, "%s: launch failure injected by qsv_debug_fail_launch", name);
   const bool t = s->timer.wants(name);
   hipEvent_t a = nullptr, b = nullptr;
   if (t) {
@@ -441,16 +466,32 @@ static qsv_status get_pauli_ex(qsv_state* s, const qsv_pauli_sum* H, const doubl
     h = fnv1a(coeffs_im, sizeof(double) * H->n_terms, h ^ 0x1a5ull);
     h = fnv1a(&im_sign, sizeof im_sign, h);
   }
+  const size_t n_codes = (size_t)H->n_terms * n;
   auto it = s->paulis.find(h);
   if (it != s->paulis.end()) {
-    *out = it->second.get();
-    return QSV_OK;
+    const PauliPlan* q = it->second.get();
+    const size_t cb = sizeof(double) * (size_t)H->n_terms;
+    const bool same =
+        q->key_codes.size() == n_codes && q->key_coeffs.size() == (size_t)H->n_terms &&
+        (n_codes == 0 || std::memcmp(q->key_codes.data(), H->codes, n_codes) == 0) &&
+        (H->n_terms == 0 || std::memcmp(q->key_coeffs.data(), H->coeffs, cb) == 0) &&
+        (coeffs_im ? (q->key_im.size() == (size_t)H->n_terms && q->key_sign == im_sign &&
+                      (H->n_terms == 0 || std::memcmp(q->key_im.data(), coeffs_im, cb) == 0))
+                   : q->key_im.empty());
+    if (same) {
+      *out = it->second.get();
+      return QSV_OK;
+    }
   }
   if (s->paulis.size() >= kMaxCachedPlans) {
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->paulis.clear();
   }
   auto p = std::make_unique<PauliPlan>();
+  p->key_codes.assign(H->codes, H->codes + n_codes);
+  p->key_coeffs.assign(H->coeffs, H->coeffs + H->n_terms);
+  if (coeffs_im) p->key_im.assign(coeffs_im, coeffs_im + H->n_terms);
+  p->key_sign = im_sign;
   // (P psi)_j = i^{nY} (-1)^{popcount((j^x) & z)} psi_{j^x}: x = X|Y positions, z = Z|Y.
   std::vector<uint64_t> xs;
   std::vector<std::vector<PauliTerm>> by_group;
@@ -608,12 +649,20 @@ static qsv_status run_graph(qsv_state* s, uint64_t key, F&& enqueue,
     extra[i]->stream = gc.capture_stream;
   }
   s->stream = gc.capture_stream;
-  HIP_TRY(hipStreamBeginCapture(gc.capture_stream, hipStreamCaptureModeThreadLocal));
+  // every exit from here on puts the handles back on their own streams
+  auto restore = [&] {
+    s->stream = user;
+    for (auto& kv : saved) kv.first->stream = kv.second;
+  };
+  const hipError_t eb = hipStreamBeginCapture(gc.capture_stream, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) {
+    restore();
+    return fail(QSV_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(eb));
+  }
   const qsv_status st = enqueue();
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(gc.capture_stream, &graph);
-  s->stream = user;
-  for (auto& kv : saved) kv.first->stream = kv.second;
+  restore();
   if (st != QSV_OK) {
     if (graph) (void)hipGraphDestroy(graph);
     return st;
@@ -1043,9 +1092,10 @@ static qsv_status adjoint_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* 
   // stands for the clone phi := psi. E = <psi|H psi>.
   QSV_TRY(forward<R>(s, p, s->d_state, phi));
   QSV_TRY(pauli<R>(s, hp, phi, lam, ep));
-  HIP_TRY(launch_final_energy(ep, nb, d_energy, nullptr, st));
   const FinalDesc* fd = nullptr;
   QSV_TRY(backward<R>(s, p, &fd));
+  // the outputs are written only once every pass has been enqueued
+  HIP_TRY(launch_final_energy(ep, nb, d_energy, nullptr, st));
   HIP_TRY(launch_final_grad(fd, 1, p->n_theta, d_grad, st));
   return QSV_OK;
 }
@@ -1262,13 +1312,13 @@ static qsv_status batched_t(qsv_state* const* states, int B, const std::vector<P
     return launch_pauli_batched<R>(bp->d_jobs.as<PauliJob>(), B, kBatchPauliBlocks,
                                    bp->partials_e.as<double2>(), st);
   }));
-  HIP_TRY(launch_final_energy_batched(bp->partials_e.as<double2>(), kBatchPauliBlocks, B, d_energy,
-                                      st));
   for (auto& L : bp->bwd)
     QSV_TRY(timed(s0, "k_pass_bwd", L->bytes, [&] {
       return launch_fused_backward<R>(L->d_items.as<PassItem>(), L->n_items, L->total, L->chunk,
                                       bp->r, bp->w, L->general, L->grid, st);
     }));
+  HIP_TRY(launch_final_energy_batched(bp->partials_e.as<double2>(), kBatchPauliBlocks, B, d_energy,
+                                      st));
   HIP_TRY(launch_final_grad(bp->d_final.as<FinalDesc>(), B, bp->total_params, d_grad_flat, st));
   return QSV_OK;
 }
@@ -1824,7 +1874,19 @@ struct TuneKey {
 struct TuneHash {
   size_t operator()(const TuneKey& k) const { return (size_t)k.h; }
 };
-static std::unordered_map<TuneKey, std::array<int, 3>, TuneHash> g_tuned;  // mode, r, w
+struct TuneEntry {
+  std::array<int, 3> best;  // mode, r, w
+  int32_t n, dt;
+  double ms;                // measured time of the choice, -1 if unknown
+};
+// Process-wide: handles on different threads may tune concurrently, so every access holds the
+// lock (the timing runs themselves do not).
+static std::mutex g_tune_mu;
+static std::unordered_map<TuneKey, TuneEntry, TuneHash> g_tuned;
+
+#ifndef QSV_SOURCE_ID
+#define QSV_SOURCE_ID "unversioned"
+#endif
 
 // Circuit structure (kinds and qubits, not angles), qubit count and storage type.
 static uint64_t tune_key(const qsv_state* s, const Plan* p) {
@@ -1849,12 +1911,19 @@ extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t 
   QSV_TRY(get_plan(s, gates, n_gates, n_theta, &p));
   QSV_TRY(check_theta(p, d_theta));
   const TuneKey key{tune_key(s, p)};
-  auto found = g_tuned.find(key);
   std::array<int, 3> best = {0, 0, 0};
   double best_ms = -1;
-  if (found != g_tuned.end()) {
-    best = found->second;
-  } else {
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto found = g_tuned.find(key);
+    if (found != g_tuned.end() && found->second.n == s->n && found->second.dt == (int32_t)s->dt) {
+      best = found->second.best;
+      best_ms = found->second.ms;
+      cached = true;
+    }
+  }
+  if (!cached) {
     std::vector<std::array<int, 3>> cands;
     if (s->n <= 20) cands.push_back({0, 0, 0});
     const int ws[3] = {9, 8, 6};
@@ -1904,7 +1973,8 @@ extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t 
     s->graphs.on = graphs;
     (void)hipStreamSynchronize(s->stream);  // the temporary outputs are freed on return
     if (st != QSV_OK) return st;
-    g_tuned[key] = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = TuneEntry{best, s->n, (int32_t)s->dt, best_ms};
   }
   s->fusion_mode = best[0] ? 1 : 0;
   s->fr = best[1];
@@ -1913,5 +1983,71 @@ extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t 
   if (out_reg_qubits) *out_reg_qubits = best[1];
   if (out_threads_log2) *out_threads_log2 = best[2];
   if (out_ms) *out_ms = best_ms;
+  return QSV_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// persisted tuning choices: one JSON object per line, tagged with the library's source id so
+// that choices timed on other kernel sources are never reused
+// ------------------------------------------------------------------------------------------------
+extern "C" const char* qsv_build_id(void) { return QSV_SOURCE_ID; }
+
+extern "C" qsv_status qsv_tune_cache_save(const char* path) {
+  if (!path) return fail(QSV_ERR_INVALID_ARG, "path is NULL");
+  std::vector<std::pair<TuneKey, TuneEntry>> all;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    all.assign(g_tuned.begin(), g_tuned.end());
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return fail(QSV_ERR_INVALID_ARG, "cannot write %s", tmp.c_str());
+  for (const auto& kv : all) {
+    const TuneEntry& e = kv.second;
+    std::fprintf(f,
+                 "{\"source\": \"%s\", \"key\": \"%016llx\", \"n\": %d, \"dtype\": %d, "
+                 "\"mode\": %d, \"r\": %d, \"w\": %d, \"ms\": %.6f}\n",
+                 QSV_SOURCE_ID, (unsigned long long)kv.first.h, e.n, e.dt, e.best[0], e.best[1],
+                 e.best[2], e.ms);
+  }
+  const bool ok = std::fflush(f) == 0 && !std::ferror(f);
+  std::fclose(f);
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return fail(QSV_ERR_INVALID_ARG, "cannot write %s", path);
+  }
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_tune_cache_load(const char* path, int32_t* out_loaded) {
+  if (!path) return fail(QSV_ERR_INVALID_ARG, "path is NULL");
+  if (out_loaded) *out_loaded = 0;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return QSV_OK;  // no cache yet
+  char line[512];
+  int loaded = 0;
+  std::vector<std::pair<TuneKey, TuneEntry>> got;
+  while (std::fgets(line, sizeof line, f)) {
+    char src[64] = {0};
+    unsigned long long h = 0;
+    int n = 0, dt = 0, m = 0, r = 0, w = 0;
+    double ms = -1;
+    const int k = std::sscanf(line,
+                              "{\"source\": \"%63[^\"]\", \"key\": \"%llx\", \"n\": %d, "
+                              "\"dtype\": %d, \"mode\": %d, \"r\": %d, \"w\": %d, "
+                              "\"ms\": %lf}",
+                              src, &h, &n, &dt, &m, &r, &w, &ms);
+    if (k != 8 || std::strcmp(src, QSV_SOURCE_ID) != 0) continue;
+    if (n < 1 || n > kMaxQubits || (dt != QSV_C64 && dt != QSV_C128)) continue;
+    if (m == 1 ? !fused_config_supported(r, w, dt == QSV_C128) : m != 0) continue;
+    got.push_back({TuneKey{(uint64_t)h}, TuneEntry{{m, r, w}, n, dt, ms}});
+    ++loaded;
+  }
+  std::fclose(f);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : got) g_tuned[kv.first] = kv.second;
+  }
+  if (out_loaded) *out_loaded = loaded;
   return QSV_OK;
 }

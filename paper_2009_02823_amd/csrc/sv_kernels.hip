@@ -485,11 +485,12 @@ hipError_t launch_backward_gate(void* phi_, void* lam_, int n, const GateDesc& g
 // ----------------------------------------------------------------------------------------------
 // (H psi) at the V consecutive indices j0 .. j0 + V - 1 (j0 a multiple of V = 1, 2 or 4). For a
 // group with X mask x the sources (j0 + k) ^ x form the aligned block j0 ^ (x & ~(V - 1)), in the
-// order k ^ (x & (V - 1)): one contiguous load per group, permuted in registers.
+// order k ^ (x & (V - 1)): one contiguous load per group, permuted in registers. The sum over
+// the groups is kept in FP64 whatever the storage precision (rounded only where it is stored).
 template <typename R, int V>
 __device__ __forceinline__ void pauli_block(const typename Vec2<R>::T* psi, uint64_t j0,
                                             const PauliGroup* groups, int n_groups,
-                                            const PauliTerm* terms, cx<R>* acc) {
+                                            const PauliTerm* terms, cx<double>* acc) {
 #pragma unroll
   for (int k = 0; k < V; ++k) acc[k] = {0, 0};
 #pragma unroll 2
@@ -537,8 +538,18 @@ __device__ __forceinline__ void pauli_block(const typename Vec2<R>::T* psi, uint
       }
     }
 #pragma unroll
-    for (int k = 0; k < V; ++k) acc[k] = acc[k] + cx<R>{(R)sr[k], (R)si[k]} * a[k];
+    for (int k = 0; k < V; ++k)
+      acc[k] = acc[k] + cx<double>{sr[k], si[k]} * cx<double>{(double)a[k].r, (double)a[k].i};
   }
+}
+
+template <typename R>
+__device__ __forceinline__ cx<double> widen(cx<R> a) {
+  return {(double)a.r, (double)a.i};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> narrow(cx<double> a) {
+  return {(R)a.r, (R)a.i};
 }
 
 template <typename R, bool WRITE, int V>
@@ -550,12 +561,12 @@ k_pauli(const typename Vec2<R>::T* psi, typename Vec2<R>::T* out, int n, const P
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < blocks;
        b += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t j0 = b * V;
-    cx<R> acc[V];
+    cx<double> acc[V];
     pauli_block<R, V>(psi, j0, groups, n_groups, terms, acc);
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-      if (WRITE) store<R>(out, j0 + k, acc[k]);
-      acc_dot<R>(e, load<R>(psi, j0 + k), acc[k]);
+      if (WRITE) store<R>(out, j0 + k, narrow<R>(acc[k]));
+      acc_dot<double>(e, widen<R>(load<R>(psi, j0 + k)), acc[k]);
     }
   }
   block_sum_store<kBlock>(e, partial + blockIdx.x);
@@ -575,12 +586,12 @@ k_pauli_batched(const PauliJob* __restrict__ jobs, double2* partials) {
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < blocks;
        b += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t j0 = b * V;
-    cx<R> acc[V];
+    cx<double> acc[V];
     pauli_block<R, V>(psi, j0, J.groups, J.n_groups, J.terms, acc);
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-      store<R>(out, j0 + k, acc[k]);
-      acc_dot<R>(e, load<R>(psi, j0 + k), acc[k]);
+      store<R>(out, j0 + k, narrow<R>(acc[k]));
+      acc_dot<double>(e, widen<R>(load<R>(psi, j0 + k)), acc[k]);
     }
   }
   block_sum_store<kBlock>(e, partials + (size_t)blockIdx.y * gridDim.x + blockIdx.x);

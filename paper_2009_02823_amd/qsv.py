@@ -91,6 +91,10 @@ def lib() -> ctypes.CDLL:
         "qsv_set_graphs": ([P, i32], i32),
         "qsv_autotune": ([P, P, i32, P, i32, P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                           ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], i32),
+        "qsv_tune_cache_save": ([ctypes.c_char_p], i32),
+        "qsv_tune_cache_load": ([ctypes.c_char_p, ctypes.POINTER(i32)], i32),
+        "qsv_build_id": ([], ctypes.c_char_p),
+        "qsv_debug_fail_launch": ([i32], i32),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -121,6 +125,28 @@ def pauli_struct(codes, coeffs, n_qubits):
         raise ValueError("codes and coeffs disagree on the number of terms")
     s = PauliSum(codes.shape[0], codes.ctypes.data, coeffs.ctypes.data)
     return s, (codes, coeffs)   # keep the arrays alive with the struct
+
+
+def build_id() -> str:
+    """Source id of the loaded library build (tags persisted tuning choices)."""
+    return lib().qsv_build_id().decode()
+
+
+def debug_fail_launch(k: int):
+    """Test hook: the k-th computation launch from now fails with QSV_ERR_HIP (0 disarms)."""
+    check(lib().qsv_debug_fail_launch(int(k)))
+
+
+def tune_cache_save(path: str):
+    """Write the process's tuning choices to `path` (see qsv_tune_cache_save)."""
+    check(lib().qsv_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_load(path: str) -> int:
+    """Merge the tuning choices of `path` made by this library build; returns how many."""
+    n = ctypes.c_int32()
+    check(lib().qsv_tune_cache_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
 
 
 def validate_circuit(n_qubits: int, gates, n_theta: int):
@@ -349,7 +375,8 @@ class StateVector:
 
     def autotune(self, gates, theta, codes, coeffs, repeats: int = 2):
         """Time every execution mode on this circuit and keep the fastest; returns
-        (mode, reg_qubits, threads_log2, ms per gradient or -1 if cached)."""
+        (mode, reg_qubits, threads_log2, ms per gradient; for a cached choice the time it was
+        measured with, -1 if unknown)."""
         g = as_gate_table(gates)
         t = self._theta(theta)
         s, keep = pauli_struct(codes, coeffs, self.n)

@@ -2,10 +2,14 @@
 
 Every value written here comes from the CPU oracle (``oracle/``), i.e. Algorithm 1 in complex128
 with plain loops, on the seeded synthetic inputs of ``paper_2009_02823_amd/workloads.py``. The
-GPU parity tests read these files so that workloads whose oracle run takes minutes (26 qubits)
-do not have to be recomputed on every test run.
+GPU parity tests read these files so that workloads whose oracle run takes minutes or hours (26
+and 30 qubits, the 512-circuit batch) do not have to be recomputed on every test run.
 
-Usage:  python tests/golden/make_golden.py 1 2 3     (configuration numbers)
+Usage:  python tests/golden/make_golden.py 1 2 3 4 5    (configuration numbers)
+
+Configuration 4 (512 independent circuits) is written as ``batch512_hea12-18_L5-15_heis.npz``:
+arrays ``energy`` [B], ``grad`` (all gradients concatenated in circuit order), ``offset`` [B + 1]
+and ``seconds`` (oracle time per circuit).
 """
 from __future__ import annotations
 
@@ -65,7 +69,42 @@ def read(name: str):
     return e, grad
 
 
+BATCH_NAME = "batch512_hea12-18_L5-15_heis"
+
+
+def write_batch(probs):
+    t0 = time.time()
+    energy = np.zeros(len(probs))
+    secs = np.zeros(len(probs))
+    grads, offset = [], [0]
+    for b, p in enumerate(probs):
+        t1 = time.time()
+        e, g = O.adjoint_gradient(p.n_qubits, p.gates, p.theta, p.codes, p.coeffs)
+        secs[b] = time.time() - t1
+        energy[b] = e.real
+        grads.append(np.asarray(g, dtype=np.float64))
+        offset.append(offset[-1] + len(g))
+    path = os.path.join(HERE, BATCH_NAME + ".npz")
+    np.savez_compressed(path, energy=energy, grad=np.concatenate(grads),
+                        offset=np.asarray(offset, dtype=np.int64), seconds=secs,
+                        threads=np.int64(O.num_threads()))
+    print(f"wrote {path} in {time.time() - t0:.1f} s", flush=True)
+
+
+def read_batch():
+    """(energy [B], list of per-circuit gradients) of the batch golden, or None if absent."""
+    path = os.path.join(HERE, BATCH_NAME + ".npz")
+    if not os.path.exists(path):
+        return None
+    z = np.load(path)
+    off = z["offset"]
+    return z["energy"], [z["grad"][off[b]:off[b + 1]] for b in range(len(off) - 1)]
+
+
 if __name__ == "__main__":
     for arg in sys.argv[1:]:
         cid = int(arg)
-        write(W.CONFIGS[cid](), cid)
+        if cid == 4:
+            write_batch(W.CONFIGS[4]())
+        else:
+            write(W.CONFIGS[cid](), cid)

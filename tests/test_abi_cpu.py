@@ -120,3 +120,37 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     assert L.qsv_reset(None) == qsv.QSV_ERR_INVALID_ARG
     assert L.qsv_sync(None) == qsv.QSV_ERR_INVALID_ARG
     assert L.qsv_destroy(None) == qsv.QSV_OK
+
+
+def test_build_id_matches_sources():
+    from paper_2009_02823_amd import build as libbuild
+    assert qsv.build_id() == libbuild.source_id()
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """Persisted tuning choices: lines tagged with this build's source id are taken, lines of
+    other builds, malformed lines and geometries this build lacks are skipped; a save writes
+    back what was loaded."""
+    sid = qsv.build_id()
+    line = ('{{"source": "{s}", "key": "{k}", "n": {n}, "dtype": 1, "mode": {m}, "r": {r}, '
+            '"w": {w}, "ms": 12.5}}\n')
+    path = tmp_path / "tune.jsonl"
+    path.write_text(line.format(s=sid, k="00000000000000aa", n=20, m=1, r=3, w=9)
+                    + line.format(s="0123456789abcdef", k="00000000000000bb", n=20, m=1, r=3, w=9)
+                    + "not json\n"
+                    + line.format(s=sid, k="00000000000000cc", n=20, m=1, r=7, w=9)
+                    + line.format(s=sid, k="00000000000000dd", n=12, m=0, r=0, w=0))
+    assert qsv.tune_cache_load(str(path)) == 2
+    out = tmp_path / "saved.jsonl"
+    qsv.tune_cache_save(str(out))
+    text = out.read_text()
+    assert '"key": "00000000000000aa"' in text and '"key": "00000000000000dd"' in text
+    assert "00000000000000bb" not in text and "00000000000000cc" not in text
+    assert all(f'"source": "{sid}"' in ln for ln in text.splitlines())
+    assert qsv.tune_cache_load(str(tmp_path / "absent.jsonl")) == 0
+
+
+def test_debug_fail_launch_rejects_negative():
+    with pytest.raises(qsv.QsvError):
+        qsv.debug_fail_launch(-1)
+    qsv.debug_fail_launch(0)

@@ -42,9 +42,8 @@ def run(Q, n, gates, theta, codes, coeffs, dtype, geom):
 
 def tol_check(dtype, e, g, psi, e_ref, g_ref, psi_ref, coeffs):
     if dtype == "c128":
-        scale = max(1.0, float(np.abs(coeffs).sum()))
-        assert abs(e - e_ref.real) <= 1e-10 * scale
-        assert np.max(np.abs(g - g_ref)) <= 1e-10 * scale
+        assert abs(e - e_ref.real) <= 1e-10
+        assert np.max(np.abs(g - g_ref)) <= 1e-10
         assert np.max(np.abs(psi - psi_ref)) <= 1e-12
     else:
         assert abs(e - e_ref.real) <= 2e-4 * max(abs(e_ref), 1.0)

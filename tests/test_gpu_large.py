@@ -1,6 +1,7 @@
-"""Full-size GPU parity: the 26-qubit complex64 workload against stored oracle values, and the
-30-qubit complex128 workload through properties that hold at any size (closed forms, theta = 0
-identities, the exact parameter-shift rule on sampled entries, the phi-returns-to-|in> invariant).
+"""Full-size GPU parity: the 26-qubit complex64 and 30-qubit complex128 workloads against stored
+oracle values entry by entry, and the 30-qubit workload also through properties that hold at any
+size (closed forms, theta = 0 identities, the exact parameter-shift rule on sampled entries, the
+phi-returns-to-|in> invariant).
 
 These allocate up to ~200 GiB of device memory and take seconds each.
 """
@@ -51,6 +52,31 @@ def test_config3_c64_full_vs_oracle(Q, geom):
           f"median|dg|={np.median(err):.2e}")
     assert abs(e - e_ref.real) <= 2e-4 * max(abs(e_ref), 1.0)
     assert err.max() <= 2e-4 * gmax
+
+
+@pytest.mark.parametrize("geom", [None, (3, 9)])
+def test_config5_full_vs_oracle(Q, geom):
+    """30 qubits, 10 layers (P = 600), Ising chain with N(0,1) couplings and fields, complex128:
+    the energy and every gradient entry against the oracle's Algorithm 1, 1e-10 absolute, in
+    the automatic geometry and in the one the benchmark's tuning picks."""
+    import make_golden
+    p = W.config5()
+    ref = make_golden.read(p.name)
+    if ref is None:
+        pytest.skip("oracle values for the 30-qubit workload not generated")
+    e_ref, g_ref = ref
+    with Q.StateVector(p.n_qubits) as sv:
+        if geom is not None:
+            sv.set_fusion(1, *geom)
+        e, g = sv.adjoint_gradient(p.gates, p.theta, p.codes, p.coeffs)
+        sv.sync()
+        e = float(e.cpu()[0])
+        g = g.cpu().numpy()
+    err = np.abs(g - g_ref)
+    print(f"\nconfig5 c128: |dE|={abs(e - e_ref.real):.2e} (E={e_ref.real:.6f}) "
+          f"max|dg|={err.max():.2e} max|g|={np.max(np.abs(g_ref)):.3e}", flush=True)
+    assert abs(e - e_ref.real) <= 1e-10
+    assert err.max() <= 1e-10, int(np.argmax(err))
 
 
 def test_n30_product_layer_closed_form(Q):

@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C-ABI) against the CPU oracle on the same seeded inputs.
 
-Tolerances: complex128 storage max |dg| <= 1e-10 and |dE| <= 1e-10 (absolute; scaled by the
-Hamiltonian's 1-norm where that exceeds 1); complex64 storage with FP64 reductions
+Tolerances: complex128 storage max |dg| <= 1e-10 and |dE| <= 1e-10 (absolute); complex64
+storage with FP64 reductions
 max |dg| <= 2e-4 * max|g_oracle| and |dE| <= 2e-4 * max(|E|, 1).
 """
 import math
@@ -41,11 +41,10 @@ def gpu_adjoint(Q, n, gates, theta, codes, coeffs, dtype="c128", prep=None, geom
 
 
 def assert_c128(e_gpu, g_gpu, e_ref, g_ref, coeffs):
-    scale = max(1.0, float(np.abs(coeffs).sum()))
-    assert abs(e_gpu - e_ref.real) <= 1e-10 * scale, (e_gpu, e_ref)
+    assert abs(e_gpu - e_ref.real) <= 1e-10, (e_gpu, e_ref)
     if g_ref.size:
         err = np.max(np.abs(g_gpu - g_ref))
-        assert err <= 1e-10 * scale, err
+        assert err <= 1e-10, err
 
 
 def c64_grad_scale(g_ref, coeffs):
@@ -177,6 +176,33 @@ def test_invalid_call_leaves_outputs_untouched(Q):
             sv.adjoint_gradient(bad, [0.1, 0.2, 0.3], np.zeros((1, n), np.uint8), [1.0], e, g)
         sv.sync()
         assert float(e.cpu()[0]) == 7.0 and bool((g == 7.0).all())
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_failed_launch_leaves_outputs_untouched(Q, orc, k):
+    """A launch failure forced from the host (the k-th launch of the call is refused) makes
+    the call return QSV_ERR_HIP with the energy and gradient buffers as they were and |in>
+    unchanged; the next call on the same handle gives the oracle's result."""
+    import torch
+    p = W.config1()
+    with Q.StateVector(p.n_qubits) as sv:
+        psi0 = sv.state.clone()
+        e = torch.full((1,), 7.0, dtype=torch.float64, device=sv.device)
+        g = torch.full((p.n_params,), 7.0, dtype=torch.float64, device=sv.device)
+        Q.debug_fail_launch(k)
+        try:
+            with pytest.raises(Q.QsvError) as err:
+                sv.adjoint_gradient(p.gates, p.theta, p.codes, p.coeffs, e, g)
+        finally:
+            Q.debug_fail_launch(0)
+        assert err.value.status == Q.QSV_ERR_HIP
+        sv.sync()
+        assert float(e.cpu()[0]) == 7.0 and bool((g == 7.0).all())
+        assert torch.equal(sv.state, psi0)
+        sv.adjoint_gradient(p.gates, p.theta, p.codes, p.coeffs, e, g)
+        sv.sync()
+        e_ref, g_ref = orc.adjoint_gradient(p.n_qubits, p.gates, p.theta, p.codes, p.coeffs)
+        assert_c128(float(e.cpu()[0]), g.cpu().numpy(), e_ref, g_ref, p.coeffs)
 
 
 @pytest.mark.parametrize("dtype,geom", [("c128", None), ("c128", (3, 9)), ("c64", None),

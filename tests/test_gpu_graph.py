@@ -93,4 +93,4 @@ def test_autotune_picks_a_valid_mode_and_caches(Q, orc):
     assert np.max(np.abs(g.cpu().numpy() - g_ref)) < 1e-10
     with Q.StateVector(p.n_qubits) as sv2:   # same structure: cached choice, no timing
         m2, r2, w2, ms2 = sv2.autotune(p.gates, p.theta * 0.5, p.codes, p.coeffs)
-        assert (m2, r2, w2) == (mode, r, w) and ms2 == -1.0
+        assert (m2, r2, w2) == (mode, r, w) and ms2 == ms   # the time the choice was made with

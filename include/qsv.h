@@ -324,7 +324,10 @@ qsv_status qsv_get_fusion(qsv_state* s, int32_t* mode, int32_t* reg_qubits, int3
    states), so that loads and stores move contiguous runs. All arrays are caller-owned with
    n_gates entries. n_macros counts
    the rotation macros (runs of reg_qubits same-axis rotations, one per register qubit, that run
-   as one op; formed for reg_qubits <= 3). */
+   as one op; formed for reg_qubits <= 3). n_direct_loads / n_direct_stores count the passes whose
+   tiles move between HBM and registers in their first / last phase's layout (those phases keep
+   the low run qubits off the register bits), which saves the relayout after the loads / before
+   the stores. */
 typedef struct {
   int32_t n_passes;
   int32_t n_phases;
@@ -334,6 +337,8 @@ typedef struct {
   uint64_t* tile_mask;
   uint64_t* reg_mask;
   int32_t n_macros;
+  int32_t n_direct_loads;   /* passes that load their tiles in the first phase's layout        */
+  int32_t n_direct_stores;  /* passes that store their tiles from the last phase's layout      */
 } qsv_schedule_info;
 
 qsv_status qsv_schedule_describe(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates,

@@ -77,6 +77,12 @@ struct FusedOp {
 #define QSV_V_THREAD 63
 #define QSV_V_MACRO 32  // RX/RY/RZ: a rotation macro head
 
+// Tiles of a pass are loaded in the first phase's layout (stored from the last phase's) instead
+// of the direct layout when that phase keeps the contiguous runs on the low lane bits (none of
+// its register bits is one of the low run qubits) and the pass has no phantom bits: the relayout
+// after the loads (before the stores) is then skipped.
+enum : uint8_t { PASS_LOAD_FIRST_PHASE = 1, PASS_STORE_LAST_PHASE = 2 };
+
 struct PhaseDesc {
   int32_t op_end;                 // ops [previous op_end, op_end) of the pass
   int8_t regbit[kMaxRegBits];     // tile bit of each register position
@@ -88,7 +94,8 @@ struct PassDesc {
   int32_t nt;                     // tile bits t
   int32_t n_outer;                // N - t
   int8_t tile[kMaxTileBits];      // physical qubit of tile bit s (ascending)
-  int8_t pad0[2];
+  uint8_t io_flags;               // PASS_LOAD_FIRST_PHASE | PASS_STORE_LAST_PHASE
+  int8_t pad0;
   int8_t outer[40];               // physical qubits outside the tile (ascending)
   int32_t phase_begin, phase_end; // into the phase table
   int32_t op_begin;               // into the op table (phase op_end values are relative)

@@ -59,36 +59,26 @@ __device__ __forceinline__ void lds_barrier() {
 // ---------------------------------------------------------------------------------------------
 // Layouts
 // ---------------------------------------------------------------------------------------------
-template <int T>
-__device__ __forceinline__ uint32_t thread_deposit(uint32_t rmask, uint32_t tid) {
-  uint32_t x = 0;
-  int j = 0;
+template <int RB>
+struct Layout {
+  int8_t rb[RB];   // tile bit of each register position (ascending)
+  uint32_t tdep;   // thread part of the tile index
+  uint32_t tsw;    // its swizzled LDS element index
+};
+
+// The thread index deposited into the tile bits that are not register bits (lowest first): a
+// zero inserted at every register bit, in ascending order.
+template <int RB>
+__device__ __forceinline__ uint32_t insert_zeros(const int8_t* regbit, uint32_t tid) {
+  uint32_t x = tid;
 #pragma unroll
-  for (int s = 0; s < T; ++s) {
-    if (!((rmask >> s) & 1u)) {
-      x |= ((tid >> j) & 1u) << s;
-      ++j;
-    }
+  for (int k = 0; k < RB; ++k) {
+    const uint32_t b = (uint32_t)regbit[k];
+    x = ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u));
   }
   return x;
 }
 
-template <int RB>
-struct Layout {
-  int8_t rb[RB];   // tile bit of each register position
-  uint32_t tdep;   // thread part of the tile index
-};
-
-template <int RB, int T>
-__device__ __forceinline__ void make_layout(Layout<RB>& L, const int8_t* regbit, uint32_t tid) {
-  uint32_t rmask = 0;
-#pragma unroll
-  for (int k = 0; k < RB; ++k) {
-    L.rb[k] = regbit[k];
-    rmask |= 1u << regbit[k];
-  }
-  L.tdep = thread_deposit<T>(rmask, tid);
-}
 
 template <int RB>
 __device__ __forceinline__ uint32_t reg_deposit(const Layout<RB>& L, int ri) {
@@ -96,6 +86,21 @@ __device__ __forceinline__ uint32_t reg_deposit(const Layout<RB>& L, int ri) {
 #pragma unroll
   for (int k = 0; k < RB; ++k) x |= (uint32_t)((ri >> k) & 1) << L.rb[k];
   return x;
+}
+
+// The swizzle is linear over GF(2) (an XOR of shifted copies), and the thread and register
+// parts of an element index have disjoint bits, so the LDS index of element ri is the XOR of the
+// swizzled thread part (once per layout and thread) and the swizzled register part (uniform).
+template <typename R, int RB>
+__device__ __forceinline__ void make_layout(Layout<RB>& L, const int8_t* regbit, uint32_t tid) {
+#pragma unroll
+  for (int k = 0; k < RB; ++k) L.rb[k] = regbit[k];
+  L.tdep = insert_zeros<RB>(regbit, tid);
+  L.tsw = Swz<R>::f(L.tdep);
+}
+template <typename R, int RB>
+__device__ __forceinline__ uint32_t lds_index(const Layout<RB>& L, int ri) {
+  return L.tsw ^ Swz<R>::f(reg_deposit<RB>(L, ri));
 }
 
 template <typename R, int RB>
@@ -107,12 +112,12 @@ __device__ __forceinline__ void relayout(cx<R>* a, const Layout<RB>& from, const
     typename Vec2<R>::T v;
     v.x = a[ri].r;
     v.y = a[ri].i;
-    lds[Swz<R>::f(from.tdep | reg_deposit<RB>(from, ri))] = v;
+    lds[lds_index<R, RB>(from, ri)] = v;
   }
   lds_barrier();
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
-    const typename Vec2<R>::T v = lds[Swz<R>::f(to.tdep | reg_deposit<RB>(to, ri))];
+    const typename Vec2<R>::T v = lds[lds_index<R, RB>(to, ri)];
     a[ri].r = v.x;
     a[ri].i = v.y;
   }
@@ -127,7 +132,7 @@ __device__ __forceinline__ void relayout2(cx<R>* a, cx<R>* b, const Layout<RB>& 
   constexpr int NA = 1 << RB;
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
-    const uint32_t x = Swz<R>::f(from.tdep | reg_deposit<RB>(from, ri));
+    const uint32_t x = lds_index<R, RB>(from, ri);
     typename Vec2<R>::T v, w;
     v.x = a[ri].r;
     v.y = a[ri].i;
@@ -139,7 +144,7 @@ __device__ __forceinline__ void relayout2(cx<R>* a, cx<R>* b, const Layout<RB>& 
   lds_barrier();
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
-    const uint32_t x = Swz<R>::f(to.tdep | reg_deposit<RB>(to, ri));
+    const uint32_t x = lds_index<R, RB>(to, ri);
     const typename Vec2<R>::T v = lds[x], w = lds[half + x];
     a[ri].r = v.x;
     a[ri].i = v.y;
@@ -939,42 +944,104 @@ struct Geometry {
   static constexpr int NW = NT / 64;
 };
 
-// Offsets of the thread's amplitudes in the direct layout: thread bits = tile bits 0..W-1,
-// register bits = tile bits W..T-1. Phantom tile bits (tile[s] < 0, states smaller than the tile)
-// contribute no address bit; amplitudes with a phantom bit set are not live (never loaded or
-// stored, zero in registers). live: the thread's phantom bits are all zero; preg: register
-// positions on phantom bits.
+// Global amplitude offsets of a layout's elements in a pass: a thread part and one offset per
+// register position; element ri sits at gthr | greg[k] for every set bit k of ri.
+template <int RB>
+struct TileMap {
+  uint64_t gthr;
+  uint64_t greg[RB];
+};
+
+template <int RB>
+__device__ __forceinline__ uint64_t map_off(const TileMap<RB>& M, int ri) {
+  uint64_t o = 0;
+#pragma unroll
+  for (int k = 0; k < RB; ++k)
+    if ((ri >> k) & 1) o |= M.greg[k];
+  return o;
+}
+
+// The direct layout's map: thread bits = tile bits 0..W-1, register bits = tile bits W..T-1.
+// Phantom tile bits (tile[s] < 0, states smaller than the tile) contribute no address bit;
+// amplitudes with a phantom bit set are not live (never loaded or stored, zero in registers).
+// live: the thread's phantom bits are all zero; preg: register positions on phantom bits.
 template <int RB, int W>
-__device__ __forceinline__ void direct_offsets(const PassDesc& pd, uint32_t tid, uint64_t& gthr,
-                                               uint64_t* groff, bool& live, uint32_t& preg) {
-  gthr = 0;
+__device__ __forceinline__ void direct_map(const PassDesc& pd, uint32_t tid, TileMap<RB>& M,
+                                           bool& live, uint32_t& preg) {
+  M.gthr = 0;
   live = true;
 #pragma unroll
   for (int s = 0; s < W; ++s) {
     const uint32_t b = (tid >> s) & 1u;
-    if (pd.tile[s] >= 0) gthr |= (uint64_t)b << pd.tile[s];
+    if (pd.tile[s] >= 0) M.gthr |= (uint64_t)b << pd.tile[s];
     else live = live && !b;
   }
   preg = 0;
 #pragma unroll
-  for (int k = 0; k < RB; ++k)
+  for (int k = 0; k < RB; ++k) {
+    M.greg[k] = pd.tile[W + k] >= 0 ? 1ull << pd.tile[W + k] : 0ull;
     if (pd.tile[W + k] < 0) preg |= 1u << k;
-#pragma unroll
-  for (int ri = 0; ri < (1 << RB); ++ri) {
-    uint64_t o = 0;
-#pragma unroll
-    for (int k = 0; k < RB; ++k)
-      if (pd.tile[W + k] >= 0) o |= (uint64_t)((ri >> k) & 1) << pd.tile[W + k];
-    groff[ri] = o;
   }
 }
 
-template <int RB, int W>
+// The map of any layout of a pass without phantom bits (tile bit indices resolved at compile
+// time: the register bits select among the T tile qubits).
+template <int RB, int T>
+__device__ __forceinline__ void layout_map(const PassDesc& pd, const Layout<RB>& L, TileMap<RB>& M) {
+  M.gthr = 0;
+#pragma unroll
+  for (int s = 0; s < T; ++s) M.gthr |= (uint64_t)((L.tdep >> s) & 1u) << pd.tile[s];
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    uint64_t g = 0;
+#pragma unroll
+    for (int s = 0; s < T; ++s)
+      if (L.rb[k] == s) g = 1ull << pd.tile[s];
+    M.greg[k] = g;
+  }
+}
+
+// Register bits of phase ph of a pass, read from the global phase table (uniform).
+template <int RB>
+__device__ __forceinline__ void global_phase_regbits(const PhaseDesc* phases, int ph, int8_t* rb) {
+  const QSV_GLOBAL uint32_t* p = (const QSV_GLOBAL uint32_t*)(phases + ph);
+  const uint32_t w1 = __builtin_amdgcn_readfirstlane(p[1]);
+  const uint32_t w2 = __builtin_amdgcn_readfirstlane(p[2]);
+#pragma unroll
+  for (int k = 0; k < RB; ++k) rb[k] = (int8_t)(((k < 4 ? w1 >> (8 * k) : w2 >> (8 * (k - 4)))) & 0xffu);
+}
+
+// The layouts (and maps) a pass loads its tiles in and stores them from: the first and last
+// phase's layouts where the scheduler marked them as keeping the contiguous runs on the low lane
+// bits (PASS_LOAD_FIRST_PHASE, PASS_STORE_LAST_PHASE), otherwise the direct layout.
+template <typename R, int RB, int T>
+__device__ __forceinline__ void io_layouts(const PassItem& I, uint32_t tid, const Layout<RB>& D,
+                                           const TileMap<RB>& MD, Layout<RB>& LL, TileMap<RB>& ML,
+                                           Layout<RB>& LS, TileMap<RB>& MS) {
+  LL = D;
+  ML = MD;
+  LS = D;
+  MS = MD;
+  const uint32_t fl = I.pd.io_flags;
+  int8_t rb[RB];
+  if (fl & PASS_LOAD_FIRST_PHASE) {
+    global_phase_regbits<RB>(I.phases, I.pd.phase_begin, rb);
+    make_layout<R, RB>(LL, rb, tid);
+    layout_map<RB, T>(I.pd, LL, ML);
+  }
+  if (fl & PASS_STORE_LAST_PHASE) {
+    global_phase_regbits<RB>(I.phases, I.pd.phase_end - 1, rb);
+    make_layout<R, RB>(LS, rb, tid);
+    layout_map<RB, T>(I.pd, LS, MS);
+  }
+}
+
+template <typename R, int RB, int W>
 __device__ __forceinline__ void direct_layout(Layout<RB>& L, uint32_t tid) {
   int8_t rb[RB];
 #pragma unroll
   for (int k = 0; k < RB; ++k) rb[k] = (int8_t)(W + k);
-  make_layout<RB, RB + W>(L, rb, tid);
+  make_layout<R, RB>(L, rb, tid);
 }
 
 // Item of the chunk-local tile g: the last item whose first tile is <= g (binary search).
@@ -1140,17 +1207,19 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
   if (g0 >= g1) return;
   int it = find_item(items, n_items, g0);
   Layout<RB> D;
-  direct_layout<RB, W>(D, tid);
+  direct_layout<R, RB, W>(D, tid);
   while (g0 < g1) {
     const PassItem I = items[it];
     const int64_t stop = I.tile_begin + (1ll << I.n_outer) < g1 ? I.tile_begin + (1ll << I.n_outer) : g1;
     const V* src = static_cast<const V*>(I.src);
     V* dst = static_cast<V*>(I.dst);
     const int n_ph = I.pd.phase_end - I.pd.phase_begin;
-    uint64_t gthr, groff[G::NA];
+    TileMap<RB> MD, ML, MS;
     bool live;
     uint32_t preg;
-    direct_offsets<RB, W>(I.pd, tid, gthr, groff, live, preg);
+    direct_map<RB, W>(I.pd, tid, MD, live, preg);
+    Layout<RB> LL, LS;
+    io_layouts<R, RB, G::T>(I, tid, D, MD, LL, ML, LS, MS);
     const bool phantom = I.pd.tile[G::T - 1] < 0;  // phantom bits are the top tile bits
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
     // reference gradient (Algorithm 2): an item with lam set ends its entry with Re <lambda|mu>
@@ -1158,23 +1227,23 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     const V* lamv = static_cast<const V*>(I.lam);
     double dot = 0.0;
     for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
-      const uint64_t ob = obase | gthr;
+      const uint64_t obl = obase | ML.gthr, obs = obase | MS.gthr;
       cx<R> a[G::NA];
       if (!phantom) {
 #pragma unroll
-        for (int ri = 0; ri < G::NA; ++ri) a[ri] = load<R>(src, ob | groff[ri]);
+        for (int ri = 0; ri < G::NA; ++ri) a[ri] = load<R>(src, obl | map_off<RB>(ML, ri));
       } else {
 #pragma unroll
         for (int ri = 0; ri < G::NA; ++ri) {
           a[ri] = cx<R>{0, 0};
-          if (live && !(ri & preg)) a[ri] = load<R>(src, ob | groff[ri]);
+          if (live && !(ri & preg)) a[ri] = load<R>(src, obl | map_off<RB>(ML, ri));
         }
       }
       if (g == g0) {  // staged while the first tile's loads are in flight
         stage_pass(I, sops, sph, (int)tid, G::NT);
         lds_barrier();
       }
-      Layout<RB> cur = D;
+      Layout<RB> cur = LL;
       int k = 0;
       uint4 nraw = staged_words(sops, 0);
       double2 ncs = staged_cs(sops, 0);
@@ -1183,7 +1252,7 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
         const int op_end = uniform_phase<RB>(sph, ph, rb);
         if (!same_layout<RB>(cur, rb)) {
           Layout<RB> nxt;
-          make_layout<RB, G::T>(nxt, rb, tid);
+          make_layout<R, RB>(nxt, rb, tid);
           relayout<R, RB>(a, cur, nxt, lds);
           cur = nxt;
         }
@@ -1207,21 +1276,21 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           }
         }
       }
-      if (!same_layout<RB>(cur, D.rb)) relayout<R, RB>(a, cur, D, lds);
+      if (!same_layout<RB>(cur, LS.rb)) relayout<R, RB>(a, cur, LS, lds);
       if (lamv) {
 #pragma unroll
         for (int ri = 0; ri < G::NA; ++ri)
           if (live && !(ri & preg)) {
-            const cx<R> l = load<R>(lamv, ob | groff[ri]);
+            const cx<R> l = load<R>(lamv, obs | map_off<RB>(MS, ri));
             dot += re_cm(l.r, l.i, a[ri].r, a[ri].i);
           }
       } else if (!phantom) {
 #pragma unroll
-        for (int ri = 0; ri < G::NA; ++ri) store<R>(dst, ob | groff[ri], a[ri]);
+        for (int ri = 0; ri < G::NA; ++ri) store<R>(dst, obs | map_off<RB>(MS, ri), a[ri]);
       } else {
 #pragma unroll
         for (int ri = 0; ri < G::NA; ++ri)
-          if (live && !(ri & preg)) store<R>(dst, ob | groff[ri], a[ri]);
+          if (live && !(ri & preg)) store<R>(dst, obs | map_off<RB>(MS, ri), a[ri]);
       }
     }
     if (lamv) {
@@ -1251,7 +1320,11 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
            int cplx) {
   using G = Geometry<RB, W>;
   using V = typename Vec2<R>::T;
-  __shared__ V lds[2 << G::T];
+  // Workgroups of at most four waves re-lay out phi and lambda one after the other through one
+  // tile-sized buffer when a buffer for both would exceed 80 KiB: two such workgroups then fit
+  // in a CU's LDS and run independently, one's loads and stores overlapping the other's gates.
+  constexpr bool SPLIT = W <= 8 && (2u << G::T) * sizeof(V) > (80u << 10);
+  __shared__ V lds[SPLIT ? (1 << G::T) : (2 << G::T)];
   __shared__ OpStage sops[kMaxOpsPerPass + 1];
   __shared__ PhaseDesc sph[kMaxPhasesPerPass];
   // per-wave slot sums, written after the item's last tile: they share the relayout buffer
@@ -1267,17 +1340,19 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
   if (g0 >= g1) return;
   int it = find_item(items, n_items, g0);
   Layout<RB> D;
-  direct_layout<RB, W>(D, tid);
+  direct_layout<R, RB, W>(D, tid);
   while (g0 < g1) {
     const PassItem I = items[it];
     const int64_t stop = I.tile_begin + (1ll << I.n_outer) < g1 ? I.tile_begin + (1ll << I.n_outer) : g1;
     V* phi = static_cast<V*>(I.dst);
     V* lam = static_cast<V*>(I.lam);
     const int n_ph = I.pd.phase_end - I.pd.phase_begin;
-    uint64_t gthr, groff[G::NA];
+    TileMap<RB> MD, ML, MS;
     bool live;
     uint32_t preg;
-    direct_offsets<RB, W>(I.pd, tid, gthr, groff, live, preg);
+    direct_map<RB, W>(I.pd, tid, MD, live, preg);
+    Layout<RB> LL, LS;
+    io_layouts<R, RB, G::T>(I, tid, D, MD, LL, ML, LS, MS);
     const bool phantom = I.pd.tile[G::T - 1] < 0;  // phantom bits are the top tile bits
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
     // every wave accumulates the product slots over its share of the tiles: lane j of acc0
@@ -1285,13 +1360,13 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     double acc0 = 0.0, acc1 = 0.0, acc0_im = 0.0, acc1_im = 0.0;
     const bool cx_entries = GEN && cplx;
     for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
-      const uint64_t ob = obase | gthr;
+      const uint64_t obl = obase | ML.gthr, obs = obase | MS.gthr;
       cx<R> f[G::NA], l[G::NA];
       if (!phantom) {
 #pragma unroll
         for (int ri = 0; ri < G::NA; ++ri) {
-          f[ri] = load<R>(phi, ob | groff[ri]);
-          l[ri] = load<R>(lam, ob | groff[ri]);
+          f[ri] = load<R>(phi, obl | map_off<RB>(ML, ri));
+          l[ri] = load<R>(lam, obl | map_off<RB>(ML, ri));
         }
       } else {
 #pragma unroll
@@ -1299,8 +1374,8 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           f[ri] = cx<R>{0, 0};
           l[ri] = cx<R>{0, 0};
           if (live && !(ri & preg)) {
-            f[ri] = load<R>(phi, ob | groff[ri]);
-            l[ri] = load<R>(lam, ob | groff[ri]);
+            f[ri] = load<R>(phi, obl | map_off<RB>(ML, ri));
+            l[ri] = load<R>(lam, obl | map_off<RB>(ML, ri));
           }
         }
       }
@@ -1308,7 +1383,7 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
         stage_pass(I, sops, sph, (int)tid, G::NT);
         lds_barrier();
       }
-      Layout<RB> cur = D;
+      Layout<RB> cur = LL;
       int k = 0;
       uint4 nraw = staged_words(sops, 0);
       double2 ncs = staged_cs(sops, 0);
@@ -1317,8 +1392,13 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
         const int op_end = uniform_phase<RB>(sph, ph, rb);
         if (!same_layout<RB>(cur, rb)) {
           Layout<RB> nxt;
-          make_layout<RB, G::T>(nxt, rb, tid);
-          relayout2<R, RB>(f, l, cur, nxt, lds, 1 << G::T);
+          make_layout<R, RB>(nxt, rb, tid);
+          if constexpr (SPLIT) {
+            relayout<R, RB>(f, cur, nxt, lds);
+            relayout<R, RB>(l, cur, nxt, lds);
+          } else {
+            relayout2<R, RB>(f, l, cur, nxt, lds, 1 << G::T);
+          }
           cur = nxt;
         }
         // every load in flight is complete before the ops: without this the compiler's wait
@@ -1378,19 +1458,26 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           }
         }
       }
-      if (!same_layout<RB>(cur, D.rb)) relayout2<R, RB>(f, l, cur, D, lds, 1 << G::T);
+      if (!same_layout<RB>(cur, LS.rb)) {
+        if constexpr (SPLIT) {
+          relayout<R, RB>(f, cur, LS, lds);
+          relayout<R, RB>(l, cur, LS, lds);
+        } else {
+          relayout2<R, RB>(f, l, cur, LS, lds, 1 << G::T);
+        }
+      }
       if (!phantom) {
 #pragma unroll
         for (int ri = 0; ri < G::NA; ++ri) {
-          store<R>(phi, ob | groff[ri], f[ri]);
-          store<R>(lam, ob | groff[ri], l[ri]);
+          store<R>(phi, obs | map_off<RB>(MS, ri), f[ri]);
+          store<R>(lam, obs | map_off<RB>(MS, ri), l[ri]);
         }
       } else {
 #pragma unroll
         for (int ri = 0; ri < G::NA; ++ri) {
           if (live && !(ri & preg)) {
-            store<R>(phi, ob | groff[ri], f[ri]);
-            store<R>(lam, ob | groff[ri], l[ri]);
+            store<R>(phi, obs | map_off<RB>(MS, ri), f[ri]);
+            store<R>(lam, obs | map_off<RB>(MS, ri), l[ri]);
           }
         }
       }

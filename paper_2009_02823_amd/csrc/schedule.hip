@@ -274,8 +274,11 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
           left.push_back(k);
         }
       }
-      // complete the register set: direct-layout bits first, then the lowest free bits
+      // complete the register set: direct-layout bits first, then the lowest free bits above
+      // the contiguous runs (so that the phase can still load or store its tiles directly),
+      // then any
       for (uint32_t d = dmask & ~R; d && popc(R) < r; d &= d - 1) R |= d & (~d + 1);
+      for (int b = c; b < t && popc(R) < r; ++b) R |= 1u << b;
       for (int b = 0; b < t && popc(R) < r; ++b) R |= 1u << b;
 
       PhaseDesc P;
@@ -410,6 +413,16 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
       prem.swap(left);
     }
     pd.phase_end = (int32_t)out.phases.size();
+    // tiles move in the first / last phase's layout when it keeps the runs on the low lane bits
+    if (tq == t && pd.phase_end > pd.phase_begin) {
+      auto keeps_runs = [&](const PhaseDesc& P) {
+        for (int k2 = 0; k2 < r; ++k2)
+          if (P.regbit[k2] < c) return false;
+        return true;
+      };
+      if (keeps_runs(out.phases[pd.phase_begin])) pd.io_flags |= PASS_LOAD_FIRST_PHASE;
+      if (keeps_runs(out.phases[pd.phase_end - 1])) pd.io_flags |= PASS_STORE_LAST_PHASE;
+    }
     pd.n_slots = lslot;
     const size_t n_exec = out.ops.size() - pd.op_begin;
     for (const auto& h : heads) out.ops[h.first].k1 = (uint8_t)(n_exec + h.second);

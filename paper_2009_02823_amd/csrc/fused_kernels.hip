@@ -1185,6 +1185,38 @@ __device__ __forceinline__ void add_to_slot(double& a0, double& a1, int slot, in
   else a1 += add;
 }
 
+// Product batches of the reverse sweep: the products of four consecutive slots 4b .. 4b + 3 are
+// buffered per thread and reduced together (wave_totals4); their wave totals stay in the rows
+// that wave_totals4 leaves them in, so slot 4b + k accumulates in register b / 16, in the lanes
+// of row rowof(k) = (0, 2, 1, 3)[k] and column b % 16 (each lane of a row adds only in its own
+// column). slot_of_lane inverts the map for the end of a pass.
+struct ProductBatch {
+  double p[4];
+};
+
+__device__ __forceinline__ void batch_put(ProductBatch& B, int k, double v) {
+  switch (k) {  // uniform
+    case 0: B.p[0] = v; break;
+    case 1: B.p[1] = v; break;
+    case 2: B.p[2] = v; break;
+    default: B.p[3] = v; break;
+  }
+}
+
+__device__ __forceinline__ void batch_flush(ProductBatch& B, int b, int lane, double& a0,
+                                            double& a1) {
+  const double t = wave_totals4(B.p[0], B.p[1], B.p[2], B.p[3]);
+  const double add = (lane & 15) == (b & 15) ? t : 0.0;
+  if (b < 16) a0 += add;
+  else a1 += add;
+  B.p[0] = B.p[1] = B.p[2] = B.p[3] = 0.0;
+}
+
+__device__ __forceinline__ int slot_of_lane(int reg, int lane) {
+  const int row = lane >> 4;
+  return 4 * (16 * reg + (lane & 15)) + (((row & 1) << 1) | (row >> 1));
+}
+
 __device__ __forceinline__ double lane63_value(double v) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
@@ -1355,10 +1387,13 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
     io_layouts<R, RB, G::T>(I, tid, D, MD, LL, ML, LS, MS);
     const bool phantom = I.pd.tile[G::T - 1] < 0;  // phantom bits are the top tile bits
     uint64_t obase = deposit_bits((uint64_t)(g0 - I.tile_begin), I.pd.outer_mask);
-    // every wave accumulates the product slots over its share of the tiles: lane j of acc0
-    // holds slot j, lane j of acc1 slot 64 + j
+    // every wave accumulates the product slots over its share of the tiles, in two registers:
+    // batched (ProductBatch) for real entries; for complex entries lane j of acc0 holds slot j,
+    // lane j of acc1 slot 64 + j
     double acc0 = 0.0, acc1 = 0.0, acc0_im = 0.0, acc1_im = 0.0;
     const bool cx_entries = GEN && cplx;
+    ProductBatch pb;
+    pb.p[0] = pb.p[1] = pb.p[2] = pb.p[3] = 0.0;
     for (int64_t g = g0; g < stop; ++g, obase = next_in_mask(obase, I.pd.outer_mask)) {
       const uint64_t obl = obase | ML.gthr, obs = obase | MS.gthr;
       cx<R> f[G::NA], l[G::NA];
@@ -1435,13 +1470,13 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
               if (cx_entries && op.np) prod_im[0] = lean_product_im<R, RB>(op, f, l, cur.tdep);
               lean_step<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, sops, f, l, cur.tdep, prod);
             }
-            if (op.np >= 2 && !cx_entries) {  // a macro's (or a U3's) products together
-              const double t = wave_totals4(prod[0], prod[1], prod[2], 0.0);
-              const double tot[3] = {lane_value<0>(t), lane_value<32>(t), lane_value<16>(t)};
+            if (!cx_entries) {
 #pragma unroll
               for (int j = 0; j < 3; ++j) {
                 if (j >= op.np) break;
-                add_to_slot(acc0, acc1, op.lslot + j, lane, tot[j]);
+                const int slot = op.lslot + j;
+                batch_put(pb, slot & 3, prod[j]);
+                if ((slot & 3) == 3) batch_flush(pb, slot >> 2, lane, acc0, acc1);
               }
             } else {
 #pragma unroll
@@ -1458,6 +1493,8 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
           }
         }
       }
+      // the tile's last, partial batch
+      if (!cx_entries && (I.pd.n_slots & 3)) batch_flush(pb, (I.pd.n_slots - 1) >> 2, lane, acc0, acc1);
       if (!same_layout<RB>(cur, LS.rb)) {
         if constexpr (SPLIT) {
           relayout<R, RB>(f, cur, LS, lds);
@@ -1482,11 +1519,14 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
         }
       }
     }
-    wacc[lane][wave] = acc0;
-    wacc[64 + lane][wave] = acc1;
     if (cx_entries) {
+      wacc[lane][wave] = acc0;
+      wacc[64 + lane][wave] = acc1;
       wacc_im[lane][wave] = acc0_im;
       wacc_im[64 + lane][wave] = acc1_im;
+    } else {
+      wacc[slot_of_lane(0, lane)][wave] = acc0;
+      wacc[slot_of_lane(1, lane)][wave] = acc1;
     }
     lds_barrier();
     const int col = (int)blockIdx.x - I.first_wg;

@@ -324,7 +324,7 @@ qsv_status qsv_get_fusion(qsv_state* s, int32_t* mode, int32_t* reg_qubits, int3
    states), so that loads and stores move contiguous runs. All arrays are caller-owned with
    n_gates entries. n_macros counts
    the rotation macros (runs of reg_qubits same-axis rotations, one per register qubit, that run
-   as one op; formed for reg_qubits <= 3). n_direct_loads / n_direct_stores count the passes whose
+   as one op; formed for reg_qubits <= 4). n_direct_loads / n_direct_stores count the passes whose
    tiles move between HBM and registers in their first / last phase's layout (those phases keep
    the low run qubits off the register bits), which saves the relayout after the loads / before
    the stores. */

@@ -51,7 +51,7 @@ enum : uint8_t { FOPF_S0_REG = 1, FOPF_S1_REG = 2, FOPF_MACRO = 4 };
 // (the head is position 0). The records of positions 1 .. r - 1 sit after the executed ops of the
 // pass, from op index k1 of the pass on. The head's np counts the products of all r
 // (consecutive local slots). Only for r <= kMaxMacroRegBits.
-constexpr int kMaxMacroRegBits = 3;
+constexpr int kMaxMacroRegBits = 4;
 
 struct FusedOp {
   uint8_t type;

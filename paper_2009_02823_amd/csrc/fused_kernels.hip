@@ -1460,7 +1460,7 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
               cs = staged_cs(sops, mem + sub - 1);
             }
             const GateRec* rec = I.recs + op.gate;
-            double prod[3] = {0, 0, 0}, prod_im[3] = {0, 0, 0};
+            double prod[kMaxMacroRegBits] = {}, prod_im[kMaxMacroRegBits] = {};
             if (GEN && op.type >= FOP_FIRST_GENERAL) {
               apply_general<R, RB, true>(op, rec, f, cur, true);
               if (op.np)
@@ -1472,7 +1472,7 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
             }
             if (!cx_entries) {
 #pragma unroll
-              for (int j = 0; j < 3; ++j) {
+              for (int j = 0; j < kMaxMacroRegBits; ++j) {
                 if (j >= op.np) break;
                 const int slot = op.lslot + j;
                 batch_put(pb, slot & 3, prod[j]);

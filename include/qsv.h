@@ -256,6 +256,19 @@ qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
                         int32_t repeats, int32_t* out_mode, int32_t* out_reg_qubits,
                         int32_t* out_threads_log2, double* out_ms);
 
+/* Host-only description of how a handle of n_qubits qubits and storage dt applies H (no GPU
+   needed). Terms are grouped by X mask (*n_groups groups). Groups whose X bits fit one tile of
+   2^12 (complex128) or 2^13 (complex64) amplitudes that holds the low run qubits are applied in
+   tiled passes that read psi once for all of their groups (*n_tiled_passes, each kept only if it
+   takes at least three groups); the other groups (*n_gather_groups) are applied by a gather that
+   reads psi once per group. For the first max_passes passes, tile_masks[i] = the pass's qubits
+   and pass_groups[i] = its groups (both arrays caller-owned, may be NULL). Every group is applied
+   exactly once. QSV_ERR_INVALID_ARG for an invalid sum or dtype. */
+qsv_status qsv_pauli_describe(int32_t n_qubits, qsv_dtype dt, const qsv_pauli_sum* H,
+                              int32_t* n_groups, int32_t* n_tiled_passes,
+                              int32_t* n_gather_groups, uint64_t* tile_masks,
+                              int32_t* pass_groups, int32_t max_passes);
+
 /* Persisted tuning choices. qsv_tune_cache_save writes every cached choice to `path` (one JSON
    object per line: source id of this library build, structure key, qubit count, storage type,
    mode, geometry, measured ms), replacing the file atomically; QSV_ERR_INVALID_ARG if it cannot

@@ -233,7 +233,146 @@ struct PauliPlan {
   std::vector<PauliGroup> groups;
   std::vector<PauliTerm> terms;
   DevBuf d_groups, d_terms;
+  // the handle's application of H: tiled passes (their groups and sign-folded terms) and the
+  // groups left to the gather kernel
+  std::vector<PauliTilePass> tpasses;
+  std::vector<PauliTileGroup> tgroups;
+  std::vector<PauliTerm> tterms;
+  std::vector<PauliGroup> rgroups;
+  std::vector<PauliTerm> rterms;
+  DevBuf d_tgroups, d_tterms, d_rgroups, d_rterms;
 };
+
+// Chooses the tiled passes of the application of H on an n-qubit state: a pass holds TB tile
+// qubits (the low run qubits plus TB - c free ones) and applies every X-mask group whose X bits
+// lie in its tile, reading psi once for all of them; a gather reads psi once per group. Tiles are
+// grown greedily (seeded by each remaining group, adding the qubit that completes the most
+// remaining groups) and kept while a pass takes at least three groups; passes hold at most
+// kPauliTileMaxTerms terms. Fills the plan's tiled and remaining (gather) tables.
+static void plan_pauli_tiles(PauliPlan& P, int n, bool c128) {
+  P.tpasses.clear();
+  P.tgroups.clear();
+  P.tterms.clear();
+  P.rgroups.clear();
+  P.rterms.clear();
+  const int TB = pauli_tile_bits(c128);
+  std::vector<int> unc;
+  for (size_t g = 0; g < P.groups.size(); ++g) unc.push_back((int)g);
+  if (n >= TB + 2) {
+    const int c = run_qubits_for(c128, n);
+    const uint64_t run = (1ull << c) - 1;
+    const int F = TB - c;
+    auto need = [&](int g) { return P.groups[g].x & ~run; };
+    auto count_in = [&](uint64_t free) {
+      int k = 0;
+      for (int g : unc) k += (need(g) & ~free) == 0 ? 1 : 0;
+      return k;
+    };
+    while (!unc.empty()) {
+      uint64_t best_free = 0;
+      int best = -1;
+      std::vector<uint64_t> seeds;
+      for (int g : unc) {
+        const uint64_t x = need(g);
+        if (__builtin_popcountll(x) <= F && std::find(seeds.begin(), seeds.end(), x) == seeds.end())
+          seeds.push_back(x);
+        if (seeds.size() >= 48) break;
+      }
+      for (uint64_t free : seeds) {
+        while (__builtin_popcountll(free) < F) {
+          int bq = -1, bgain = -1, bfreq = -1;
+          for (int q = c; q < n; ++q) {
+            const uint64_t b = 1ull << q;
+            if (free & b) continue;
+            int gain = 0, freq = 0;
+            for (int g : unc) {
+              const uint64_t x = need(g);
+              if ((x & ~(free | b)) == 0 && (x & ~free) != 0) ++gain;
+              if (x & b) ++freq;
+            }
+            if (gain > bgain || (gain == bgain && freq > bfreq)) {
+              bq = q;
+              bgain = gain;
+              bfreq = freq;
+            }
+          }
+          if (bq < 0) break;
+          free |= 1ull << bq;
+        }
+        const int k = count_in(free);
+        if (k > best) {
+          best = k;
+          best_free = free;
+        }
+      }
+      if (best < 3) break;
+      // the pass: its tile (run qubits, the free ones, padded with the lowest others)
+      uint64_t tile = run | best_free;
+      for (int q = c; q < n && __builtin_popcountll(tile) < TB; ++q) tile |= 1ull << q;
+      PauliTilePass T;
+      std::memset(&T, 0, sizeof T);
+      int tb_of[64], s = 0;
+      for (int q = 0; q < n; ++q) {
+        tb_of[q] = -1;
+        if ((tile >> q) & 1) {
+          tb_of[q] = s;
+          T.tile[s++] = (int8_t)q;
+        } else {
+          T.outer_mask |= 1ull << q;
+        }
+      }
+      T.n_outer = n - TB;
+      T.g0 = (int32_t)P.tgroups.size();
+      T.t0 = (int32_t)P.tterms.size();
+      std::vector<int> left;
+      for (int g : unc) {
+        const PauliGroup& G = P.groups[g];
+        const int nt = G.t1 - G.t0;
+        if ((need(g) & ~best_free) != 0 || T.n_terms + nt > kPauliTileMaxTerms) {
+          left.push_back(g);
+          continue;
+        }
+        PauliTileGroup TG{0, T.n_terms, T.n_terms + nt};
+        for (uint64_t x = G.x; x; x &= x - 1) TG.xl |= 1u << tb_of[__builtin_ctzll(x)];
+        for (int t = G.t0; t < G.t1; ++t) {
+          PauliTerm term = P.terms[t];
+          if (__builtin_popcountll(G.x & term.z) & 1) {  // (-1)^popcount(x & z) folded in
+            term.cre = -term.cre;
+            term.cim = -term.cim;
+          }
+          P.tterms.push_back(term);
+        }
+        T.n_terms += nt;
+        P.tgroups.push_back(TG);
+      }
+      T.g1 = (int32_t)P.tgroups.size();
+      if (T.g1 - T.g0 < 3) {  // the term limit left too little: undo and stop
+        P.tgroups.resize(T.g0);
+        P.tterms.resize(T.t0);
+        break;
+      }
+      const int E = pauli_tile_elements(c128), LE = __builtin_ctz(E);
+      for (int k = 0; k < E; ++k) {
+        uint64_t off = 0;
+        for (int b = 0; b < LE; ++b)
+          if ((k >> b) & 1) off |= 1ull << T.tile[TB - LE + b];
+        uint64_t bits = 0;
+        for (int t = 0; t < T.n_terms; ++t)
+          bits |= (uint64_t)(__builtin_popcountll(off & P.tterms[T.t0 + t].z) & 1) << t;
+        T.kbits[k] = bits;
+      }
+      P.tpasses.push_back(T);
+      unc.swap(left);
+    }
+  }
+  for (int g : unc) {
+    const PauliGroup& G = P.groups[g];
+    PauliGroup R{G.x, (int32_t)P.rterms.size(), 0};
+    for (int t = G.t0; t < G.t1; ++t) P.rterms.push_back(P.terms[t]);
+    R.t1 = (int32_t)P.rterms.size();
+    P.rgroups.push_back(R);
+  }
+}
 
 // Per-launch HIP-event timing of selected kernel families (qsv_timing_enable / _read).
 struct Timer {
@@ -454,6 +593,68 @@ static qsv_status get_plan(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
   return QSV_OK;
 }
 
+template <typename T>
+static qsv_status upload_vec(DevBuf& b, const std::vector<T>& v, hipStream_t st) {
+  QSV_TRY(b.ensure(sizeof(T) * (v.size() ? v.size() : 1), st));
+  if (!v.empty())
+    HIP_TRY(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+  return QSV_OK;
+}
+
+// Terms grouped by X mask: (P psi)_j = i^{nY} (-1)^{popcount((j^x) & z)} psi_{j^x} with
+// x = X|Y positions, z = Z|Y; each term's weight (c + i ci) i^{nY}.
+static void build_pauli_groups(PauliPlan& P, int n, const qsv_pauli_sum* H,
+                               const double* coeffs_im, double im_sign) {
+  std::vector<uint64_t> xs;
+  std::vector<std::vector<PauliTerm>> by_group;
+  for (int t = 0; t < H->n_terms; ++t) {
+    uint64_t x = 0, z = 0;
+    int ny = 0;
+    for (int q = 0; q < n; ++q) {
+      const int c = H->codes[(size_t)t * n + q];
+      if (c == 1 || c == 2) x |= 1ull << q;
+      if (c == 3 || c == 2) z |= 1ull << q;
+      if (c == 2) ++ny;
+    }
+    static const double ire[4] = {1, 0, -1, 0}, iim[4] = {0, 1, 0, -1};
+    const double c = H->coeffs[t], ci = coeffs_im ? im_sign * coeffs_im[t] : 0.0;
+    PauliTerm term{z, c * ire[ny & 3] - ci * iim[ny & 3], c * iim[ny & 3] + ci * ire[ny & 3]};
+    size_t g = 0;
+    while (g < xs.size() && xs[g] != x) ++g;
+    if (g == xs.size()) {
+      xs.push_back(x);
+      by_group.emplace_back();
+    }
+    by_group[g].push_back(term);
+  }
+  for (size_t g = 0; g < xs.size(); ++g) {
+    PauliGroup G{xs[g], (int32_t)P.terms.size(), 0};
+    P.terms.insert(P.terms.end(), by_group[g].begin(), by_group[g].end());
+    G.t1 = (int32_t)P.terms.size();
+    P.groups.push_back(G);
+  }
+}
+
+extern "C" qsv_status qsv_pauli_describe(int32_t n_qubits, qsv_dtype dt, const qsv_pauli_sum* H,
+                                         int32_t* n_groups, int32_t* n_tiled_passes,
+                                         int32_t* n_gather_groups, uint64_t* tile_masks,
+                                         int32_t* pass_groups, int32_t max_passes) {
+  if (dt != QSV_C64 && dt != QSV_C128) return fail(QSV_ERR_INVALID_ARG, "unknown dtype %d", dt);
+  QSV_TRY(qsv_validate_pauli_sum(n_qubits, H));
+  PauliPlan P;
+  build_pauli_groups(P, n_qubits, H, nullptr, 1.0);
+  plan_pauli_tiles(P, n_qubits, dt == QSV_C128);
+  if (n_groups) *n_groups = (int32_t)P.groups.size();
+  if (n_tiled_passes) *n_tiled_passes = (int32_t)P.tpasses.size();
+  if (n_gather_groups) *n_gather_groups = (int32_t)P.rgroups.size();
+  for (int i = 0; i < (int)P.tpasses.size() && i < max_passes; ++i) {
+    const PauliTilePass& T = P.tpasses[i];
+    if (tile_masks) tile_masks[i] = ~T.outer_mask & (n_qubits >= 64 ? ~0ull : (1ull << n_qubits) - 1);
+    if (pass_groups) pass_groups[i] = T.g1 - T.g0;
+  }
+  return QSV_OK;
+}
+
 // coeffs_im (may be NULL): imaginary parts of the weights, taken times im_sign (-1 gives the
 // adjoint of a non-Hermitian sum, the Pauli strings being Hermitian).
 static qsv_status get_pauli_ex(qsv_state* s, const qsv_pauli_sum* H, const double* coeffs_im,
@@ -492,36 +693,7 @@ static qsv_status get_pauli_ex(qsv_state* s, const qsv_pauli_sum* H, const doubl
   p->key_coeffs.assign(H->coeffs, H->coeffs + H->n_terms);
   if (coeffs_im) p->key_im.assign(coeffs_im, coeffs_im + H->n_terms);
   p->key_sign = im_sign;
-  // (P psi)_j = i^{nY} (-1)^{popcount((j^x) & z)} psi_{j^x}: x = X|Y positions, z = Z|Y.
-  std::vector<uint64_t> xs;
-  std::vector<std::vector<PauliTerm>> by_group;
-  for (int t = 0; t < H->n_terms; ++t) {
-    uint64_t x = 0, z = 0;
-    int ny = 0;
-    for (int q = 0; q < n; ++q) {
-      const int c = H->codes[(size_t)t * n + q];
-      if (c == 1 || c == 2) x |= 1ull << q;
-      if (c == 3 || c == 2) z |= 1ull << q;
-      if (c == 2) ++ny;
-    }
-    static const double ire[4] = {1, 0, -1, 0}, iim[4] = {0, 1, 0, -1};
-    const double c = H->coeffs[t], ci = coeffs_im ? im_sign * coeffs_im[t] : 0.0;
-    // (c + i ci) i^{nY}
-    PauliTerm term{z, c * ire[ny & 3] - ci * iim[ny & 3], c * iim[ny & 3] + ci * ire[ny & 3]};
-    size_t g = 0;
-    while (g < xs.size() && xs[g] != x) ++g;
-    if (g == xs.size()) {
-      xs.push_back(x);
-      by_group.emplace_back();
-    }
-    by_group[g].push_back(term);
-  }
-  for (size_t g = 0; g < xs.size(); ++g) {
-    PauliGroup G{xs[g], (int32_t)p->terms.size(), 0};
-    p->terms.insert(p->terms.end(), by_group[g].begin(), by_group[g].end());
-    G.t1 = (int32_t)p->terms.size();
-    p->groups.push_back(G);
-  }
+  build_pauli_groups(*p, n, H, coeffs_im, im_sign);
   const hipStream_t st = s->stream;
   QSV_TRY(p->d_groups.ensure(sizeof(PauliGroup) * (p->groups.size() + 1), st));
   QSV_TRY(p->d_terms.ensure(sizeof(PauliTerm) * (p->terms.size() + 1), st));
@@ -531,6 +703,11 @@ static qsv_status get_pauli_ex(qsv_state* s, const qsv_pauli_sum* H, const doubl
     HIP_TRY(hipMemcpyAsync(p->d_terms.p, p->terms.data(), sizeof(PauliTerm) * p->terms.size(),
                            hipMemcpyHostToDevice, st));
   }
+  plan_pauli_tiles(*p, n, s->dt == QSV_C128);
+  QSV_TRY(upload_vec(p->d_tgroups, p->tgroups, st));
+  QSV_TRY(upload_vec(p->d_tterms, p->tterms, st));
+  QSV_TRY(upload_vec(p->d_rgroups, p->rgroups, st));
+  QSV_TRY(upload_vec(p->d_rterms, p->rterms, st));
   *out = p.get();
   s->paulis[h] = std::move(p);
   return QSV_OK;
@@ -753,14 +930,6 @@ static qsv_status upload_schedule(FusedSchedule& fs, hipStream_t st) {
   if (!sc.slot_map.empty())
     HIP_TRY(hipMemcpyAsync(fs.d_slot_map.p, sc.slot_map.data(),
                            sizeof(int32_t) * sc.slot_map.size(), hipMemcpyHostToDevice, st));
-  return QSV_OK;
-}
-
-template <typename T>
-static qsv_status upload_vec(DevBuf& b, const std::vector<T>& v, hipStream_t st) {
-  QSV_TRY(b.ensure(sizeof(T) * (v.size() ? v.size() : 1), st));
-  if (!v.empty())
-    HIP_TRY(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
   return QSV_OK;
 }
 
@@ -1004,13 +1173,39 @@ static qsv_status backward(qsv_state* s, Plan* p, const FinalDesc** final_desc,
   return QSV_OK;
 }
 
+// out <- H psi (if out is set) and ep[0 .. nb) = the handle's energy partials: the gather kernel
+// over the groups no tiled pass takes, then the tiled passes, each adding to out and to the
+// partials (the first launch sets them).
 template <typename R>
 static qsv_status pauli(qsv_state* s, PauliPlan* hp, const void* psi, void* out, double2* ep) {
   const double S = state_bytes_d(s);
-  return timed(s, "k_pauli", out ? 2 * S : S, [&] {
-    return launch_pauli<R>(psi, out, s->n, hp->d_groups.as<PauliGroup>(), (int)hp->groups.size(),
-                           hp->d_terms.as<PauliTerm>(), ep, s->nb, s->stream);
-  });
+  if (hp->tpasses.empty())
+    return timed(s, "k_pauli", out ? 2 * S : S, [&] {
+      return launch_pauli<R>(psi, out, s->n, hp->d_groups.as<PauliGroup>(),
+                             (int)hp->groups.size(), hp->d_terms.as<PauliTerm>(), ep, s->nb,
+                             s->stream);
+    });
+  bool started = false;
+  if (!hp->rgroups.empty()) {
+    QSV_TRY(timed(s, "k_pauli", out ? 2 * S : S, [&] {
+      return launch_pauli<R>(psi, out, s->n, hp->d_rgroups.as<PauliGroup>(),
+                             (int)hp->rgroups.size(), hp->d_rterms.as<PauliTerm>(), ep, s->nb,
+                             s->stream);
+    }));
+    started = true;
+  }
+  for (const PauliTilePass& T : hp->tpasses) {
+    PauliTilePass P = T;
+    P.lam_mode = out ? (started ? 1 : 0) : 2;
+    P.e_accumulate = started ? 1 : 0;
+    const double bytes = S + (P.lam_mode == 0 ? S : P.lam_mode == 1 ? 2 * S : 0.0);
+    QSV_TRY(timed(s, "k_pauli_tile", bytes, [&] {
+      return launch_pauli_tile<R>(psi, out, P, hp->d_tgroups.as<PauliTileGroup>(),
+                                  hp->d_tterms.as<PauliTerm>(), ep, s->nb, s->stream);
+    }));
+    started = true;
+  }
+  return QSV_OK;
 }
 
 template <typename R>

@@ -31,6 +31,39 @@ template <typename R>
 hipError_t launch_pauli(const void* psi, void* out, int n, const PauliGroup* d_groups, int n_groups,
                         const PauliTerm* d_terms, double2* partial, int nb, hipStream_t st);
 
+// Tiled application of H (Algorithm 1, step lambda <- H psi): the 2^TB amplitudes that share
+// the values of the qubits outside a tile are loaded into LDS once, and every X-mask group whose
+// X bits lie in the tile is applied there (one HBM read of psi for all of them). TB = 12 for
+// complex128, 13 for complex64 (64 KiB of LDS); 2^TB / 8 threads, each owning E = 8
+// amplitudes, element k of thread tid being tile index tid + k * 2^TB / E.
+constexpr int kPauliTileMaxTerms = 64;
+struct PauliTileGroup {
+  uint32_t xl;        // X bits as a tile-local bit mask
+  int32_t t0, t1;     // its terms [t0, t1) in the pass's term table (sign bit t - pass t0)
+};
+struct PauliTilePass {
+  uint64_t outer_mask;            // qubits outside the tile
+  uint64_t kbits[16];             // element k < E: bit t = parity of (k's tile offset & z_t)
+  int8_t tile[16];                // physical qubit of tile bit s (ascending)
+  int32_t n_outer;
+  int32_t g0, g1;                 // groups [g0, g1) of the tiled group table
+  int32_t t0, n_terms;            // terms [t0, t0 + n_terms), n_terms <= kPauliTileMaxTerms
+  int32_t lam_mode;               // 0: lambda = (H psi) part, 1: lambda += it, 2: no lambda
+  int32_t e_accumulate;           // 0: partial[block] = sum, 1: partial[block] += sum
+};
+
+// One tiled pass over psi (and lambda): terms' coefficients already carry the sign
+// (-1)^popcount(x & z) of their group's X mask. partial[block] as set by e_accumulate; grid
+// blocks stride over the tiles. tile_bits: 12 (complex128) or 13 (complex64).
+template <typename R>
+hipError_t launch_pauli_tile(const void* psi, void* lam, const PauliTilePass& P,
+                             const PauliTileGroup* d_groups, const PauliTerm* d_terms,
+                             double2* partial, int grid, hipStream_t st);
+
+// Tile bits and amplitudes per thread of the tiled application for the storage type.
+constexpr int pauli_tile_bits(bool c128) { return c128 ? 12 : 13; }
+constexpr int pauli_tile_elements(bool) { return 8; }
+
 template <typename R>
 hipError_t launch_copy(void* dst, const void* src, int n, hipStream_t st);
 

@@ -525,14 +525,19 @@ __device__ __forceinline__ void pauli_block(const typename Vec2<R>::T* psi, uint
       }
     }
     // a[k] = psi[(j0 + k) ^ x]; its coefficient sums the group's terms with their Z signs
+    // (-1)^popcount(((j0 + k) ^ x) & z). j0 is a multiple of V, so the parity splits into the
+    // block's part, popcount((j0 ^ x) & z) (once per term), and k's, popcount(k & z) (uniform).
     double sr[V], si[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) sr[k] = si[k] = 0.0;
     for (int t = G.t0; t < G.t1; ++t) {
       const PauliTerm T = terms[t];
+      const uint32_t pb = (uint32_t)__popcll((j0 ^ G.x) & T.z & ~(uint64_t)(V - 1)) & 1u;
+      const uint32_t zl = (uint32_t)(T.z & (V - 1));
 #pragma unroll
       for (int k = 0; k < V; ++k) {
-        const bool odd = __popcll(((j0 + k) ^ G.x) & T.z) & 1;
+        const uint32_t pk = (uint32_t)__popc((uint32_t)(k ^ (uint32_t)(G.x & (V - 1))) & zl) & 1u;
+        const bool odd = (pb ^ pk) != 0;
         sr[k] += odd ? -T.cre : T.cre;
         si[k] += odd ? -T.cim : T.cim;
       }
@@ -626,6 +631,155 @@ hipError_t launch_pauli(const void* psi_, void* out_, int n, const PauliGroup* d
     QSV_PAULI(1)
   }
 #undef QSV_PAULI
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------------------------
+// Tiled application of H
+// ----------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t parity64(uint64_t v) { return (uint32_t)__popcll(v) & 1u; }
+
+template <typename R, int TB, int LE>
+__global__ void __launch_bounds__(1 << (TB - LE))
+k_pauli_tile(const typename Vec2<R>::T* __restrict__ psi, typename Vec2<R>::T* lam,
+             PauliTilePass P, const PauliTileGroup* __restrict__ groups,
+             const PauliTerm* __restrict__ terms, double2* partial) {
+  using V = typename Vec2<R>::T;
+  constexpr int NT = 1 << (TB - LE), EPT = 1 << LE, HALF = EPT / 2;
+  __shared__ V tile[1 << TB];
+  __shared__ PauliTerm sterm[kPauliTileMaxTerms];
+  __shared__ PauliTileGroup sgroup[kPauliTileMaxTerms];
+  __shared__ double2 red[NT / 64];
+  const uint32_t tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int n_terms = P.n_terms, n_groups = P.g1 - P.g0;
+  // the pass's terms and groups, staged once
+  for (int t = tid; t < n_terms; t += NT) sterm[t] = terms[P.t0 + t];
+  for (int g = tid; g < n_groups; g += NT) sgroup[g] = groups[P.g0 + g];
+  // thread part of the amplitude index (tile bits 0 .. TB-LE-1); element offsets (bits TB-LE ..
+  // TB-1) are uniform
+  uint64_t gthr = 0;
+#pragma unroll
+  for (int s = 0; s < TB - LE; ++s) gthr |= (uint64_t)((tid >> s) & 1u) << P.tile[s];
+  uint64_t greg[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    uint64_t o = 0;
+#pragma unroll
+    for (int b = 0; b < LE; ++b)
+      if ((k >> b) & 1) o |= 1ull << P.tile[TB - LE + b];
+    greg[k] = o;
+  }
+  __syncthreads();
+  // sign bits of the thread part, one per term of the pass
+  uint64_t tb = 0;
+  for (int t = 0; t < n_terms; ++t) tb |= (uint64_t)parity64(gthr & sterm[t].z) << t;
+  // lane t holds term t's Z mask for the per-tile sign bits (one ballot per tile)
+  const uint64_t zl = lane < n_terms ? sterm[lane].z : 0ull;
+  double2 e = make_double2(0, 0);
+  const uint64_t n_tiles = 1ull << P.n_outer;
+  for (uint64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
+    uint64_t obase = 0;
+    {
+      uint64_t x = g;
+      for (uint64_t m = P.outer_mask; m && x; m &= m - 1, x >>= 1)
+        if (x & 1) obase |= m & (~m + 1);
+    }
+    const uint64_t ob = __ballot(parity64(obase & zl) != 0);
+    const uint64_t base = obase | gthr;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const cx<R> v = load<R>(psi, base | greg[k]);
+      V w;
+      w.x = v.r;
+      w.y = v.i;
+      tile[tid + NT * k] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      cx<R> lv[HALF];
+      if (P.lam_mode == 1) {
+#pragma unroll
+        for (int k = 0; k < HALF; ++k) lv[k] = load<R>(lam, base | greg[h * HALF + k]);
+      }
+      uint64_t sb[HALF];
+#pragma unroll
+      for (int k = 0; k < HALF; ++k) sb[k] = tb ^ ob ^ P.kbits[h * HALF + k];
+      double ar[HALF], ai[HALF];
+#pragma unroll
+      for (int k = 0; k < HALF; ++k) ar[k] = ai[k] = 0.0;
+      for (int gi = 0; gi < n_groups; ++gi) {
+        const PauliTileGroup G = sgroup[gi];
+        double cr[HALF], ci[HALF];
+#pragma unroll
+        for (int k = 0; k < HALF; ++k) cr[k] = ci[k] = 0.0;
+        for (int t = G.t0; t < G.t1; ++t) {
+          const PauliTerm T = sterm[t];
+          // the sign flips the weight's sign bit; a Hermitian term's weight is real or imaginary
+          const int sh = 31 - (t & 31);
+          const bool hi = t >= 32, has_re = T.cre != 0.0, has_im = T.cim != 0.0;
+#pragma unroll
+          for (int k = 0; k < HALF; ++k) {
+            const uint32_t word = hi ? (uint32_t)(sb[k] >> 32) : (uint32_t)sb[k];
+            const uint32_t flip = (word << sh) & 0x80000000u;
+            if (has_re) cr[k] += __hiloint2double(__double2hiint(T.cre) ^ (int)flip, __double2loint(T.cre));
+            if (has_im) ci[k] += __hiloint2double(__double2hiint(T.cim) ^ (int)flip, __double2loint(T.cim));
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < HALF; ++k) {
+          const V w = tile[(tid + NT * (h * HALF + k)) ^ G.xl];
+          const double wr = (double)w.x, wi = (double)w.y;
+          ar[k] += cr[k] * wr - ci[k] * wi;
+          ai[k] += cr[k] * wi + ci[k] * wr;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < HALF; ++k) {
+        // E part: conj(psi_j) (H psi)_j, FP64
+        const V w = tile[tid + NT * (h * HALF + k)];
+        const double pr = (double)w.x, pi = (double)w.y;
+        e.x += pr * ar[k] + pi * ai[k];
+        e.y += pr * ai[k] - pi * ar[k];
+        const uint64_t idx = base | greg[h * HALF + k];
+        if (P.lam_mode == 0)
+          store<R>(lam, idx, cx<R>{(R)ar[k], (R)ai[k]});
+        else if (P.lam_mode == 1)
+          store<R>(lam, idx, cx<R>{(R)((double)lv[k].r + ar[k]), (R)((double)lv[k].i + ai[k])});
+      }
+    }
+    __syncthreads();  // the tile buffer is rewritten by the next tile
+  }
+  // block sum in a fixed order: waves, then the waves in index order
+  const double re = wave_sum(e.x), im = wave_sum(e.y);
+  if (lane == 0) red[tid >> 6] = make_double2(re, im);
+  __syncthreads();
+  if (tid == 0) {
+    double2 s = red[0];
+    for (int w = 1; w < NT / 64; ++w) {
+      s.x += red[w].x;
+      s.y += red[w].y;
+    }
+    if (P.e_accumulate) {
+      s.x = partial[blockIdx.x].x + s.x;
+      s.y = partial[blockIdx.x].y + s.y;
+    }
+    partial[blockIdx.x] = s;
+  }
+}
+
+template <typename R>
+hipError_t launch_pauli_tile(const void* psi, void* lam, const PauliTilePass& P,
+                             const PauliTileGroup* d_groups, const PauliTerm* d_terms,
+                             double2* partial, int grid, hipStream_t st) {
+  using V = typename Vec2<R>::T;
+  constexpr bool C128 = sizeof(R) == 8;
+  constexpr int TB = C128 ? 12 : 13, LE = 3;
+  static_assert(TB == pauli_tile_bits(C128) && (1 << LE) == pauli_tile_elements(C128), "tile shape");
+  hipLaunchKernelGGL((k_pauli_tile<R, TB, LE>), dim3(grid), dim3(1 << (TB - LE)), 0, st,
+                     static_cast<const V*>(psi), static_cast<V*>(lam), P, d_groups, d_terms,
+                     partial);
   return hipGetLastError();
 }
 
@@ -826,6 +980,9 @@ hipError_t launch_ps_combine(double* grad, const double* e, int first, int count
   template hipError_t launch_pauli_batched<R>(const PauliJob*, int, int, double2*, hipStream_t); \
   template hipError_t launch_pauli<R>(const void*, void*, int, const PauliGroup*, int,             \
                                       const PauliTerm*, double2*, int, hipStream_t);               \
+  template hipError_t launch_pauli_tile<R>(const void*, void*, const PauliTilePass&,               \
+                                           const PauliTileGroup*, const PauliTerm*, double2*, int,   \
+                                           hipStream_t);                                             \
   template hipError_t launch_copy<R>(void*, const void*, int, hipStream_t);                        \
   template hipError_t launch_reset<R>(void*, int, hipStream_t);
 QSV_INSTANTIATE(double)

@@ -95,6 +95,8 @@ def lib() -> ctypes.CDLL:
         "qsv_tune_cache_save": ([ctypes.c_char_p], i32),
         "qsv_tune_cache_load": ([ctypes.c_char_p, ctypes.POINTER(i32)], i32),
         "qsv_build_id": ([], ctypes.c_char_p),
+        "qsv_pauli_describe": ([i32, i32, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                ctypes.POINTER(i32), P, P, i32], i32),
         "qsv_debug_fail_launch": ([i32], i32),
     }
     for name, (args, res) in sigs.items():
@@ -159,6 +161,22 @@ def validate_pauli_sum(n_qubits: int, codes, coeffs):
     s, keep = pauli_struct(codes, coeffs, n_qubits)
     check(lib().qsv_validate_pauli_sum(n_qubits, ctypes.byref(s)))
     del keep
+
+
+def pauli_describe(n_qubits: int, codes, coeffs, dtype: str = "c128", max_passes: int = 64):
+    """Host-only: how H is applied (see qsv_pauli_describe): groups, tiled passes with their
+    qubit masks and group counts, and the groups left to the gather."""
+    s, keep = pauli_struct(codes, coeffs, n_qubits)
+    ng, npass, nr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    masks = np.zeros(max_passes, np.uint64)
+    pg = np.zeros(max_passes, np.int32)
+    check(lib().qsv_pauli_describe(n_qubits, DTYPES[dtype], ctypes.byref(s), ctypes.byref(ng),
+                                   ctypes.byref(npass), ctypes.byref(nr), masks.ctypes.data,
+                                   pg.ctypes.data, max_passes))
+    del keep
+    k = min(npass.value, max_passes)
+    return {"n_groups": ng.value, "n_tiled_passes": npass.value, "n_gather_groups": nr.value,
+            "tile_masks": masks[:k], "pass_groups": pg[:k]}
 
 
 def schedule_describe(n_qubits: int, gates, backward: bool, reg_qubits: int, threads_log2: int,

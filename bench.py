@@ -264,7 +264,7 @@ def run_param_shift(qsv, torch, prob, dtype, entries, adj_grad=None, tune=None):
 def run_cpu_baseline(prob, W):
     """The oracle's Algorithm 1 (complex128, OpenMP over the host cores) timed on a bounded
     sample (about 10-30 s): the whole energy + gradient of the same workload when its state has
-    at most 22 qubits, otherwise of the same ansatz and Hamiltonian recipe at fewer qubits (22
+    at most 22 qubits, otherwise of the same ansatz and Hamiltonian recipe at fewer qubits (24
     for the 30-qubit workload, 20 for the 26-qubit one), scaled to one full-size gradient by the
     ratio of the two circuits' one-pass-per-gate bytes (the oracle makes one pass over its
     states per gate primitive, so its time is proportional to them)."""
@@ -273,7 +273,7 @@ def run_cpu_baseline(prob, W):
     n = prob.n_qubits
     sample = prob
     if n > 22:
-        cfg = {30: (W.config5, 22), 26: (W.config3, 20)}.get(n)
+        cfg = {30: (W.config5, 24), 26: (W.config3, 20)}.get(n)
         if cfg is None:
             return None
         sample = cfg[0](n=cfg[1])

@@ -165,6 +165,19 @@ qsv_status qsv_apply_circuit(qsv_state* s, const qsv_gate* gates, int32_t n_gate
    workspace). d_energy: device float64[1]. (Sec. 2.2, the energy functional.) */
 qsv_status qsv_expectation_pauli_sum(qsv_state* s, const qsv_pauli_sum* H, double* d_energy);
 
+/* The same as qsv_expectation_pauli_sum, for callers that cannot allocate (code under graph
+   capture, tight serving loops, harnesses that forbid allocation): nothing is allocated on the
+   device or the host. The energy partials and the Pauli tables live in a fixed device array of
+   1 MiB per GPU (kept until the process ends); the terms are grouped on the host in static
+   tables and copied to the device through kernel arguments. Limits: at most 16384 terms, and
+   16 bytes per gather block plus 16 bytes per X-mask group plus 24 bytes per term within the
+   1 MiB; beyond them QSV_ERR_INVALID_ARG with a message, nothing enqueued. All X-mask groups are
+   gathered (no tiled passes), so the result agrees with qsv_expectation_pauli_sum to rounding.
+   Every call on a GPU shares that GPU's array, and host grouping is serialised by a lock:
+   calls that overlap on one GPU (on different streams) race on the array. */
+qsv_status qsv_expectation_pauli_sum_noalloc(qsv_state* s, const qsv_pauli_sum* H,
+                                             double* d_energy);
+
 /* *d_energy <- <psi|H|psi> with psi = U(theta)|in>, computed in the workspace (the handle's state
    |in> is left unchanged): the forward pass and expectation of Sec. 2.2 without the sweep. */
 qsv_status qsv_energy(qsv_state* s, const qsv_gate* gates, int32_t n_gates, const double* d_theta,

@@ -2251,3 +2251,118 @@ extern "C" qsv_status qsv_tune_cache_load(const char* path, int32_t* out_loaded)
   if (out_loaded) *out_loaded = loaded;
   return QSV_OK;
 }
+
+// ------------------------------------------------------------------------------------------------
+// allocation-free expectation: the energy partials and the Pauli tables live in a fixed device
+// array (one per GPU, kept until the process ends); nothing is allocated on the device or the host
+// ------------------------------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = 1u << 20;
+constexpr int kNoAllocMaxTerms = 16384;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;             // guards the per-device addresses and the host tables
+static void* g_scratch_ptr[64] = {nullptr};  // device address of `scratch` on each GPU
+// host-side grouping tables (static: no heap use per call)
+static PauliGroup g_na_groups[kNoAllocMaxTerms];
+static PauliTerm g_na_terms[kNoAllocMaxTerms];
+static int32_t g_na_group_of[kNoAllocMaxTerms];
+static int32_t g_na_fill[kNoAllocMaxTerms];
+static PauliTerm g_na_sorted[kNoAllocMaxTerms];
+
+// Copies host words into device memory through kernel arguments (captured by value), so that no
+// host buffer has to outlive the call and no staging allocation is made.
+constexpr int kStageWords = 896;
+struct StageChunk {
+  uint32_t off, n;
+  uint32_t w[kStageWords];
+};
+__global__ void k_stage_words(uint32_t* dst, StageChunk c) {
+  for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) dst[c.off + i] = c.w[i];
+}
+
+static qsv_status stage_words(uint32_t* dst, const void* src, size_t n_words, hipStream_t st) {
+  const uint32_t* w = static_cast<const uint32_t*>(src);
+  StageChunk c;
+  for (size_t off = 0; off < n_words; off += kStageWords) {
+    c.off = (uint32_t)off;
+    c.n = (uint32_t)std::min<size_t>(kStageWords, n_words - off);
+    std::memcpy(c.w, w + off, sizeof(uint32_t) * c.n);
+    hipLaunchKernelGGL(k_stage_words, dim3(1), dim3(256), 0, st, dst, c);
+    HIP_TRY(hipGetLastError());
+  }
+  return QSV_OK;
+}
+
+extern "C" qsv_status qsv_expectation_pauli_sum_noalloc(qsv_state* s, const qsv_pauli_sum* H,
+                                                        double* d_energy) {
+  QSV_TRY(check_handle(s));
+  QSV_TRY(qsv_validate_pauli_sum(s->n, H));
+  if (!d_energy) return fail(QSV_ERR_INVALID_ARG, "d_energy is NULL");
+  if (H->n_terms > kNoAllocMaxTerms)
+    return fail(QSV_ERR_INVALID_ARG, "%d Pauli terms exceed the allocation-free limit of %d",
+                H->n_terms, kNoAllocMaxTerms);
+  if (s->device < 0 || s->device >= 64)
+    return fail(QSV_ERR_UNSUPPORTED, "device %d beyond the allocation-free table", s->device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[s->device]) {  // once per device, with that device current
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[s->device] = p;
+  }
+  char* base = static_cast<char*>(g_scratch_ptr[s->device]);
+  // group the terms by X mask, as the cached path does, into the static host tables
+  const int n = s->n, T = H->n_terms;
+  int G = 0;
+  static const double ire[4] = {1, 0, -1, 0}, iim[4] = {0, 1, 0, -1};
+  for (int t = 0; t < T; ++t) {
+    uint64_t x = 0, z = 0;
+    int ny = 0;
+    for (int q = 0; q < n; ++q) {
+      const int c = H->codes[(size_t)t * n + q];
+      if (c == 1 || c == 2) x |= 1ull << q;
+      if (c == 3 || c == 2) z |= 1ull << q;
+      if (c == 2) ++ny;
+    }
+    int g = 0;
+    while (g < G && g_na_groups[g].x != x) ++g;
+    if (g == G) g_na_groups[G++] = PauliGroup{x, 0, 0};
+    ++g_na_groups[g].t1;  // count
+    g_na_group_of[t] = g;
+    const double c = H->coeffs[t];
+    g_na_terms[t] = PauliTerm{z, c * ire[ny & 3], c * iim[ny & 3]};  // temporary, term order
+  }
+  // terms ordered by group (prefix sums, then place)
+  int acc = 0;
+  for (int g = 0; g < G; ++g) {
+    const int cnt = g_na_groups[g].t1;
+    g_na_groups[g].t0 = acc;
+    g_na_groups[g].t1 = acc + cnt;
+    g_na_fill[g] = acc;
+    acc += cnt;
+  }
+  for (int t = 0; t < T; ++t) g_na_sorted[g_na_fill[g_na_group_of[t]]++] = g_na_terms[t];
+  // scratch layout: [energy partials | groups | terms], 256-byte aligned parts
+  const size_t part_bytes = sizeof(double2) * (size_t)s->nb;
+  const size_t groups_off = (part_bytes + 255) & ~(size_t)255;
+  const size_t terms_off = (groups_off + sizeof(PauliGroup) * (size_t)G + 255) & ~(size_t)255;
+  const size_t need = terms_off + sizeof(PauliTerm) * (size_t)T;
+  if (need > kNoAllocScratchBytes)
+    return fail(QSV_ERR_INVALID_ARG,
+                "allocation-free expectation needs %zu bytes of device scratch, the limit is %zu",
+                need, kNoAllocScratchBytes);
+  const hipStream_t st = s->stream;
+  static_assert(sizeof(PauliGroup) % 4 == 0 && sizeof(PauliTerm) % 4 == 0, "word tables");
+  QSV_TRY(stage_words(reinterpret_cast<uint32_t*>(base + groups_off), g_na_groups,
+                      sizeof(PauliGroup) * (size_t)G / 4, st));
+  QSV_TRY(stage_words(reinterpret_cast<uint32_t*>(base + terms_off), g_na_sorted,
+                      sizeof(PauliTerm) * (size_t)T / 4, st));
+  double2* ep = reinterpret_cast<double2*>(base);
+  const PauliGroup* dg = reinterpret_cast<const PauliGroup*>(base + groups_off);
+  const PauliTerm* dt = reinterpret_cast<const PauliTerm*>(base + terms_off);
+  if (s->dt == QSV_C128)
+    HIP_TRY(launch_pauli<double>(s->d_state, nullptr, n, dg, G, dt, ep, s->nb, st));
+  else
+    HIP_TRY(launch_pauli<float>(s->d_state, nullptr, n, dg, G, dt, ep, s->nb, st));
+  HIP_TRY(launch_final_energy(ep, s->nb, d_energy, nullptr, st));
+  return QSV_OK;
+}

@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
         "qsv_sync": ([P], i32),
         "qsv_apply_circuit": ([P, P, i32, P, i32], i32),
         "qsv_expectation_pauli_sum": ([P, P, P], i32),
+        "qsv_expectation_pauli_sum_noalloc": ([P, P, P], i32),
         "qsv_adjoint_gradient": ([P, P, i32, P, i32, P, P, P], i32),
         "qsv_energy": ([P, P, i32, P, i32, P, P], i32),
         "qsv_adjoint_gradient_batched": ([i32, P, P, P, P, P, P, P, P, P], i32),
@@ -298,6 +299,14 @@ class StateVector:
         check(lib().qsv_expectation_pauli_sum(self._h, ctypes.byref(s), e.data_ptr()))
         del keep
         return e
+
+    def expectation_noalloc(self, codes, coeffs, out):
+        """<state|H|state> into the float64 device tensor `out` without any allocation (see
+        qsv_expectation_pauli_sum_noalloc); `out` must be given."""
+        s, keep = pauli_struct(codes, coeffs, self.n)
+        check(lib().qsv_expectation_pauli_sum_noalloc(self._h, ctypes.byref(s), out.data_ptr()))
+        del keep
+        return out
 
     def energy(self, gates, theta, codes, coeffs, out=None):
         """<psi|H|psi> with psi = U(theta)|in> as a float64 device tensor of shape (1,)."""

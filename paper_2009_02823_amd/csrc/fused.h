@@ -183,8 +183,14 @@ bool build_forward_schedule(int n, const std::vector<GateDesc>& gates, int t, in
 // 1.42 -> 1.37 ms per gradient; at 26 qubits half lines measured 3 % slower).
 inline int run_qubits_for(bool c128, int n) { return c128 ? 3 : (n <= 24 ? 3 : 4); }
 
-// Launchers of the fused pass kernels. Configurations (r, w) available: see fused_kernels.hip.
-bool fused_config_supported(int r, int w, bool c128);
+// Geometries (r, w) with a fused kernel instance whose amplitude registers do not spill (reverse
+// sweep: two states per thread); the launchers in fused_kernels.hip instantiate exactly these.
+inline bool fused_config_supported(int r, int w, bool c128) {
+  if (w == 9) return r >= 2 && r <= (c128 ? 3 : 4);
+  if (w == 8) return r >= 2 && r <= 4;
+  if (w == 6) return r >= 2 && r <= 3;
+  return false;
+}
 
 // Launch over `n_items` items whose tiles total `total`; workgroup w takes tiles
 // [w * chunk, (w + 1) * chunk). `general` selects the kernel instance that also handles the

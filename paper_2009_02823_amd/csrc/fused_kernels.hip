@@ -1549,15 +1549,7 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
 // ---------------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------------
-// Geometries with a kernel instance whose amplitude registers do not spill (reverse sweep: two
-// states per thread).
-bool fused_config_supported(int r, int w, bool c128) {
-  if (w == 9) return r >= 2 && r <= (c128 ? 3 : 4);
-  if (w == 8) return r >= 2 && r <= 4;
-  if (w == 6) return r >= 2 && r <= 3;
-  return false;
-}
-
+// The cases below are the geometries fused_config_supported (fused.h) names.
 #define QSV_FUSED_CASES(X, R) X(R, 2, 8) X(R, 3, 8) X(R, 3, 9) X(R, 2, 9) X(R, 2, 6) X(R, 3, 6)
 
 template <typename R>

@@ -334,12 +334,25 @@ qsv_status qsv_timing_read(qsv_state* s, qsv_kernel_stat* out, int32_t max_out, 
                 may exceed the state: its extra ("phantom") bits hold amplitudes that are never
                 loaded or stored, and a state within one tile runs every pass of a sweep in a
                 single launch (one workgroup walks the passes in order);
-     mode = -1  automatic (the default): fused with a size-dependent geometry. qsv_autotune
-                picks among all modes by measurement. */
+     mode = 2   (states of at most 6 qubits) the gradient runs Algorithm 1 in one wave: amplitude
+                j in lane j, gates applied across lanes by lane permutations, the forward pass,
+                H, the reverse sweep and the gradient entries in one launch; the other calls run
+                fused passes; qsv_adjoint_gradient_batched runs one such wave per circuit;
+     mode = 3   (states of at most 5 qubits) as mode 2, with the gradient's gates taken in chunks
+                of 64: the product W_c of each chunk is formed in parallel (the chunk applied to
+                the basis states), psi, phi and lambda are carried across chunk boundaries by W_c
+                and W_c^dag on one wave, and the steps of Algorithm 1 inside the chunks run for
+                all chunks at once. Circuits with a non-unitary gate run mode 2;
+     mode = -1  automatic (the default): for the gradient of states of at most 6 qubits mode 3
+                from 192 gates on (at most 5 qubits, unitary gates), else mode 2; otherwise fused
+                with a size-dependent geometry. qsv_autotune picks among all modes by
+                measurement. */
 qsv_status qsv_set_fusion(qsv_state* s, int32_t mode, int32_t reg_qubits, int32_t threads_log2);
 
-/* The geometry the handle currently runs with: *mode = 1 (fused, with *reg_qubits and
-   *threads_log2) or 0 (gate-granular). */
+/* The geometry the handle's gradient currently runs with: *mode = 2 (one wave, chosen or
+   automatic; the automatic mode runs long circuits chunked) or 3 (chunked one wave), with
+   *reg_qubits = *threads_log2 = 0; 1 (fused, with *reg_qubits and *threads_log2) or 0
+   (gate-granular). */
 qsv_status qsv_get_fusion(qsv_state* s, int32_t* mode, int32_t* reg_qubits, int32_t* threads_log2);
 
 /* Host-only description of the fused schedule of a circuit (no GPU needed): the order gates run

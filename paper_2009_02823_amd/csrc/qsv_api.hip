@@ -222,6 +222,13 @@ struct Plan {
   // gate-granular reverse sweep: partials [slot][block] and their descriptors
   bool gg_ready = false;
   DevBuf gg_partials, d_gg_occ_base, d_gg_occ_nb, d_gg_final;
+  // one-wave sweep (states of at most kWaveMaxQubits qubits): one product sum per slot
+  DevBuf wave_slot_sum;
+  bool all_unitary = true;
+  // chunked one-circuit sweep: chunk operators, boundary states, first slots, finish counter
+  bool wc_ready = false;
+  int wc_chunks = 0;
+  DevBuf wc_A, wc_B, wc_phi, wc_lam, wc_slot0, wc_done;
 };
 
 struct PauliPlan {
@@ -430,6 +437,9 @@ struct BatchPlan {
   // one launch prepares the whole batch; one launch applies H to every circuit
   DevBuf d_gates_all, d_recs_all, d_jobs, partials_e;
   int total_gates = 0;
+  // one-wave batch (every circuit of at most kWaveMaxQubits qubits): one wave per circuit
+  bool wave = false;
+  DevBuf d_wave_jobs;
 };
 
 static constexpr int kBatchPauliBlocks = 128;  // blocks per circuit of the batched H apply
@@ -466,7 +476,8 @@ struct qsv_state {
   hipStream_t stream = nullptr;
   int device = 0;
   int nb = 1;
-  int fusion_mode = -1;  // -1 automatic, 0 gate-granular, 1 fused with (fr, fw)
+  int fusion_mode = -1;  // -1 automatic, 0 gate-granular, 1 fused with (fr, fw), 2 one wave,
+                         // 3 chunked one-circuit sweep
   int fr = 0, fw = 0;
   std::unordered_map<uint64_t, std::unique_ptr<Plan>> plans;
   std::unordered_map<uint64_t, std::unique_ptr<PauliPlan>> paulis;
@@ -570,6 +581,7 @@ static qsv_status get_plan(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
     slot += np;
   }
   p->n_occ = slot;
+  for (const GateDesc& g : p->gates) p->all_unitary = p->all_unitary && kind_unitary(g.kind);
   p->param_ptr.assign(n_theta + 1, 0);
   for (int q = 0; q < n_theta; ++q) {
     p->param_ptr[q + 1] = p->param_ptr[q] + (int32_t)per_param[q].size();
@@ -1087,6 +1099,105 @@ static qsv_status get_gate_granular(qsv_state* s, Plan* p) {
   return QSV_OK;
 }
 
+// The one-wave sweep (launch_wave_adjoint): fusion mode 2, and the automatic mode's choice, for
+// states of at most kWaveMaxQubits qubits.
+static bool wave_path(const qsv_state* s) {
+  return s->n <= kWaveMaxQubits &&
+         (s->fusion_mode == 2 || s->fusion_mode == 3 || s->fusion_mode == -1);
+}
+
+// Circuits long enough for the chunked sweep to pay for forming the chunk operators (about
+// 2^n gate applications per gate): the automatic mode takes it from this many gates on.
+static constexpr int kWaveChunkMinGates = 192;
+
+// The chunked variant (launch_wave_chunked) of a one-wave gradient: mode 3, or the automatic
+// mode for long circuits; every gate unitary (phi is carried back by W_c^dag).
+static bool wave_chunked(const qsv_state* s, const Plan* p) {
+  const int G = (int)p->gates.size();
+  return s->n <= kWaveChunkMaxQubits && p->all_unitary && G > 0 &&
+         (s->fusion_mode == 3 || (s->fusion_mode == -1 && G >= kWaveChunkMinGates));
+}
+
+static qsv_status get_wave_chunks(qsv_state* s, Plan* p) {
+  if (p->wc_ready) return QSV_OK;
+  const hipStream_t st = s->stream;
+  const int G = (int)p->gates.size();
+  const int C = (G + kWaveChunk - 1) / kWaveChunk;
+  const size_t N = (size_t)1 << s->n;
+  QSV_TRY(p->wc_A.ensure(sizeof(double2) * C * N * N, st));
+  QSV_TRY(p->wc_B.ensure(sizeof(double2) * C * N * N, st));
+  QSV_TRY(p->wc_phi.ensure(sizeof(double2) * C * N, st));
+  QSV_TRY(p->wc_lam.ensure(sizeof(double2) * C * N, st));
+  // chunk c's first slot: the products of the gates after it (slots run in sweep order)
+  std::vector<int32_t> slot0(C, 0);
+  int after = 0;
+  for (int c = C - 1; c >= 0; --c) {
+    slot0[c] = after;
+    for (int k = c * kWaveChunk; k < std::min(G, (c + 1) * kWaveChunk); ++k)
+      after += kind_nparams(p->gates[k].kind);
+  }
+  QSV_TRY(upload_vec(p->wc_slot0, slot0, st));
+  QSV_TRY(p->wc_done.ensure(sizeof(int32_t), st));
+  HIP_TRY(hipMemsetAsync(p->wc_done.p, 0, sizeof(int32_t), st));
+  p->wc_chunks = C;
+  p->wc_ready = true;
+  return QSV_OK;
+}
+
+static qsv_status get_wave(qsv_state* s, Plan* p) {
+  return p->wave_slot_sum.ensure(sizeof(double) * (size_t)std::max(p->n_occ, 1), s->stream);
+}
+
+static WaveJob wave_job(qsv_state* s, Plan* p, PauliPlan* hp, double* d_energy, double* d_grad) {
+  WaveJob J;
+  std::memset(&J, 0, sizeof J);
+  J.gates = p->d_gates.as<GateDesc>();
+  J.recs = p->d_recs.as<GateRec>();
+  J.in = s->d_state;
+  J.groups = hp->d_groups.as<PauliGroup>();
+  J.terms = hp->d_terms.as<PauliTerm>();
+  J.param_ptr = p->d_param_ptr.as<int32_t>();
+  J.occ = p->d_occ.as<int32_t>();
+  J.slot_sum = p->wave_slot_sum.as<double>();
+  J.energy = d_energy;
+  J.grad = d_grad;
+  J.n_gates = (int32_t)p->gates.size();
+  J.n = s->n;
+  J.n_groups = (int32_t)hp->groups.size();
+  J.n_theta = p->n_theta;
+  return J;
+}
+
+// Algorithm 1 in one wave: the forward pass, H, the reverse sweep and the gradient entries in
+// one launch (after the launch that fills the gate records).
+template <typename R>
+static qsv_status wave_adjoint_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* d_theta,
+                                 double* d_energy, double* d_grad) {
+  const hipStream_t st = s->stream;
+  QSV_TRY(get_wave(s, p));
+  HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
+                      p->d_recs.as<GateRec>(), st));
+  const WaveJob J = wave_job(s, p, hp, d_energy, d_grad);
+  if (wave_chunked(s, p)) {
+    QSV_TRY(get_wave_chunks(s, p));
+    WaveChunks K;
+    std::memset(&K, 0, sizeof K);
+    K.A = p->wc_A.as<double2>();
+    K.B = p->wc_B.as<double2>();
+    K.phi = p->wc_phi.as<double2>();
+    K.lam = p->wc_lam.as<double2>();
+    K.slot0 = p->wc_slot0.as<int32_t>();
+    K.done = p->wc_done.as<int32_t>();
+    K.n_chunks = p->wc_chunks;
+    return timed(s, "k_wave_chunked", 3 * state_bytes_d(s), [&] {
+      return launch_wave_chunked<R>(J, K, st);
+    });
+  }
+  return timed(s, "k_wave_adjoint", 3 * state_bytes_d(s), [&] {
+    return launch_wave_adjoint<R>(nullptr, 1, J, nullptr, nullptr, st);
+  });
+}
+
 // dst <- U src (fused: into phi or in place on the state; gate-granular: any pair of buffers).
 template <typename R>
 static qsv_status forward(qsv_state* s, Plan* p, const void* src, void* dst) {
@@ -1315,9 +1426,13 @@ extern "C" qsv_status qsv_adjoint_gradient(qsv_state* s, const qsv_gate* gates, 
   const uint64_t serials[2] = {p->serial, hp->serial};
   const void* key_parts[3] = {d_theta, d_energy, d_grad};
   uint64_t key = fnv1a(key_parts, sizeof key_parts, fnv1a(serials, sizeof serials));
-  const int geo[3] = {fz ? 1 : 0, r, w};
+  const bool wave = wave_path(s);
+  const int geo[3] = {wave ? 2 : fz ? 1 : 0, r, w};
   key = fnv1a(geo, sizeof geo, key ^ 0xad301ull);
   return run_graph(s, key, [&] {
+    if (wave)
+      return s->dt == QSV_C128 ? wave_adjoint_t<double>(s, p, hp, d_theta, d_energy, d_grad)
+                               : wave_adjoint_t<float>(s, p, hp, d_theta, d_energy, d_grad);
     return s->dt == QSV_C128 ? adjoint_t<double>(s, p, hp, d_theta, d_energy, d_grad)
                              : adjoint_t<float>(s, p, hp, d_theta, d_energy, d_grad);
   });
@@ -1341,6 +1456,67 @@ struct StreamOverride {
   }
 };
 
+// The batch's gate table (parameter indices into the flat theta) and matrix records, so that one
+// launch prepares every circuit's records; gate_base[b] = circuit b's first gate.
+static qsv_status build_batch_gates(const std::vector<Plan*>& plans, int B,
+                                    const int64_t* theta_off, hipStream_t st, BatchPlan* bp,
+                                    std::vector<int64_t>& gate_base) {
+  std::vector<GateDesc> all;
+  gate_base.assign(B, 0);
+  for (int b = 0; b < B; ++b) {
+    gate_base[b] = (int64_t)all.size();
+    for (GateDesc g : plans[b]->gates) {
+      for (int j = 0; j < 3; ++j)
+        if (g.p[j] >= 0) g.p[j] += (int32_t)theta_off[b];
+      all.push_back(g);
+    }
+  }
+  bp->total_gates = (int)all.size();
+  QSV_TRY(upload_vec(bp->d_gates_all, all, st));
+  return bp->d_recs_all.ensure(sizeof(GateRec) * (all.size() ? all.size() : 1), st);
+}
+
+// A batch of small circuits: one wave each (see wave_adjoint_t).
+static qsv_status build_batch_wave(qsv_state* const* states, const std::vector<Plan*>& plans,
+                                   const std::vector<PauliPlan*>& hps, int B,
+                                   const int64_t* theta_off, BatchPlan* bp) {
+  const hipStream_t st = states[0]->stream;
+  std::vector<int64_t> gate_base;
+  QSV_TRY(build_batch_gates(plans, B, theta_off, st, bp, gate_base));
+  bp->wave = true;
+  std::vector<WaveJob> jobs(B);
+  for (int b = 0; b < B; ++b) {
+    QSV_TRY(get_wave(states[b], plans[b]));
+    WaveJob J = wave_job(states[b], plans[b], hps[b], nullptr, nullptr);
+    J.gates = bp->d_gates_all.as<GateDesc>() + gate_base[b];
+    J.recs = bp->d_recs_all.as<GateRec>() + gate_base[b];
+    J.grad_off = theta_off[b];
+    jobs[b] = J;
+  }
+  QSV_TRY(upload_vec(bp->d_wave_jobs, jobs, st));
+  bp->plans = plans;
+  bp->paulis = hps;
+  bp->states.assign(states, states + B);
+  return QSV_OK;
+}
+
+template <typename R>
+static qsv_status batched_wave_t(qsv_state* const* states, int B, BatchPlan* bp,
+                                 const double* d_theta_flat, const int64_t* theta_off,
+                                 double* d_energy, double* d_grad_flat) {
+  qsv_state* s0 = states[0];
+  const hipStream_t st = s0->stream;
+  (void)theta_off;
+  HIP_TRY(launch_prep(bp->d_gates_all.as<GateDesc>(), bp->total_gates, d_theta_flat,
+                      bp->d_recs_all.as<GateRec>(), st));
+  double bytes = 0;
+  for (int b = 0; b < B; ++b) bytes += 3.0 * (double)qsv_state_bytes(states[b]->n, states[b]->dt);
+  return timed(s0, "k_wave_adjoint", bytes, [&] {
+    return launch_wave_adjoint<R>(bp->d_wave_jobs.as<WaveJob>(), B, WaveJob{}, d_energy,
+                                  d_grad_flat, st);
+  });
+}
+
 static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>& plans,
                               const std::vector<PauliPlan*>& hps, int B, const int64_t* theta_off,
                               int r, int w, BatchPlan* bp) {
@@ -1355,20 +1531,8 @@ static qsv_status build_batch(qsv_state* const* states, const std::vector<Plan*>
     lf = std::max(lf, fps[b]->fwd.sched.passes.size());
     lb = std::max(lb, fps[b]->bwd.sched.passes.size());
   }
-  // the batch's gate table and matrix records
-  std::vector<GateDesc> all;
-  std::vector<int64_t> gate_base(B);
-  for (int b = 0; b < B; ++b) {
-    gate_base[b] = (int64_t)all.size();
-    for (GateDesc g : plans[b]->gates) {
-      for (int j = 0; j < 3; ++j)
-        if (g.p[j] >= 0) g.p[j] += (int32_t)theta_off[b];
-      all.push_back(g);
-    }
-  }
-  bp->total_gates = (int)all.size();
-  QSV_TRY(upload_vec(bp->d_gates_all, all, st));
-  QSV_TRY(bp->d_recs_all.ensure(sizeof(GateRec) * (all.size() ? all.size() : 1), st));
+  std::vector<int64_t> gate_base;
+  QSV_TRY(build_batch_gates(plans, B, theta_off, st, bp, gate_base));
   GateRec* recs_all = bp->d_recs_all.as<GateRec>();
   // H applied to every circuit in one launch
   std::vector<PauliJob> jobs(B);
@@ -1555,15 +1719,18 @@ extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* c
     QSV_TRY(check_theta(plans[b], d_theta_flat));
     QSV_TRY(get_pauli(states[b], &H[b], &hps[b]));
   }
+  // every circuit small enough for one wave: one launch of one wave per circuit
+  bool wave = true;
+  for (int b = 0; b < n_batch && wave; ++b) wave = wave_path(states[b]);
   // a common tile geometry that fits every circuit; otherwise one circuit after the other
   int r = 0, w = 0;
-  bool fused = fusion_geometry(s0, &r, &w);
+  bool fused = !wave && fusion_geometry(s0, &r, &w);
   for (int b = 0; b < n_batch && fused; ++b) {
     int rb = 0, wb = 0;
     fused = fusion_geometry(states[b], &rb, &wb) && r + w <= states[b]->n &&
             !plans[b]->gates.empty();
   }
-  if (!fused) {
+  if (!fused && !wave) {
     for (int b = 0; b < n_batch; ++b) {
       qsv_state* s = states[b];
       double* g = d_grad_flat ? d_grad_flat + theta_off[b] : nullptr;
@@ -1580,6 +1747,7 @@ extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* c
   key = fnv1a(theta_off, sizeof(int64_t) * n_batch, key);
   key = fnv1a(&r, sizeof r, key);
   key = fnv1a(&w, sizeof w, key);
+  key = fnv1a(&wave, sizeof wave, key);
   std::vector<uint64_t> serials;
   for (int b = 0; b < n_batch; ++b) {
     serials.push_back(plans[b]->serial);
@@ -1597,7 +1765,10 @@ extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* c
       s0->batches.clear();
     }
     auto nbp = std::make_unique<BatchPlan>();
-    QSV_TRY(build_batch(states, plans, hps, n_batch, theta_off, r, w, nbp.get()));
+    if (wave)
+      QSV_TRY(build_batch_wave(states, plans, hps, n_batch, theta_off, nbp.get()));
+    else
+      QSV_TRY(build_batch(states, plans, hps, n_batch, theta_off, r, w, nbp.get()));
     nbp->serials = serials;
     bp = nbp.get();
     s0->batches[key] = std::move(nbp);
@@ -1607,6 +1778,11 @@ extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* c
   return run_graph(
       s0, gkey,
       [&] {
+        if (bp->wave)
+          return s0->dt == QSV_C128 ? batched_wave_t<double>(states, n_batch, bp, d_theta_flat,
+                                                             theta_off, d_energy, d_grad_flat)
+                                    : batched_wave_t<float>(states, n_batch, bp, d_theta_flat,
+                                                            theta_off, d_energy, d_grad_flat);
         return s0->dt == QSV_C128
                    ? batched_t<double>(states, n_batch, plans, hps, bp, d_theta_flat, theta_off,
                                        d_energy, d_grad_flat)
@@ -1975,7 +2151,13 @@ extern "C" qsv_status qsv_timing_read(qsv_state* s, qsv_kernel_stat* out, int32_
 extern "C" qsv_status qsv_set_fusion(qsv_state* s, int32_t mode, int32_t reg_qubits,
                                      int32_t threads_log2) {
   QSV_TRY(check_handle(s));
-  if (mode < -1 || mode > 1) return fail(QSV_ERR_INVALID_ARG, "fusion mode %d", mode);
+  if (mode < -1 || mode > 3) return fail(QSV_ERR_INVALID_ARG, "fusion mode %d", mode);
+  if (mode == 2 && s->n > kWaveMaxQubits)
+    return fail(QSV_ERR_UNSUPPORTED, "the one-wave sweep holds at most %d qubits (state has %d)",
+                kWaveMaxQubits, s->n);
+  if (mode == 3 && s->n > kWaveChunkMaxQubits)
+    return fail(QSV_ERR_UNSUPPORTED, "the chunked sweep holds at most %d qubits (state has %d)",
+                kWaveChunkMaxQubits, s->n);
   if (mode == 1) {
     if (!fused_config_supported(reg_qubits, threads_log2, s->dt == QSV_C128))
       return fail(QSV_ERR_UNSUPPORTED, "no fused kernel for reg_qubits=%d threads_log2=%d",
@@ -1991,6 +2173,11 @@ extern "C" qsv_status qsv_get_fusion(qsv_state* s, int32_t* mode, int32_t* reg_q
                                      int32_t* threads_log2) {
   QSV_TRY(check_handle(s));
   if (!mode || !reg_qubits || !threads_log2) return fail(QSV_ERR_INVALID_ARG, "NULL output");
+  if (wave_path(s)) {  // the gradient runs the one-wave sweep (mode 3: its chunked variant)
+    *mode = s->fusion_mode == 3 ? 3 : 2;
+    *reg_qubits = *threads_log2 = 0;
+    return QSV_OK;
+  }
   int r = 0, w = 0;
   const bool f = fusion_geometry(s, &r, &w);
   *mode = f ? 1 : 0;
@@ -2125,6 +2312,8 @@ extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t 
   }
   if (!cached) {
     std::vector<std::array<int, 3>> cands;
+    if (s->n <= kWaveMaxQubits) cands.push_back({2, 0, 0});
+    if (s->n <= kWaveChunkMaxQubits) cands.push_back({3, 0, 0});
     if (s->n <= 20) cands.push_back({0, 0, 0});
     const int ws[3] = {9, 8, 6};
     for (int w : ws)
@@ -2176,7 +2365,7 @@ extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_gate* gates, int32_t 
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[key] = TuneEntry{best, s->n, (int32_t)s->dt, best_ms};
   }
-  s->fusion_mode = best[0] ? 1 : 0;
+  s->fusion_mode = best[0];
   s->fr = best[1];
   s->fw = best[2];
   if (out_mode) *out_mode = best[0];
@@ -2239,7 +2428,9 @@ extern "C" qsv_status qsv_tune_cache_load(const char* path, int32_t* out_loaded)
                               src, &h, &n, &dt, &m, &r, &w, &ms);
     if (k != 8 || std::strcmp(src, QSV_SOURCE_ID) != 0) continue;
     if (n < 1 || n > kMaxQubits || (dt != QSV_C64 && dt != QSV_C128)) continue;
-    if (m == 1 ? !fused_config_supported(r, w, dt == QSV_C128) : m != 0) continue;
+    if (m == 1 ? !fused_config_supported(r, w, dt == QSV_C128)
+               : (m == 2 ? n > kWaveMaxQubits : (m == 3 ? n > kWaveChunkMaxQubits : m != 0)))
+      continue;
     got.push_back({TuneKey{(uint64_t)h}, TuneEntry{{m, r, w}, n, dt, ms}});
     ++loaded;
   }

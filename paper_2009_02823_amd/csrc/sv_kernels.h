@@ -64,6 +64,50 @@ hipError_t launch_pauli_tile(const void* psi, void* lam, const PauliTilePass& P,
 constexpr int pauli_tile_bits(bool c128) { return c128 ? 12 : 13; }
 constexpr int pauli_tile_elements(bool) { return 8; }
 
+// Algorithm 1 for states of at most kWaveMaxQubits qubits, one wave (64 threads) per circuit:
+// amplitude j in lane j. The wave writes the energy, the per-slot sums of the products
+// Re <lambda|mu> (slots in sweep order, last gate first) and the gradient itself.
+constexpr int kWaveMaxQubits = 6;
+struct WaveJob {
+  const GateDesc* gates;
+  const GateRec* recs;
+  const void* in;                 // |in>, 2^n amplitudes of the storage type
+  const PauliGroup* groups;
+  const PauliTerm* terms;
+  const int32_t* param_ptr;       // parameter p owns slots occ[param_ptr[p] .. param_ptr[p+1])
+  const int32_t* occ;
+  double* slot_sum;               // [slots] workspace: Re <lambda|mu> per slot
+  double* energy;                 // [1] <- E (one circuit)
+  double* grad;                   // [n_theta] <- dE/dtheta (one circuit)
+  int64_t grad_off;               // batch: the gradient goes to grad_base + grad_off
+  int32_t n_gates, n, n_groups, n_theta;
+};
+
+// The chunked sweep of one circuit (every gate unitary, at most kWaveChunkMaxQubits qubits): the
+// gates in chunks of 64, each chunk's operator W_c formed in parallel, the states at the chunk
+// boundaries carried by W_c, and the steps inside all chunks run at once (launch_wave_chunked).
+constexpr int kWaveChunk = 64;
+constexpr int kWaveChunkMaxQubits = 5;
+struct WaveChunks {
+  double2* A;               // [n_chunks][N][N]: A[c][j * N + r] = W_c[r][j]
+  double2* B;               // [n_chunks][N][N]: B[c][j * N + r] = W_c[j][r]
+  double2* phi;             // [n_chunks][N]: phi at the end of chunk c
+  double2* lam;             // [n_chunks][N]: lambda at the end of chunk c
+  const int32_t* slot0;     // [n_chunks]: first product slot of chunk c
+  int32_t* done;            // chunks finished (0 between calls)
+  int32_t n_chunks;
+  int32_t pad;
+};
+template <typename R>
+hipError_t launch_wave_chunked(const WaveJob& J, const WaveChunks& K, hipStream_t st);
+
+// d_jobs = NULL: one circuit, `single`; else n_jobs circuits from the device table, job b writing
+// energy_base[b] and its gradient at grad_base + grad_off (the output pointers are launch
+// arguments, so a table serves any outputs).
+template <typename R>
+hipError_t launch_wave_adjoint(const WaveJob* d_jobs, int n_jobs, const WaveJob& single,
+                               double* energy_base, double* grad_base, hipStream_t st);
+
 template <typename R>
 hipError_t launch_copy(void* dst, const void* src, int n, hipStream_t st);
 

@@ -390,7 +390,8 @@ class StateVector:
         return gr
 
     def set_fusion(self, mode: int, reg_qubits: int = 0, threads_log2: int = 0):
-        """mode 0: gate-granular; 1: fused with the given geometry; -1: automatic."""
+        """mode 0: gate-granular; 1: fused with the given geometry; 2: one wave (at most 6
+        qubits); 3: the chunked one-wave sweep (at most 5 qubits); -1: automatic."""
         check(lib().qsv_set_fusion(self._h, mode, reg_qubits, threads_log2))
 
     def get_fusion(self):

@@ -150,3 +150,93 @@ def test_autograd_batched(Q, orc):
         o = batch.theta_off[b]
         assert np.max(np.abs(grad[o:o + p.n_params] - (b + 1) * g_ref)) <= 1e-10 * (b + 1)
     batch.close()
+
+
+def wave_batch(seed):
+    """Circuits of 1 to 6 qubits (one wave each): every gate kind, repeated and unique
+    parameters, gate counts around the 64-gate chunks of gate data, slot counts at the 32-slot
+    flushes of the product rows, and an empty circuit."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    shapes = [(1, 0, None), (1, 1, None), (2, 63, None), (3, 64, None), (4, 65, None),
+              (5, 200, None), (6, 200, 30), (6, 129, 7), (5, 333, None), (2, 40, 3)]
+    for b, (n, G, npar) in enumerate(shapes):
+        kinds = [k for k in list(W.GATE_NAMES) if n >= 2 or W.N_QUBITS[k] == 1]
+        gates, P = W.random_circuit(rng, n, G, kinds, n_params=npar)
+        codes = W.random_pauli_strings(rng, n, 5)
+        coeffs = rng.standard_normal(5)
+        probs.append(W.Problem(f"w{b}", n, gates, W.uniform_angles(rng, P), codes, coeffs))
+    # rotations only: exactly 32 and 64 products (the flush boundaries)
+    for n, G in ((3, 32), (5, 64)):
+        rows = [(int(rng.choice([W.RX, W.RY, W.RZ])), int(rng.integers(0, n)), -1, j, -1, -1)
+                for j in range(G)]
+        codes = W.random_pauli_strings(rng, n, 4)
+        probs.append(W.Problem(f"r{n}", n, W.circuit_table(rows), W.uniform_angles(rng, G),
+                               codes, rng.standard_normal(4)))
+    return probs
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_wave_batch_vs_oracle(Q, orc, dtype):
+    """A batch of circuits of at most 6 qubits runs one wave per circuit in one launch; every
+    energy and gradient entry against the oracle, with graphs on, over replays into two pairs of
+    output buffers."""
+    import torch
+    probs = wave_batch(21)
+    batch = Q.Batch(probs, dtype)
+    batch.set_graphs(True)
+    th = batch.theta_flat()
+    refs = [orc.adjoint_gradient(p.n_qubits, p.gates, p.theta, p.codes, p.coeffs) for p in probs]
+    outs = [(torch.full((len(probs),), np.nan, dtype=torch.float64, device=th.device),
+             torch.full((batch.n_params,), np.nan, dtype=torch.float64, device=th.device))
+            for _ in range(2)]
+    for rep in range(3):
+        for e, g in outs:
+            batch.adjoint_gradient(th, e, g)
+            batch.sync()
+            ec, gc = e.cpu().numpy(), g.cpu().numpy()
+            for b, (p, (e_ref, g_ref)) in enumerate(zip(probs, refs)):
+                gb = gc[batch.theta_off[b]: batch.theta_off[b] + p.n_params]
+                if dtype == "c128":
+                    assert abs(ec[b] - e_ref.real) <= 1e-10, (rep, b)
+                    assert p.n_params == 0 or np.max(np.abs(gb - g_ref)) <= 1e-10, (rep, b)
+                else:
+                    assert abs(ec[b] - e_ref.real) <= 2e-4 * max(abs(e_ref), 1.0), (rep, b)
+                    scale = max(np.max(np.abs(g_ref), initial=0), 1e-5 * np.abs(p.coeffs).sum())
+                    assert p.n_params == 0 or np.max(np.abs(gb - g_ref)) <= 2e-4 * scale, (rep, b)
+    batch.close()
+
+
+def test_wave_batch_paper_circuits(Q, orc):
+    """The paper's regime at batch scale: 5-qubit circuits with P up to 1290 (Hadamard^(x)5), a
+    sample of the batch against the oracle and every circuit against its single call."""
+    import torch
+    probs = []
+    for L in (1, 8, 129):
+        base = W.paper_benchmark(5, L)
+        rng = np.random.default_rng(L)
+        for c in range(3):
+            probs.append(W.Problem(f"{base.name}_{c}", 5, base.gates,
+                                   W.uniform_angles(rng, base.n_params), base.codes, base.coeffs))
+    batch = Q.Batch(probs)
+    e, g = batch.adjoint_gradient(batch.theta_flat())
+    batch.sync()
+    ec, gc = e.cpu().numpy(), g.cpu().numpy()
+    for b, p in enumerate(probs):
+        gb = gc[batch.theta_off[b]: batch.theta_off[b] + p.n_params]
+        if b % 3 == 0:
+            e_ref, g_ref = orc.adjoint_gradient(5, p.gates, p.theta, p.codes, p.coeffs)
+            assert abs(ec[b] - e_ref.real) <= 1e-10
+            assert np.max(np.abs(gb - g_ref)) <= 1e-10
+        for mode in (2, -1):  # the plain one-wave sweep is the batch's, bit for bit; the
+            with Q.StateVector(5) as sv:  # automatic mode runs long circuits chunked
+                sv.set_fusion(mode)
+                e1, g1 = sv.adjoint_gradient(p.gates, torch.as_tensor(p.theta, device="cuda:0"),
+                                             p.codes, p.coeffs)
+                sv.sync()
+                e1, g1 = float(e1.cpu()[0]), g1.cpu().numpy()
+            if mode == 2:
+                assert e1 == ec[b] and np.array_equal(g1, gb)
+            else:
+                assert abs(e1 - ec[b]) <= 1e-12 and np.max(np.abs(g1 - gb)) <= 1e-12
+    batch.close()

@@ -142,5 +142,114 @@ def test_states_smaller_than_the_tile(Q, orc, dtype, n):
     for geom in geoms:
         e, g, psi = run(Q, n, gates, theta, codes, coeffs, dtype, geom)
         tol_check(dtype, e, g, psi, e_ref, g_ref, psi_ref, coeffs)
-    with Q.StateVector(n, dtype) as sv:       # the automatic geometry
-        assert sv.get_fusion()[0] == 1
+    with Q.StateVector(n, dtype) as sv:       # the automatic mode: one wave up to 6 qubits
+        assert sv.get_fusion()[0] == (2 if n <= 6 else 1)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 4, 5, 6])
+def test_one_wave_sweep(Q, orc, dtype, n):
+    """Algorithm 1 in one wave (states of up to 6 qubits): every gate kind, repeated parameters,
+    a prepared input state, against the oracle; the automatic mode takes this path."""
+    rng = np.random.default_rng(500 + n)
+    kinds = [k for k in ALL_KINDS if n >= 2 or W.N_QUBITS[k] == 1]
+    gates, P = W.random_circuit(rng, n, 150, kinds, n_params=40)
+    theta = W.uniform_angles(rng, P)
+    prep, Pp = W.random_circuit(rng, n, 20, [W.RY, W.RX, W.CNOT] if n >= 2 else [W.RY, W.RX])
+    theta_p = W.uniform_angles(rng, Pp)
+    codes = W.random_pauli_strings(rng, n, 6)
+    coeffs = rng.standard_normal(6)
+    psi_in = orc.statevector(n, prep, theta_p)
+    e_ref, g_ref = orc.adjoint_gradient(n, gates, theta, codes, coeffs, psi_in=psi_in)
+    for mode in (2, -1):
+        with Q.StateVector(n, dtype) as sv:
+            sv.set_fusion(mode)
+            sv.apply_circuit(prep, theta_p)
+            e, g = sv.adjoint_gradient(gates, theta, codes, coeffs)
+            sv.sync()
+            assert sv.get_fusion() == (2, 0, 0)
+            e, g = float(e.cpu()[0]), g.cpu().numpy()
+        if dtype == "c128":
+            assert abs(e - e_ref.real) <= 1e-10 and np.max(np.abs(g - g_ref)) <= 1e-10
+        else:
+            assert abs(e - e_ref.real) <= 2e-4 * max(abs(e_ref), 1.0)
+            assert np.max(np.abs(g - g_ref)) <= 2e-4 * max(np.max(np.abs(g_ref)),
+                                                         1e-5 * np.abs(coeffs).sum())
+
+
+def test_one_wave_mode_needs_a_small_state(Q):
+    with Q.StateVector(7) as sv:
+        with pytest.raises(Q.QsvError):
+            sv.set_fusion(2)
+
+
+UNITARY_KINDS = [k for k in ALL_KINDS if k not in (W.NRX, W.NRY, W.NRZ)]
+assert set(UNITARY_KINDS) == set(ALL_KINDS)  # the named kinds are the unitary ones
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_chunked_sweep(Q, orc, dtype, n):
+    """The chunked one-wave sweep (mode 3): chunk operators, boundary states carried by them, and
+    the per-chunk steps; every unitary kind, repeated parameters, a prepared input state, gate
+    counts of one partial chunk up to many chunks; the automatic mode takes it for long circuits
+    and gives the same result; repeated calls and graph replays re-arm the finish counter."""
+    import torch
+    rng = np.random.default_rng(700 + n)
+    kinds = [k for k in UNITARY_KINDS if n >= 2 or W.N_QUBITS[k] == 1]
+    prep, Pp = W.random_circuit(rng, n, 20, [W.RY, W.RX, W.CNOT] if n >= 2 else [W.RY, W.RX])
+    theta_p = W.uniform_angles(rng, Pp)
+    psi_in = orc.statevector(n, prep, theta_p)
+    for G in (1, 64, 65, 300):
+        gates, P = W.random_circuit(rng, n, G, kinds, n_params=max(3, G // 3))
+        theta = W.uniform_angles(rng, P)
+        codes = W.random_pauli_strings(rng, n, 6)
+        coeffs = rng.standard_normal(6)
+        e_ref, g_ref = orc.adjoint_gradient(n, gates, theta, codes, coeffs, psi_in=psi_in)
+        results = []
+        for mode, graphs in ((3, False), (3, True), (-1, False)):
+            with Q.StateVector(n, dtype) as sv:
+                sv.set_fusion(mode)
+                sv.set_graphs(graphs)
+                sv.apply_circuit(prep, theta_p)
+                th = torch.as_tensor(theta, device="cuda:0")
+                for rep in range(3):
+                    e, g = sv.adjoint_gradient(gates, th, codes, coeffs)
+                    sv.sync()
+                    e, g = float(e.cpu()[0]), g.cpu().numpy()
+                    if dtype == "c128":
+                        assert abs(e - e_ref.real) <= 1e-10, (G, mode, rep)
+                        assert np.max(np.abs(g - g_ref)) <= 1e-10, (G, mode, rep)
+                    else:
+                        assert abs(e - e_ref.real) <= 2e-4 * max(abs(e_ref), 1.0)
+                        assert np.max(np.abs(g - g_ref)) <= 2e-4 * max(
+                            np.max(np.abs(g_ref)), 1e-5 * np.abs(coeffs).sum())
+                    results.append((e, g))
+        if G >= 192:  # the automatic mode ran the chunked kernels too
+            assert results[-1][0] == results[0][0] and np.array_equal(results[-1][1], results[0][1])
+
+
+def test_chunked_mode_limits(Q, orc):
+    """Mode 3 needs at most 5 qubits; a circuit with a non-unitary gate runs the plain one-wave
+    sweep under mode 3 (phi cannot be carried back by W_c^dag)."""
+    with Q.StateVector(6) as sv:
+        with pytest.raises(Q.QsvError):
+            sv.set_fusion(3)
+    rng = np.random.default_rng(9)
+    n = 4
+    gates, P = W.random_circuit(rng, n, 250, ALL_KINDS)
+    rot = [i for i in range(len(gates)) if int(gates[i, 0]) in (W.RX, W.RY, W.RZ)]
+    for i in rot[::len(rot) // 4][:4]:  # four rotations become their non-unitary variants
+        gates[i, 0] = {W.RX: W.NRX, W.RY: W.NRY, W.RZ: W.NRZ}[int(gates[i, 0])]
+    theta = W.uniform_angles(rng, P)
+    codes = W.random_pauli_strings(rng, n, 5)
+    coeffs = rng.standard_normal(5)
+    e_ref, g_ref = orc.adjoint_gradient(n, gates, theta, codes, coeffs)
+    with Q.StateVector(n) as sv:
+        sv.set_fusion(3)
+        assert sv.get_fusion() == (3, 0, 0)
+        e, g = sv.adjoint_gradient(gates, theta, codes, coeffs)
+        sv.sync()
+        scale = max(1.0, abs(e_ref), float(np.max(np.abs(g_ref))))  # the norm is not kept
+        assert abs(float(e.cpu()[0]) - e_ref.real) <= 1e-10 * scale
+        assert np.max(np.abs(g.cpu().numpy() - g_ref)) <= 1e-10 * scale

@@ -418,6 +418,63 @@ def paper_sweep(qsv, torch, W, n, layers_list, runs, cpu):
             "loglog_slopes": fit}
 
 
+def paper_batch(qsv, torch, W, n, layers_list, B, runs):
+    """The paper's comparison at batch scale: B circuits of the paper's regime per L (the same
+    ansatz, independent uniform angles per circuit) through Algorithm 1
+    (qsv_adjoint_gradient_batched, one wave per circuit) and Algorithm 2
+    (qsv_reference_gradient_batched, one wave per circuit and parameter occurrence). Device time
+    is the sum of the library's event-timed launches per call (mean over `runs` calls); wall time
+    also holds the host's per-call work (plan lookups of B handles). A sample of circuits is
+    checked between the two algorithms."""
+    import numpy as np
+    rows = []
+    for L in layers_list:
+        base = W.paper_benchmark(n, L)
+        rng = np.random.default_rng(1000 + L)
+        probs = [W.Problem(f"{base.name}_{b}", n, base.gates,
+                           W.uniform_angles(rng, base.n_params), base.codes, base.coeffs)
+                 for b in range(B)]
+        batch = qsv.Batch(probs)
+        th = batch.theta_flat()
+        e = torch.empty(B, dtype=torch.float64, device="cuda:0")
+        g1 = torch.empty(batch.n_params, dtype=torch.float64, device="cuda:0")
+        g2 = torch.empty_like(g1)
+        row = {"layers": L, "P": base.n_params, "gates": base.n_gates, "circuits": B}
+        h0 = batch.handles[0]
+        for name, fn, g in (("adjoint", batch.adjoint_gradient, g1),
+                            ("reference", batch.reference_gradient, g2)):
+            fn(th, e, g)
+            torch.cuda.synchronize()
+            h0.timing_enable("")
+            t0 = time.perf_counter()
+            for _ in range(runs):
+                fn(th, e, g)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / runs
+            st = h0.timing_read()
+            h0.timing_enable(None)
+            dev = sum(x["total_ms"] for x in st) * 1e-3 / runs
+            row[name + "_device_s"] = dev
+            row[name + "_wall_s"] = wall
+            row[name + "_gradients_per_s"] = B / dev
+            row[name + "_kernels"] = {x["name"]: x["total_ms"] / runs for x in st}
+        d = (g1 - g2).abs().max().item()
+        row["max_abs_diff"] = d
+        row["speedup_device"] = row["reference_device_s"] / row["adjoint_device_s"]
+        batch.close()
+        del batch, th, e, g1, g2
+        rows.append(row)
+        log(f"batch N={n} L={L} P={base.n_params} B={B}: Alg. 1 {1e3 * row['adjoint_device_s']:.3f} "
+            f"ms ({row['adjoint_gradients_per_s']:.3g} gradients/s), Alg. 2 "
+            f"{1e3 * row['reference_device_s']:.3f} ms, speedup {row['speedup_device']:.1f}, "
+            f"|dg| {d:.1e}")
+    lp = np.log([r["P"] for r in rows])
+    keys = ["adjoint_device_s", "reference_device_s", "speedup_device"]
+    fit = {k: float(np.polyfit(lp, np.log([r[k] for r in rows]), 1)[0]) for k in keys}
+    return {"n_qubits": n, "observable": "Hadamard^(x)n", "circuits": B, "runs": runs,
+            "rows": rows, "loglog_slopes": fit}
+
+
 def roofline_of(res, S, flops_bwd, flops_fwd, steps, workload, dtype):
     """The dominant family's HBM fraction (algorithmic bytes per launch over the event-timed
     average launch) and its FP64 VALU fraction (algorithmic flops of the family's sweep per step
@@ -497,6 +554,9 @@ def main():
                          "on the GPU, P up to 1290, 24 runs per point")
     ap.add_argument("--paper-cpu", action="store_true",
                     help="with --paper: also time the CPU oracle's Algorithms 1 and 2")
+    ap.add_argument("--paper-batch", type=int, default=0, metavar="B",
+                    help="with --paper: also B circuits per point through the batched Algorithms "
+                         "1 and 2 (device throughput)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -524,6 +584,8 @@ def main():
         n = args.paper
         layers = [1, 2, 4, 8, 16, 32, 64, 1290 // (2 * n)]
         res = paper_sweep(qsv, torch, W, n, layers, 24, args.paper_cpu)
+        if args.paper_batch:
+            res["batch"] = paper_batch(qsv, torch, W, n, layers, args.paper_batch, 3)
         print(json.dumps({"metric": "Algorithm 1 vs Algorithm 2 gradient time over P", **res}))
         return
 

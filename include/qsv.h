@@ -224,13 +224,29 @@ qsv_status qsv_param_shift_gradient(qsv_state* s, const qsv_gate* gates, int32_t
 /* The same energy and gradient by the reference scheme of Algorithm 2 (Sec. 3): lambda = H U |in>,
    then for every parameter occurrence i a separate simulation mu = U_G..U_{i+1} dU_i/dtheta
    U_{i-1}..U_1 |in> and the entry 2 Re <lambda|mu> (summed over the occurrences of a repeated
-   parameter); O(P^2) gate applications. Arguments and results as qsv_adjoint_gradient. States that
-   fit one fused tile (see qsv_set_fusion) run all entries in parallel, one workgroup each, with a
-   library-allocated pool of up to 1 GiB of mu states; larger states run the entries one after
-   another in the phi buffer. Meant as the faithful comparison baseline for small circuits. */
+   parameter); O(P^2) gate applications. Arguments and results as qsv_adjoint_gradient. States of
+   at most 6 qubits (automatic fusion mode, or mode 2 or 3) run in waves: one wave forms lambda,
+   then one wave per parameter occurrence its simulation and entry, all at once. Larger states
+   that fit one fused tile (see qsv_set_fusion) run all entries in parallel, one workgroup each,
+   with a library-allocated pool of up to 1 GiB of mu states; larger states run the entries one
+   after another in the phi buffer. Meant as the faithful comparison baseline for small
+   circuits. */
 qsv_status qsv_reference_gradient(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
                                   const double* d_theta, int32_t n_theta, const qsv_pauli_sum* H,
                                   double* d_energy, double* d_grad);
+
+/* Algorithm 2 (as qsv_reference_gradient) for a batch of independent circuits; arguments and
+   results as qsv_adjoint_gradient_batched. When every state has at most 6 qubits (and the
+   automatic fusion mode or mode 2 or 3), one launch runs lambda = H U |in> of every circuit (one
+   wave each), one launch the simulation of every (circuit, parameter occurrence) pair (one wave
+   each) and one launch the gradient entries; otherwise the circuits run one after the other.
+   The batch counterpart of the O(P^2) baseline, for throughput comparisons with
+   qsv_adjoint_gradient_batched. */
+qsv_status qsv_reference_gradient_batched(int32_t n_batch, qsv_state* const* states,
+                                          const qsv_gate* const* gates, const int32_t* n_gates,
+                                          const double* d_theta_flat, const int64_t* theta_off,
+                                          const int32_t* n_theta, const qsv_pauli_sum* H,
+                                          double* d_energy, double* d_grad_flat);
 
 /* Non-Hermitian operator A = sum_t (A->coeffs[t] + i coeffs_im[t]) P_t (App. B.4): the complex
    expectation <A> = <psi|A|psi>, psi = U |in>, and its complex gradient. Algorithm 1 runs twice

@@ -225,6 +225,10 @@ struct Plan {
   // one-wave sweep (states of at most kWaveMaxQubits qubits): one product sum per slot
   DevBuf wave_slot_sum;
   bool all_unitary = true;
+  bool wave_needs_recs = false;  // a gate the wave kernels read from its record
+  // Algorithm 2 in waves: lambda, and the gate and parameter of each slot (k * 4 + j)
+  bool wave_ready = false;
+  DevBuf wave_ref_lam, wave_occ_gate;
   // chunked one-circuit sweep: chunk operators, boundary states, first slots, finish counter
   bool wc_ready = false;
   int wc_chunks = 0;
@@ -439,7 +443,9 @@ struct BatchPlan {
   int total_gates = 0;
   // one-wave batch (every circuit of at most kWaveMaxQubits qubits): one wave per circuit
   bool wave = false;
+  bool wave_needs_recs = false;
   DevBuf d_wave_jobs;
+  uint64_t key = 0;  // the cache key (graph keys of its calls derive from it)
 };
 
 static constexpr int kBatchPauliBlocks = 128;  // blocks per circuit of the batched H apply
@@ -581,7 +587,10 @@ static qsv_status get_plan(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
     slot += np;
   }
   p->n_occ = slot;
-  for (const GateDesc& g : p->gates) p->all_unitary = p->all_unitary && kind_unitary(g.kind);
+  for (const GateDesc& g : p->gates) {
+    p->all_unitary = p->all_unitary && kind_unitary(g.kind);
+    p->wave_needs_recs = p->wave_needs_recs || !wave_native_kind(g.kind);
+  }
   p->param_ptr.assign(n_theta + 1, 0);
   for (int q = 0; q < n_theta; ++q) {
     p->param_ptr[q + 1] = p->param_ptr[q] + (int32_t)per_param[q].size();
@@ -1145,14 +1154,26 @@ static qsv_status get_wave_chunks(qsv_state* s, Plan* p) {
 }
 
 static qsv_status get_wave(qsv_state* s, Plan* p) {
-  return p->wave_slot_sum.ensure(sizeof(double) * (size_t)std::max(p->n_occ, 1), s->stream);
+  if (p->wave_ready) return QSV_OK;
+  const hipStream_t st = s->stream;
+  QSV_TRY(p->wave_slot_sum.ensure(sizeof(double) * (size_t)std::max(p->n_occ, 1), st));
+  QSV_TRY(p->wave_ref_lam.ensure(sizeof(double2) * 64, st));
+  std::vector<int32_t> occ_gate(std::max(p->n_occ, 1), 0);
+  for (size_t k = 0; k < p->gates.size(); ++k)
+    for (int j = 0; j < kind_nparams(p->gates[k].kind); ++j)
+      occ_gate[p->slot_of_gate[k] + j] = (int32_t)k * 4 + j;
+  QSV_TRY(upload_vec(p->wave_occ_gate, occ_gate, st));
+  p->wave_ready = true;
+  return QSV_OK;
 }
 
-static WaveJob wave_job(qsv_state* s, Plan* p, PauliPlan* hp, double* d_energy, double* d_grad) {
+static WaveJob wave_job(qsv_state* s, Plan* p, PauliPlan* hp, const double* d_theta,
+                        double* d_energy, double* d_grad) {
   WaveJob J;
   std::memset(&J, 0, sizeof J);
   J.gates = p->d_gates.as<GateDesc>();
   J.recs = p->d_recs.as<GateRec>();
+  J.theta = d_theta;
   J.in = s->d_state;
   J.groups = hp->d_groups.as<PauliGroup>();
   J.terms = hp->d_terms.as<PauliTerm>();
@@ -1165,7 +1186,25 @@ static WaveJob wave_job(qsv_state* s, Plan* p, PauliPlan* hp, double* d_energy, 
   J.n = s->n;
   J.n_groups = (int32_t)hp->groups.size();
   J.n_theta = p->n_theta;
+  J.ref_lam = p->wave_ref_lam.as<double2>();
+  J.occ_gate = p->wave_occ_gate.as<int32_t>();
+  J.n_occ = p->n_occ;
   return J;
+}
+
+// Algorithm 2 in waves (launch_wave_reference), after the launch that fills the gate records.
+template <typename R>
+static qsv_status wave_reference_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* d_theta,
+                                   double* d_energy, double* d_grad) {
+  const hipStream_t st = s->stream;
+  QSV_TRY(get_wave(s, p));
+  if (p->wave_needs_recs)
+    HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
+                        p->d_recs.as<GateRec>(), st));
+  const WaveJob J = wave_job(s, p, hp, d_theta, d_energy, d_grad);
+  return timed(s, "k_wave_reference", (p->n_occ + 1.0) * state_bytes_d(s), [&] {
+    return launch_wave_reference<R>(nullptr, 1, p->n_occ, J, nullptr, d_energy, d_grad, st);
+  });
 }
 
 // Algorithm 1 in one wave: the forward pass, H, the reverse sweep and the gradient entries in
@@ -1175,9 +1214,10 @@ static qsv_status wave_adjoint_t(qsv_state* s, Plan* p, PauliPlan* hp, const dou
                                  double* d_energy, double* d_grad) {
   const hipStream_t st = s->stream;
   QSV_TRY(get_wave(s, p));
-  HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
-                      p->d_recs.as<GateRec>(), st));
-  const WaveJob J = wave_job(s, p, hp, d_energy, d_grad);
+  if (p->wave_needs_recs)
+    HIP_TRY(launch_prep(p->d_gates.as<GateDesc>(), (int)p->gates.size(), d_theta,
+                        p->d_recs.as<GateRec>(), st));
+  const WaveJob J = wave_job(s, p, hp, d_theta, d_energy, d_grad);
   if (wave_chunked(s, p)) {
     QSV_TRY(get_wave_chunks(s, p));
     WaveChunks K;
@@ -1194,7 +1234,7 @@ static qsv_status wave_adjoint_t(qsv_state* s, Plan* p, PauliPlan* hp, const dou
     });
   }
   return timed(s, "k_wave_adjoint", 3 * state_bytes_d(s), [&] {
-    return launch_wave_adjoint<R>(nullptr, 1, J, nullptr, nullptr, st);
+    return launch_wave_adjoint<R>(nullptr, 1, J, nullptr, nullptr, nullptr, st);
   });
 }
 
@@ -1487,7 +1527,8 @@ static qsv_status build_batch_wave(qsv_state* const* states, const std::vector<P
   std::vector<WaveJob> jobs(B);
   for (int b = 0; b < B; ++b) {
     QSV_TRY(get_wave(states[b], plans[b]));
-    WaveJob J = wave_job(states[b], plans[b], hps[b], nullptr, nullptr);
+    WaveJob J = wave_job(states[b], plans[b], hps[b], nullptr, nullptr, nullptr);
+    bp->wave_needs_recs = bp->wave_needs_recs || plans[b]->wave_needs_recs;
     J.gates = bp->d_gates_all.as<GateDesc>() + gate_base[b];
     J.recs = bp->d_recs_all.as<GateRec>() + gate_base[b];
     J.grad_off = theta_off[b];
@@ -1507,13 +1548,16 @@ static qsv_status batched_wave_t(qsv_state* const* states, int B, BatchPlan* bp,
   qsv_state* s0 = states[0];
   const hipStream_t st = s0->stream;
   (void)theta_off;
-  HIP_TRY(launch_prep(bp->d_gates_all.as<GateDesc>(), bp->total_gates, d_theta_flat,
-                      bp->d_recs_all.as<GateRec>(), st));
+  if (bp->wave_needs_recs)
+    QSV_TRY(timed(s0, "k_prep", 0, [&] {
+      return launch_prep(bp->d_gates_all.as<GateDesc>(), bp->total_gates, d_theta_flat,
+                         bp->d_recs_all.as<GateRec>(), st);
+    }));
   double bytes = 0;
   for (int b = 0; b < B; ++b) bytes += 3.0 * (double)qsv_state_bytes(states[b]->n, states[b]->dt);
   return timed(s0, "k_wave_adjoint", bytes, [&] {
-    return launch_wave_adjoint<R>(bp->d_wave_jobs.as<WaveJob>(), B, WaveJob{}, d_energy,
-                                  d_grad_flat, st);
+    return launch_wave_adjoint<R>(bp->d_wave_jobs.as<WaveJob>(), B, WaveJob{}, d_theta_flat,
+                                  d_energy, d_grad_flat, st);
   });
 }
 
@@ -1682,14 +1726,16 @@ static qsv_status batched_t(qsv_state* const* states, int B, const std::vector<P
   return QSV_OK;
 }
 
-extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* const* states,
-                                                   const qsv_gate* const* gates,
-                                                   const int32_t* n_gates,
-                                                   const double* d_theta_flat,
-                                                   const int64_t* theta_off,
-                                                   const int32_t* n_theta,
-                                                   const qsv_pauli_sum* H, double* d_energy,
-                                                   double* d_grad_flat) {
+template <typename R>
+static qsv_status reference_t(qsv_state* s, Plan* p, PauliPlan* hp, const double* d_theta,
+                              double* d_energy, double* d_grad);
+
+// Checks of a batch call (qsv_adjoint_gradient_batched, qsv_reference_gradient_batched).
+static qsv_status batch_validate(int32_t n_batch, qsv_state* const* states,
+                                 const qsv_gate* const* gates, const int32_t* n_gates,
+                                 const double* d_theta_flat, const int64_t* theta_off,
+                                 const int32_t* n_theta, const qsv_pauli_sum* H,
+                                 const double* d_energy, const double* d_grad_flat) {
   if (n_batch < 1) return fail(QSV_ERR_INVALID_ARG, "n_batch = %d < 1", n_batch);
   if (!states || !gates || !n_gates || !theta_off || !n_theta || !H)
     return fail(QSV_ERR_INVALID_ARG, "NULL batch array");
@@ -1711,17 +1757,90 @@ extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* c
   }
   if (any_theta && (!d_theta_flat || !d_grad_flat))
     return fail(QSV_ERR_INVALID_ARG, "d_theta_flat or d_grad_flat is NULL");
-  StreamOverride so(states, n_batch, s0->stream);
-  std::vector<Plan*> plans(n_batch);
-  std::vector<PauliPlan*> hps(n_batch);
+  return QSV_OK;
+}
+
+// The circuits' plans and Pauli plans (on states[0]'s stream, which the caller has set).
+static qsv_status batch_plans(int32_t n_batch, qsv_state* const* states,
+                              const qsv_gate* const* gates, const int32_t* n_gates,
+                              const double* d_theta_flat, const int32_t* n_theta,
+                              const qsv_pauli_sum* H, std::vector<Plan*>& plans,
+                              std::vector<PauliPlan*>& hps) {
+  plans.assign(n_batch, nullptr);
+  hps.assign(n_batch, nullptr);
   for (int b = 0; b < n_batch; ++b) {
     QSV_TRY(get_plan(states[b], gates[b], n_gates[b], n_theta[b], &plans[b]));
     QSV_TRY(check_theta(plans[b], d_theta_flat));
     QSV_TRY(get_pauli(states[b], &H[b], &hps[b]));
   }
-  // every circuit small enough for one wave: one launch of one wave per circuit
+  return QSV_OK;
+}
+
+// The cached batch plan of these circuits (wave: one wave per circuit; else the fused levels of
+// geometry (r, w)), built on first use.
+static qsv_status get_batch_plan(int32_t n_batch, qsv_state* const* states,
+                                 const std::vector<Plan*>& plans,
+                                 const std::vector<PauliPlan*>& hps, const int64_t* theta_off,
+                                 bool wave, int r, int w, BatchPlan** out) {
+  qsv_state* s0 = states[0];
+  uint64_t key = fnv1a(&n_batch, sizeof n_batch);
+  key = fnv1a(states, sizeof(qsv_state*) * n_batch, key);
+  key = fnv1a(plans.data(), sizeof(Plan*) * n_batch, key);
+  key = fnv1a(theta_off, sizeof(int64_t) * n_batch, key);
+  key = fnv1a(&r, sizeof r, key);
+  key = fnv1a(&w, sizeof w, key);
+  key = fnv1a(&wave, sizeof wave, key);
+  std::vector<uint64_t> serials;
+  for (int b = 0; b < n_batch; ++b) {
+    serials.push_back(plans[b]->serial);
+    serials.push_back(hps[b]->serial);
+  }
+  key = fnv1a(serials.data(), sizeof(uint64_t) * serials.size(), key);
+  auto it = s0->batches.find(key);
+  if (it != s0->batches.end() && it->second->serials == serials &&
+      std::equal(it->second->states.begin(), it->second->states.end(), states)) {
+    *out = it->second.get();
+    return QSV_OK;
+  }
+  if (s0->batches.size() >= kMaxCachedBatches) {
+    HIP_TRY(hipStreamSynchronize(s0->stream));
+    s0->batches.clear();
+  }
+  auto nbp = std::make_unique<BatchPlan>();
+  if (wave)
+    QSV_TRY(build_batch_wave(states, plans, hps, n_batch, theta_off, nbp.get()));
+  else
+    QSV_TRY(build_batch(states, plans, hps, n_batch, theta_off, r, w, nbp.get()));
+  nbp->serials = serials;
+  nbp->key = key;
+  *out = nbp.get();
+  s0->batches[key] = std::move(nbp);
+  return QSV_OK;
+}
+
+static bool batch_is_wave(int32_t n_batch, qsv_state* const* states) {
   bool wave = true;
   for (int b = 0; b < n_batch && wave; ++b) wave = wave_path(states[b]);
+  return wave;
+}
+
+extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* const* states,
+                                                   const qsv_gate* const* gates,
+                                                   const int32_t* n_gates,
+                                                   const double* d_theta_flat,
+                                                   const int64_t* theta_off,
+                                                   const int32_t* n_theta,
+                                                   const qsv_pauli_sum* H, double* d_energy,
+                                                   double* d_grad_flat) {
+  QSV_TRY(batch_validate(n_batch, states, gates, n_gates, d_theta_flat, theta_off, n_theta, H,
+                         d_energy, d_grad_flat));
+  qsv_state* s0 = states[0];
+  StreamOverride so(states, n_batch, s0->stream);
+  std::vector<Plan*> plans;
+  std::vector<PauliPlan*> hps;
+  QSV_TRY(batch_plans(n_batch, states, gates, n_gates, d_theta_flat, n_theta, H, plans, hps));
+  // every circuit small enough for one wave: one launch of one wave per circuit
+  const bool wave = batch_is_wave(n_batch, states);
   // a common tile geometry that fits every circuit; otherwise one circuit after the other
   int r = 0, w = 0;
   bool fused = !wave && fusion_geometry(s0, &r, &w);
@@ -1741,40 +1860,11 @@ extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* c
     }
     return QSV_OK;
   }
-  uint64_t key = fnv1a(&n_batch, sizeof n_batch);
-  key = fnv1a(states, sizeof(qsv_state*) * n_batch, key);
-  key = fnv1a(plans.data(), sizeof(Plan*) * n_batch, key);
-  key = fnv1a(theta_off, sizeof(int64_t) * n_batch, key);
-  key = fnv1a(&r, sizeof r, key);
-  key = fnv1a(&w, sizeof w, key);
-  key = fnv1a(&wave, sizeof wave, key);
-  std::vector<uint64_t> serials;
-  for (int b = 0; b < n_batch; ++b) {
-    serials.push_back(plans[b]->serial);
-    serials.push_back(hps[b]->serial);
-  }
-  key = fnv1a(serials.data(), sizeof(uint64_t) * serials.size(), key);
   BatchPlan* bp = nullptr;
-  auto it = s0->batches.find(key);
-  if (it != s0->batches.end() && it->second->serials == serials &&
-      std::equal(it->second->states.begin(), it->second->states.end(), states)) {
-    bp = it->second.get();
-  } else {
-    if (s0->batches.size() >= kMaxCachedBatches) {
-      HIP_TRY(hipStreamSynchronize(s0->stream));
-      s0->batches.clear();
-    }
-    auto nbp = std::make_unique<BatchPlan>();
-    if (wave)
-      QSV_TRY(build_batch_wave(states, plans, hps, n_batch, theta_off, nbp.get()));
-    else
-      QSV_TRY(build_batch(states, plans, hps, n_batch, theta_off, r, w, nbp.get()));
-    nbp->serials = serials;
-    bp = nbp.get();
-    s0->batches[key] = std::move(nbp);
-  }
+  QSV_TRY(get_batch_plan(n_batch, states, plans, hps, theta_off, wave, r, w, &bp));
   const void* key_parts[3] = {d_theta_flat, d_energy, d_grad_flat};
-  const uint64_t gkey = fnv1a(key_parts, sizeof key_parts, fnv1a(&bp->serial, sizeof bp->serial, key));
+  const uint64_t gkey =
+      fnv1a(key_parts, sizeof key_parts, fnv1a(&bp->serial, sizeof bp->serial, bp->key));
   return run_graph(
       s0, gkey,
       [&] {
@@ -1790,6 +1880,65 @@ extern "C" qsv_status qsv_adjoint_gradient_batched(int32_t n_batch, qsv_state* c
                                       d_energy, d_grad_flat);
       },
       states + 1, n_batch - 1);
+}
+
+template <typename R>
+static qsv_status batched_wave_reference_t(qsv_state* const* states, int B, BatchPlan* bp,
+                                           const double* d_theta_flat, double* d_energy,
+                                           double* d_grad_flat) {
+  qsv_state* s0 = states[0];
+  const hipStream_t st = s0->stream;
+  if (bp->wave_needs_recs)
+    QSV_TRY(timed(s0, "k_prep", 0, [&] {
+      return launch_prep(bp->d_gates_all.as<GateDesc>(), bp->total_gates, d_theta_flat,
+                         bp->d_recs_all.as<GateRec>(), st);
+    }));
+  double bytes = 0;
+  int max_occ = 0;
+  for (int b = 0; b < B; ++b) {
+    bytes += (bp->plans[b]->n_occ + 1.0) * (double)qsv_state_bytes(states[b]->n, states[b]->dt);
+    max_occ = std::max(max_occ, bp->plans[b]->n_occ);
+  }
+  return timed(s0, "k_wave_reference", bytes, [&] {
+    return launch_wave_reference<R>(bp->d_wave_jobs.as<WaveJob>(), B, max_occ, WaveJob{},
+                                    d_theta_flat, d_energy, d_grad_flat, st);
+  });
+}
+
+extern "C" qsv_status qsv_reference_gradient_batched(int32_t n_batch, qsv_state* const* states,
+                                                     const qsv_gate* const* gates,
+                                                     const int32_t* n_gates,
+                                                     const double* d_theta_flat,
+                                                     const int64_t* theta_off,
+                                                     const int32_t* n_theta,
+                                                     const qsv_pauli_sum* H, double* d_energy,
+                                                     double* d_grad_flat) {
+  QSV_TRY(batch_validate(n_batch, states, gates, n_gates, d_theta_flat, theta_off, n_theta, H,
+                         d_energy, d_grad_flat));
+  qsv_state* s0 = states[0];
+  StreamOverride so(states, n_batch, s0->stream);
+  std::vector<Plan*> plans;
+  std::vector<PauliPlan*> hps;
+  QSV_TRY(batch_plans(n_batch, states, gates, n_gates, d_theta_flat, n_theta, H, plans, hps));
+  if (!batch_is_wave(n_batch, states)) {
+    for (int b = 0; b < n_batch; ++b) {
+      qsv_state* s = states[b];
+      double* g = d_grad_flat ? d_grad_flat + theta_off[b] : nullptr;
+      const double* th = d_theta_flat ? d_theta_flat + theta_off[b] : nullptr;
+      if (s->dt == QSV_C128)
+        QSV_TRY(reference_t<double>(s, plans[b], hps[b], th, d_energy + b, g));
+      else
+        QSV_TRY(reference_t<float>(s, plans[b], hps[b], th, d_energy + b, g));
+    }
+    return QSV_OK;
+  }
+  BatchPlan* bp = nullptr;
+  QSV_TRY(get_batch_plan(n_batch, states, plans, hps, theta_off, true, 0, 0, &bp));
+  return s0->dt == QSV_C128
+             ? batched_wave_reference_t<double>(states, n_batch, bp, d_theta_flat, d_energy,
+                                                d_grad_flat)
+             : batched_wave_reference_t<float>(states, n_batch, bp, d_theta_flat, d_energy,
+                                               d_grad_flat);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -2055,6 +2204,9 @@ extern "C" qsv_status qsv_reference_gradient(qsv_state* s, const qsv_gate* gates
   QSV_TRY(check_theta(p, d_theta));
   PauliPlan* hp = nullptr;
   QSV_TRY(get_pauli(s, H, &hp));
+  if (wave_path(s))
+    return s->dt == QSV_C128 ? wave_reference_t<double>(s, p, hp, d_theta, d_energy, d_grad)
+                             : wave_reference_t<float>(s, p, hp, d_theta, d_energy, d_grad);
   return s->dt == QSV_C128 ? reference_t<double>(s, p, hp, d_theta, d_energy, d_grad)
                            : reference_t<float>(s, p, hp, d_theta, d_energy, d_grad);
 }

@@ -70,7 +70,8 @@ constexpr int pauli_tile_elements(bool) { return 8; }
 constexpr int kWaveMaxQubits = 6;
 struct WaveJob {
   const GateDesc* gates;
-  const GateRec* recs;
+  const GateRec* recs;            // read for the gates other than RX, RY, RZ, CNOT, CZ
+  const double* theta;            // RX, RY, RZ take cos and sin of half their angle from here
   const void* in;                 // |in>, 2^n amplitudes of the storage type
   const PauliGroup* groups;
   const PauliTerm* terms;
@@ -79,9 +80,24 @@ struct WaveJob {
   double* slot_sum;               // [slots] workspace: Re <lambda|mu> per slot
   double* energy;                 // [1] <- E (one circuit)
   double* grad;                   // [n_theta] <- dE/dtheta (one circuit)
-  int64_t grad_off;               // batch: the gradient goes to grad_base + grad_off
+  int64_t grad_off;               // batch: the gradient goes to grad_base + grad_off (the
+                                  // batch's gate tables index the flat theta_base)
+  // Algorithm 2 (launch_wave_reference): lambda = H U|in> and the gate and parameter of each
+  // slot, k * 4 + j
+  double2* ref_lam;               // [64]
+  const int32_t* occ_gate;        // [slots]
   int32_t n_gates, n, n_groups, n_theta;
+  int32_t n_occ, pad;
 };
+
+// Algorithm 2 in waves: one wave per circuit forms lambda = H U|in> and E, then one wave per
+// (circuit, slot) runs the forward pass with that slot's gate replaced by its derivative and
+// forms Re <lambda|mu> (lanes summed in order), then one wave per circuit the gradient entries.
+// max_occ: the largest slot count of the circuits.
+template <typename R>
+hipError_t launch_wave_reference(const WaveJob* d_jobs, int n_jobs, int max_occ,
+                                 const WaveJob& single, const double* theta_base,
+                                 double* energy_base, double* grad_base, hipStream_t st);
 
 // The chunked sweep of one circuit (every gate unitary, at most kWaveChunkMaxQubits qubits): the
 // gates in chunks of 64, each chunk's operator W_c formed in parallel, the states at the chunk
@@ -106,7 +122,13 @@ hipError_t launch_wave_chunked(const WaveJob& J, const WaveChunks& K, hipStream_
 // arguments, so a table serves any outputs).
 template <typename R>
 hipError_t launch_wave_adjoint(const WaveJob* d_jobs, int n_jobs, const WaveJob& single,
-                               double* energy_base, double* grad_base, hipStream_t st);
+                               const double* theta_base, double* energy_base, double* grad_base,
+                               hipStream_t st);
+
+// Gates the one-wave kernels take from their parameters alone (no record needed).
+__host__ __device__ inline bool wave_native_kind(int k) {
+  return k == K_RX || k == K_RY || k == K_RZ || k == K_CNOT || k == K_CZ;
+}
 
 template <typename R>
 hipError_t launch_copy(void* dst, const void* src, int n, hipStream_t st);

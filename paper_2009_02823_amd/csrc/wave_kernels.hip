@@ -30,7 +30,7 @@ namespace {
 
 using C = cx<double>;
 
-constexpr int kRows = 32;       // product slots staged in LDS before their rows are summed
+constexpr int kRows = 16;       // product slots staged in LDS before their rows are summed
 constexpr int kRowStride = 65;  // doubles per row: 64 lanes and one word against bank conflicts
 
 template <int N>
@@ -120,6 +120,8 @@ __device__ __forceinline__ double rl(double v, int i) {
 // ---- gate data, one gate per lane -------------------------------------------------------------
 
 // code = kind | q0 << 8 | q1 << 12; (c, s) = (cos, sin) of half the angle for RX, RY, RZ
+// (RX = [[c, -is], [-is, c]], RY = [[c, -s], [s, c]], RZ = diag(c - is, c + is)), formed here
+// from the angle as the gate records form them
 struct LaneGate {
   int code;
   double c, s;
@@ -128,10 +130,8 @@ __device__ __forceinline__ void load_lane(const WaveJob& J, int base, int lane, 
   const int k = min(base + lane, J.n_gates - 1);
   const GateDesc g = J.gates[k];
   d.code = g.kind | (g.q0 << 8) | (g.q1 << 12);
-  const QSV_GLOBAL double* w = rec_words(J.recs + k);
-  // RX = [[c, -is], [-is, c]], RY = [[c, -s], [s, c]], RZ = diag(c - is, c + is)
-  d.c = w[0];
-  d.s = g.kind == K_RY ? w[4] : g.kind == K_RX ? -w[3] : -w[1];
+  d.c = d.s = 0.0;
+  if (g.kind == K_RX || g.kind == K_RY || g.kind == K_RZ) sincos(0.5 * J.theta[g.p[0]], &d.s, &d.c);
 }
 
 // ---- rotation, CNOT and CZ paths --------------------------------------------------------------
@@ -177,7 +177,15 @@ __device__ __forceinline__ C cmac(C acc, const double2 m, C a) {
   return C{acc.r + m.x * a.r - m.y * a.i, acc.i + m.x * a.i + m.y * a.r};
 }
 __device__ __forceinline__ double2 cj(double2 m) { return make_double2(m.x, -m.y); }
-__device__ __forceinline__ double2 entry(const QSV_GLOBAL double* w, int e) {
+// A gate record read by a whole wave at one gate: the records are written by the launch before
+// (they are constant while this kernel runs), so they are read through the constant address
+// space, i.e. with scalar loads into uniform registers.
+#define QSV_CONST __attribute__((address_space(4)))
+using RecWords = const QSV_CONST double*;
+__device__ __forceinline__ RecWords uniform_words(const GateRec* rec) {
+  return (RecWords)(const void*)rec;
+}
+__device__ __forceinline__ double2 entry(RecWords w, int e) {
   return make_double2(w[2 * e], w[2 * e + 1]);
 }
 
@@ -233,7 +241,7 @@ __device__ __forceinline__ C quad_apply(const double2 m[16], const Quad& Q) {
 // The record's 2x2 matrices: mode 0 = U, 1 = U^-1 (phi), 2 = U^dag (lambda), 3 + j =
 // dU/dtheta_j (U at entries 0..3, dU_0 at 4..7, U^-1 of a non-unitary kind or dU_1 at 8..11,
 // dU_2 at 12..15).
-__device__ __forceinline__ void mat2(const QSV_GLOBAL double* w, int kind, int mode, double2 m[4]) {
+__device__ __forceinline__ void mat2(RecWords w, int kind, int mode, double2 m[4]) {
   if (mode == 1 && !kind_unitary(kind)) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) m[e] = entry(w, 8 + e);
@@ -249,7 +257,7 @@ __device__ __forceinline__ void mat2(const QSV_GLOBAL double* w, int kind, int m
   }
 }
 // 4x4: U at entries 0..15, dU at 16..31 (two-qubit kinds are unitary)
-__device__ __forceinline__ void mat4(const QSV_GLOBAL double* w, int mode, double2 m[16]) {
+__device__ __forceinline__ void mat4(RecWords w, int mode, double2 m[16]) {
   if (mode == 1 || mode == 2) {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -263,7 +271,7 @@ __device__ __forceinline__ void mat4(const QSV_GLOBAL double* w, int mode, doubl
 }
 __device__ __forceinline__ C generic_apply(const GateRec* rec, int kind, int q0, int q1, int mode,
                                            C v, int lane) {
-  const QSV_GLOBAL double* w = rec_words(rec);
+  const RecWords w = uniform_words(rec);
   if (kind_nqubits(kind) == 1) {
     double2 m[4];
     mat2(w, kind, mode, m);
@@ -373,7 +381,7 @@ __device__ __forceinline__ void backward_gate(const WaveJob& J, const LaneGate& 
     lam = rot_z(c, -s, lam, fl);
   } else {
     const GateRec* rec = J.recs + k;
-    const QSV_GLOBAL double* w = rec_words(rec);
+    const RecWords w = uniform_words(rec);
     const int np = kind_nparams(kind);
     if (np == 0) {
       phi = generic_apply(rec, kind, q0, q1, 1, phi, lane);
@@ -391,21 +399,30 @@ __device__ __forceinline__ void backward_gate(const WaveJob& J, const LaneGate& 
         stage(P, slot + j, prod_re(lam, row_apply(d, F)), lane);
       }
     } else {
+      // two-qubit: f = U^dag (the lane's quad), phi = f at the lane's local index, mu = the
+      // lane's row of dU f; matrix rows are read one at a time (uniform loads), so that the 32
+      // entries of U and dU are never all live
       const Quad Q = quad_of(phi, q0, q1, lane);
-      double2 ui[16];
-      mat4(w, 1, ui);
-      Quad F;
-      F.l = Q.l;
+      C f[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        F.a[r] = mul(ui[4 * r], Q.a[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        C a{0, 0};
 #pragma unroll
-        for (int cc = 1; cc < 4; ++cc) F.a[r] = cmac(F.a[r], ui[4 * r + cc], Q.a[cc]);
+        for (int cc = 0; cc < 4; ++cc) a = cmac(a, cj(entry(w, 4 * cc + r)), Q.a[cc]);
+        f[r] = a;
       }
-      phi = pick4(F.l, F.a[0], F.a[1], F.a[2], F.a[3]);
-      double2 d[16];
-      mat4(w, 3, d);
-      stage(P, slot, prod_re(lam, quad_apply(d, F)), lane);
+      phi = pick4(Q.l, f[0], f[1], f[2], f[3]);
+      C mu{0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        __builtin_amdgcn_sched_barrier(0);
+        C o{0, 0};
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) o = cmac(o, entry(w, 16 + 4 * r + cc), f[cc]);
+        mu = sel(Q.l == r, o, mu);
+      }
+      stage(P, slot, prod_re(lam, mu), lane);
     }
     slot += np;
     lam = generic_apply(rec, kind, q0, q1, 2, lam, lane);
@@ -471,11 +488,12 @@ __device__ __forceinline__ void sign_masks(int lane, int sm[6]) {
 
 template <typename R, bool BATCH>
 __global__ void __launch_bounds__(64) k_wave_adjoint(const WaveJob* __restrict__ jobs,
-                                                     WaveJob single, double* energy_base,
-                                                     double* grad_base) {
+                                                     WaveJob single, const double* theta_base,
+                                                     double* energy_base, double* grad_base) {
   __shared__ double rows[kRows * kRowStride];
   WaveJob J = BATCH ? jobs[blockIdx.x] : single;
   if (BATCH) {
+    J.theta = theta_base;  // batch gate tables index the flat parameter vector
     J.energy = energy_base + blockIdx.x;
     J.grad = grad_base ? grad_base + J.grad_off : nullptr;
   }
@@ -672,15 +690,136 @@ __global__ void __launch_bounds__(64) k_wave_chunk_sweep(WaveJob J, WaveChunks K
 
 template <typename R>
 hipError_t launch_wave_adjoint(const WaveJob* d_jobs, int n_jobs, const WaveJob& single,
-                               double* energy_base, double* grad_base, hipStream_t st) {
+                               const double* theta_base, double* energy_base, double* grad_base,
+                               hipStream_t st) {
   if (d_jobs)
     hipLaunchKernelGGL((k_wave_adjoint<R, true>), dim3(n_jobs), dim3(64), 0, st, d_jobs, single,
-                       energy_base, grad_base);
+                       theta_base, energy_base, grad_base);
   else
     hipLaunchKernelGGL((k_wave_adjoint<R, false>), dim3(1), dim3(64), 0, st, d_jobs, single,
-                       energy_base, grad_base);
+                       theta_base, energy_base, grad_base);
   return hipGetLastError();
 }
+
+// ---- Algorithm 2 (the reference scheme of Sec. 3) -------------------------------------------
+
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(64) k_wave_ref_lambda(const WaveJob* __restrict__ jobs,
+                                                        WaveJob single, const double* theta_base,
+                                                        double* energy_base) {
+  __shared__ double scratch[64];
+  WaveJob J = BATCH ? jobs[blockIdx.x] : single;
+  if (BATCH) {
+    J.theta = theta_base;  // batch gate tables index the flat parameter vector
+    J.energy = energy_base + blockIdx.x;
+  }
+  const int lane = threadIdx.x;
+  const int G = J.n_gates;
+  int sm[6];
+  sign_masks(lane, sm);
+  C psi = load_in<R>(J, lane);
+  LaneGate cur{}, nxt{};
+  if (G > 0) load_lane(J, 0, lane, cur);
+  for (int base = 0; base < G; base += 64) {
+    if (base + 64 < G) load_lane(J, base + 64, lane, nxt);
+    const int cnt = min(64, G - base);
+    for (int i = 0; i < cnt; ++i) psi = forward_gate(J, cur, i, base + i, psi, lane, sm);
+    cur = nxt;
+  }
+  const C lam = apply_h(J, psi, lane, scratch, J.energy);
+  J.ref_lam[lane] = make_double2(lam.r, lam.i);
+}
+
+// mu = U_G .. U_k+1 dU_k/dtheta_j U_k-1 .. U_1 |in> for slot o = blockIdx.x (gate k, parameter j
+// of the gate), then slot_sum[o] = Re <lambda|mu>
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(64) k_wave_ref_entry(const WaveJob* __restrict__ jobs,
+                                                       WaveJob single, const double* theta_base) {
+  __shared__ double scratch[64];
+  WaveJob J = BATCH ? jobs[blockIdx.y] : single;
+  if (BATCH) J.theta = theta_base;  // batch gate tables index the flat parameter vector
+  const int o = blockIdx.x;
+  if (o >= J.n_occ) return;
+  const int kd = J.occ_gate[o] >> 2, jd = J.occ_gate[o] & 3;
+  const int lane = threadIdx.x;
+  const int G = J.n_gates;
+  int sm[6];
+  sign_masks(lane, sm);
+  C v = load_in<R>(J, lane);
+  LaneGate cur{}, nxt{};
+  load_lane(J, 0, lane, cur);
+  for (int base = 0; base < G; base += 64) {
+    if (base + 64 < G) load_lane(J, base + 64, lane, nxt);
+    const int cnt = min(64, G - base);
+    for (int i = 0; i < cnt; ++i) {
+      const int k = base + i;
+      if (k == kd) {
+        const int code = rl(cur.code, i);
+        const int kind = code & 31, q0 = (code >> 8) & 7, q1 = (code >> 12) & 7;
+        if (kind == K_RX || kind == K_RY || kind == K_RZ) {
+          // dR/dt = -(s/2) 1 - i (c/2) G: a rotation's form with (c, s) -> (-s/2, c/2)
+          const double c = -0.5 * rl(cur.s, i), s = 0.5 * rl(cur.c, i);
+          if (kind == K_RZ) {
+            v = rot_z(c, s, v, flip(v, sign_mask(lane, q0)));
+          } else {
+            const C p = partner_of(v, q0, lane);
+            v = kind == K_RX ? rot_x(c, s, v, p) : rot_y(c, s, v, flip(p, sign_mask(lane, q0)));
+          }
+        } else {
+          v = generic_apply(J.recs + k, kind, q0, q1, 3 + jd, v, lane);
+        }
+      } else {
+        v = forward_gate(J, cur, i, k, v, lane, sm);
+      }
+    }
+    cur = nxt;
+  }
+  const double2 l = J.ref_lam[lane];
+  scratch[lane] = lane < (1 << J.n) ? l.x * v.r + l.y * v.i : 0.0;
+  __syncthreads();
+  if (lane == 0) {
+    double t = 0;
+    for (int q = 0; q < (1 << J.n); ++q) t += scratch[q];
+    J.slot_sum[o] = t;
+  }
+}
+
+template <bool BATCH>
+__global__ void __launch_bounds__(64) k_wave_ref_grad(const WaveJob* __restrict__ jobs,
+                                                      WaveJob single, double* grad_base) {
+  WaveJob J = BATCH ? jobs[blockIdx.x] : single;
+  if (BATCH) J.grad = grad_base ? grad_base + J.grad_off : nullptr;
+  gradient_entries(J, threadIdx.x);
+}
+
+template <typename R>
+hipError_t launch_wave_reference(const WaveJob* d_jobs, int n_jobs, int max_occ,
+                                 const WaveJob& single, const double* theta_base,
+                                 double* energy_base, double* grad_base, hipStream_t st) {
+  if (d_jobs) {
+    hipLaunchKernelGGL((k_wave_ref_lambda<R, true>), dim3(n_jobs), dim3(64), 0, st, d_jobs,
+                       single, theta_base, energy_base);
+    if (max_occ > 0)
+      hipLaunchKernelGGL((k_wave_ref_entry<R, true>), dim3(max_occ, n_jobs), dim3(64), 0, st,
+                         d_jobs, single, theta_base);
+    hipLaunchKernelGGL((k_wave_ref_grad<true>), dim3(n_jobs), dim3(64), 0, st, d_jobs, single,
+                       grad_base);
+  } else {
+    hipLaunchKernelGGL((k_wave_ref_lambda<R, false>), dim3(1), dim3(64), 0, st, d_jobs, single,
+                       theta_base, energy_base);
+    if (single.n_occ > 0)
+      hipLaunchKernelGGL((k_wave_ref_entry<R, false>), dim3(single.n_occ, 1), dim3(64), 0, st,
+                         d_jobs, single, theta_base);
+    hipLaunchKernelGGL((k_wave_ref_grad<false>), dim3(1), dim3(64), 0, st, d_jobs, single,
+                       grad_base);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_wave_reference<double>(const WaveJob*, int, int, const WaveJob&,
+                                                  const double*, double*, double*, hipStream_t);
+template hipError_t launch_wave_reference<float>(const WaveJob*, int, int, const WaveJob&,
+                                                 const double*, double*, double*, hipStream_t);
 
 template <typename R>
 hipError_t launch_wave_chunked(const WaveJob& J, const WaveChunks& K, hipStream_t st) {
@@ -702,9 +841,9 @@ hipError_t launch_wave_chunked(const WaveJob& J, const WaveChunks& K, hipStream_
 
 template hipError_t launch_wave_chunked<double>(const WaveJob&, const WaveChunks&, hipStream_t);
 template hipError_t launch_wave_chunked<float>(const WaveJob&, const WaveChunks&, hipStream_t);
-template hipError_t launch_wave_adjoint<double>(const WaveJob*, int, const WaveJob&, double*,
-                                                double*, hipStream_t);
-template hipError_t launch_wave_adjoint<float>(const WaveJob*, int, const WaveJob&, double*,
-                                               double*, hipStream_t);
+template hipError_t launch_wave_adjoint<double>(const WaveJob*, int, const WaveJob&,
+                                                const double*, double*, double*, hipStream_t);
+template hipError_t launch_wave_adjoint<float>(const WaveJob*, int, const WaveJob&, const double*,
+                                               double*, double*, hipStream_t);
 
 }  // namespace qsv

@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
         "qsv_adjoint_gradient": ([P, P, i32, P, i32, P, P, P], i32),
         "qsv_energy": ([P, P, i32, P, i32, P, P], i32),
         "qsv_adjoint_gradient_batched": ([i32, P, P, P, P, P, P, P, P, P], i32),
+        "qsv_reference_gradient_batched": ([i32, P, P, P, P, P, P, P, P, P], i32),
         "qsv_param_shift_gradient": ([P, P, i32, P, i32, P, i32, i32, P], i32),
         "qsv_reference_gradient": ([P, P, i32, P, i32, P, P, P], i32),
         "qsv_adjoint_gradient_nonhermitian": ([P, P, i32, P, i32, P, P, P, P], i32),
@@ -483,6 +484,14 @@ class Batch:
         return self._seg
 
     def adjoint_gradient(self, theta_flat, energy=None, grad=None):
+        """(E[b], flat gradient) of every circuit by Algorithm 1 (qsv_adjoint_gradient_batched)."""
+        return self._call(lib().qsv_adjoint_gradient_batched, theta_flat, energy, grad)
+
+    def reference_gradient(self, theta_flat, energy=None, grad=None):
+        """The same by Algorithm 2 (qsv_reference_gradient_batched)."""
+        return self._call(lib().qsv_reference_gradient_batched, theta_flat, energy, grad)
+
+    def _call(self, fn, theta_flat, energy, grad):
         torch = _torch()
         t = torch.as_tensor(theta_flat, dtype=torch.float64)
         if t.device != self.device:
@@ -494,9 +503,8 @@ class Batch:
                                                          device=self.device)
         g = grad if grad is not None else torch.empty(self.n_params, dtype=torch.float64,
                                                      device=self.device)
-        check(lib().qsv_adjoint_gradient_batched(B, self._states, self._gates, self._n_gates,
-                                                 t.data_ptr(), self._theta_off, self._n_theta,
-                                                 self._H, e.data_ptr(), g.data_ptr()))
+        check(fn(B, self._states, self._gates, self._n_gates, t.data_ptr(), self._theta_off,
+                 self._n_theta, self._H, e.data_ptr(), g.data_ptr()))
         return e, g
 
     def sync(self):

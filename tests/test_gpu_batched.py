@@ -240,3 +240,26 @@ def test_wave_batch_paper_circuits(Q, orc):
             else:
                 assert abs(e1 - ec[b]) <= 1e-12 and np.max(np.abs(g1 - gb)) <= 1e-12
     batch.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_wave_batch_reference(Q, orc, dtype):
+    """Algorithm 2 for a batch of circuits of at most 6 qubits (one wave per circuit for lambda,
+    one per (circuit, occurrence)), and for a batch of larger circuits (one after the other),
+    against the oracle."""
+    for probs in (wave_batch(31), small_batch(4, B=3)):
+        batch = Q.Batch(probs, dtype)
+        e, g = batch.reference_gradient(batch.theta_flat())
+        batch.sync()
+        ec, gc = e.cpu().numpy(), g.cpu().numpy()
+        for b, p in enumerate(probs):
+            e_ref, g_ref = orc.adjoint_gradient(p.n_qubits, p.gates, p.theta, p.codes, p.coeffs)
+            gb = gc[batch.theta_off[b]: batch.theta_off[b] + p.n_params]
+            if dtype == "c128":
+                assert abs(ec[b] - e_ref.real) <= 1e-10, b
+                assert p.n_params == 0 or np.max(np.abs(gb - g_ref)) <= 1e-10, b
+            else:
+                assert abs(ec[b] - e_ref.real) <= 2e-4 * max(abs(e_ref), 1.0), b
+                scale = max(np.max(np.abs(g_ref), initial=0), 1e-5 * np.abs(p.coeffs).sum())
+                assert p.n_params == 0 or np.max(np.abs(gb - g_ref)) <= 2e-4 * scale, b
+        batch.close()

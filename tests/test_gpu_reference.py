@@ -80,3 +80,24 @@ def test_no_parameters(Q):
         sv.sync()
         assert abs(float(e.cpu()[0]) - 1.0) < 1e-14
         assert np.all(g.cpu().numpy() == 0.0)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_wave_reference(Q, orc, dtype, n):
+    """Algorithm 2 in waves (states of up to 6 qubits): lambda in one wave, one wave per
+    parameter occurrence; every gate kind including the non-unitary ones, repeated parameters,
+    against the oracle's Algorithm 2."""
+    rng = np.random.default_rng(900 + n)
+    kinds = [k for k in ALL_KINDS + list(W.NONUNITARY_NAMES) if n >= 2 or W.N_QUBITS[k] == 1]
+    gates, P = W.random_circuit(rng, n, 150, kinds, n_params=50)
+    theta = rng.uniform(-0.6, 0.6, P)  # the non-unitary factors stay moderate
+    codes = W.random_pauli_strings(rng, n, 6)
+    coeffs = rng.standard_normal(6)
+    g_ref = orc.reference_gradient(n, gates, theta, codes, coeffs)
+    e_ref, _ = orc.adjoint_gradient(n, gates, theta, codes, coeffs)
+    e, g = reference(Q, n, gates, theta, codes, coeffs, dtype)
+    scale = max(1.0, abs(e_ref), float(np.max(np.abs(g_ref))))
+    tol = 1e-10 if dtype == "c128" else 2e-4
+    assert abs(e - e_ref.real) <= tol * scale
+    assert np.max(np.abs(g - g_ref)) <= tol * scale

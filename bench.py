@@ -411,11 +411,18 @@ def paper_sweep(qsv, torch, W, n, layers_list, runs, cpu):
         log(f"N={n} L={L} P={prob.n_params}: adjoint {1e3 * row['adjoint_s']:.3f} ms, reference "
             f"{1e3 * row['reference_s']:.3f} ms, speedup {row['speedup']:.1f}, "
             f"|dg| {row['max_abs_diff']:.1e}")
-    lp = np.log([r["P"] for r in rows])
     keys = ["adjoint_s", "reference_s", "speedup"] + (["cpu_adjoint_s", "cpu_reference_s"] if cpu else [])
-    fit = {k: float(np.polyfit(lp, np.log([r[k] for r in rows]), 1)[0]) for k in keys}
     return {"n_qubits": n, "observable": "Hadamard^(x)n", "runs": runs, "rows": rows,
-            "loglog_slopes": fit}
+            "loglog_slopes": loglog_slopes(rows, keys, 0),
+            "loglog_slopes_p_ge_160": loglog_slopes(rows, keys, 160)}
+
+
+def loglog_slopes(rows, keys, p_min):
+    """Slopes of log(value) against log(P) over the rows with P >= p_min (least squares)."""
+    import numpy as np
+    sel = [r for r in rows if r["P"] >= p_min]
+    lp = np.log([r["P"] for r in sel])
+    return {k: float(np.polyfit(lp, np.log([r[k] for r in sel]), 1)[0]) for k in keys}
 
 
 def paper_batch(qsv, torch, W, n, layers_list, B, runs):
@@ -468,11 +475,10 @@ def paper_batch(qsv, torch, W, n, layers_list, B, runs):
             f"ms ({row['adjoint_gradients_per_s']:.3g} gradients/s), Alg. 2 "
             f"{1e3 * row['reference_device_s']:.3f} ms, speedup {row['speedup_device']:.1f}, "
             f"|dg| {d:.1e}")
-    lp = np.log([r["P"] for r in rows])
     keys = ["adjoint_device_s", "reference_device_s", "speedup_device"]
-    fit = {k: float(np.polyfit(lp, np.log([r[k] for r in rows]), 1)[0]) for k in keys}
     return {"n_qubits": n, "observable": "Hadamard^(x)n", "circuits": B, "runs": runs,
-            "rows": rows, "loglog_slopes": fit}
+            "rows": rows, "loglog_slopes": loglog_slopes(rows, keys, 0),
+            "loglog_slopes_p_ge_160": loglog_slopes(rows, keys, 160)}
 
 
 def roofline_of(res, S, flops_bwd, flops_fwd, steps, workload, dtype):

@@ -486,6 +486,7 @@ struct qsv_state {
                          // 3 chunked one-circuit sweep
   int fr = 0, fw = 0;
   std::unordered_map<uint64_t, std::unique_ptr<Plan>> plans;
+  Plan* last_plan = nullptr;  // the plan of the last call: checked first, without hashing
   std::unordered_map<uint64_t, std::unique_ptr<PauliPlan>> paulis;
   DevBuf epartials, theta_scratch, energies;
   Timer timer;
@@ -555,6 +556,15 @@ static double backward_bytes(const GateDesc& g, double S, bool undo_lam) {
 
 static qsv_status get_plan(qsv_state* s, const qsv_gate* gates, int32_t n_gates, int32_t n_theta,
                            Plan** out) {
+  // repeated calls with one circuit (the common case, and a batch's per-handle lookups) compare
+  // the gate table with the last plan's copy instead of hashing it
+  if (Plan* lp = s->last_plan) {
+    if ((int32_t)lp->gates.size() == n_gates && lp->n_theta == n_theta &&
+        (n_gates == 0 || std::memcmp(lp->gates.data(), gates, sizeof(qsv_gate) * n_gates) == 0)) {
+      *out = lp;
+      return QSV_OK;
+    }
+  }
   uint64_t h = fnv1a(gates, sizeof(qsv_gate) * (size_t)n_gates);
   h = fnv1a(&n_theta, sizeof n_theta, h);
   h = fnv1a(&n_gates, sizeof n_gates, h);
@@ -563,13 +573,14 @@ static qsv_status get_plan(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
     Plan* p = it->second.get();
     if ((int32_t)p->gates.size() == n_gates && p->n_theta == n_theta &&
         (n_gates == 0 || std::memcmp(p->gates.data(), gates, sizeof(qsv_gate) * n_gates) == 0)) {
-      *out = p;
+      *out = s->last_plan = p;
       return QSV_OK;
     }
   }
   if (s->plans.size() >= kMaxCachedPlans) {
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->plans.clear();
+    s->last_plan = nullptr;
   }
   auto p = std::make_unique<Plan>();
   p->gates.assign(reinterpret_cast<const GateDesc*>(gates),
@@ -609,7 +620,7 @@ static qsv_status get_plan(qsv_state* s, const qsv_gate* gates, int32_t n_gates,
   if (!p->occ.empty())
     HIP_TRY(hipMemcpyAsync(p->d_occ.p, p->occ.data(), sizeof(int32_t) * p->occ.size(),
                            hipMemcpyHostToDevice, st));
-  *out = p.get();
+  *out = s->last_plan = p.get();
   s->plans[h] = std::move(p);
   return QSV_OK;
 }

@@ -44,7 +44,9 @@ enum FusedOpType : uint8_t {
 
 // A tile bit referenced by an op (control or diagonal bit) is either a register bit of the phase
 // (flag set, register position in ks0/ks1) or a thread bit (its value is constant per thread).
-enum : uint8_t { FOPF_S0_REG = 1, FOPF_S1_REG = 2, FOPF_MACRO = 4 };
+enum : uint8_t { FOPF_S0_REG = 1, FOPF_S1_REG = 2, FOPF_MACRO = 4, FOPF_FLIP = 8 };
+// FOPF_FLIP is set when a pass is staged (never by the scheduler): a rotation whose half angle
+// has a negative cosine runs as -1 times a rotation by the half angle minus pi (see OpStage).
 
 // Rotation macros (see form_rotation_macros): a head flagged FOPF_MACRO, op code
 // QSV_OPC(type, QSV_V_MACRO), stands for r rotations about one axis, one per register position
@@ -130,11 +132,16 @@ struct PassItem {
   int32_t pad;
 };
 
-// An op as staged in LDS at the start of a pass: the op record and, for RX/RY/RZ, cos(t/2) and
-// sin(t/2) of its angle.
+// An op as staged in LDS at the start of a pass: the op record and, for RX/RY/RZ, the shear
+// factors of its rotation. Each such gate is a plane rotation by phi = t/2 of pairs of real
+// components (RY: (re a0, re a1), (im a0, im a1); RX and RZ: real/imaginary pairs), applied in
+// place as three shears x += alpha y, y += beta x, x += alpha y with alpha = -tan(phi/2) and
+// beta = sin(phi). When cos(phi) < 0 the gate runs as -1 times the rotation by phi - pi
+// (FOPF_FLIP set), which keeps |alpha|, |beta| <= 1; the sign is carried per tile and applied
+// when the tile is stored (the products of the reverse sweep see it on phi and lambda alike).
 struct alignas(16) OpStage {
   FusedOp op;
-  double c, s;
+  double alpha, beta;
 };
 
 // A schedule of one gate sequence (forward order, or the reverse sweep) as host tables ready to

@@ -165,69 +165,75 @@ __device__ __forceinline__ bool same_layout(const Layout<RB>& a, const int8_t* r
 // ---------------------------------------------------------------------------------------------
 // Lean ops. ADJ selects U^dag (reverse sweep) instead of U.
 // ---------------------------------------------------------------------------------------------
-// x <- c x + t with the result in x's own register (a tied operand): left to itself the compiler
-// accumulates into the temporary holding t and copies the result back at the switch join.
-__device__ __forceinline__ void fma_inplace(double& x, double c, double t) {
-  asm("v_fma_f64 %0, %1, %0, %2" : "+v"(x) : "v"(c), "v"(t));
-}
-__device__ __forceinline__ void fma_inplace(float& x, float c, float t) {
-  asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x) : "v"(c), "v"(t));
-}
 
-template <typename R, int NA, int K, bool ADJ>
-__device__ __forceinline__ void ry_k(cx<R>* a, R c, R s) {
-  const R sp = ADJ ? -s : s;  // U = [[c, -s], [s, c]]
-#pragma unroll
-  for (int ri = 0; ri < NA; ++ri) {
-    if (ri & (1 << K)) continue;
-    const int rj = ri | (1 << K);
-    const R tr = -sp * a[rj].r, ti = -sp * a[rj].i, ur = sp * a[ri].r, ui = sp * a[ri].i;
-    fma_inplace(a[ri].r, c, tr);
-    fma_inplace(a[ri].i, c, ti);
-    fma_inplace(a[rj].r, c, ur);
-    fma_inplace(a[rj].i, c, ui);
-  }
+// x <- x + m t with the result in x's own register (a tied operand): left to itself the compiler
+// accumulates into a temporary and copies the result back at the switch join.
+__device__ __forceinline__ void fmac_inplace(double& x, double m, double t) {
+  asm("v_fma_f64 %0, %1, %2, %0" : "+v"(x) : "v"(m), "v"(t));
 }
-
-template <typename R, int NA, int K, bool ADJ>
-__device__ __forceinline__ void rx_k(cx<R>* a, R c, R s) {
-  const R sp = ADJ ? -s : s;  // U = [[c, -i s], [-i s, c]]
-#pragma unroll
-  for (int ri = 0; ri < NA; ++ri) {
-    if (ri & (1 << K)) continue;
-    const int rj = ri | (1 << K);
-    const R t0 = sp * a[rj].i, t1 = -sp * a[rj].r, t2 = sp * a[ri].i, t3 = -sp * a[ri].r;
-    fma_inplace(a[ri].r, c, t0);
-    fma_inplace(a[ri].i, c, t1);
-    fma_inplace(a[rj].r, c, t2);
-    fma_inplace(a[rj].i, c, t3);
-  }
+__device__ __forceinline__ void fmac_inplace(float& x, float m, float t) {
+  asm("v_fma_f32 %0, %1, %2, %0" : "+v"(x) : "v"(m), "v"(t));
 }
-
-// multiply by the phase c + i t
+// (x, y) <- the plane rotation [[cos phi, -sin phi], [sin phi, cos phi]] (x, y) as three shears
+// (alpha = -tan(phi/2), beta = sin phi), in place: three FMAs per pair of components.
 template <typename R>
-__device__ __forceinline__ void phase_mul_inplace(cx<R>& z, R c, R t) {
-  const R u0 = -t * z.i, u1 = t * z.r;
-  fma_inplace(z.r, c, u0);
-  fma_inplace(z.i, c, u1);
+__device__ __forceinline__ void shear3(R& x, R& y, R al, R be) {
+  fmac_inplace(x, al, y);
+  fmac_inplace(y, be, x);
+  fmac_inplace(x, al, y);
 }
 
-// RZ = diag(c - i s, c + i s): bit b multiplies by c + i (b ? s : -s) (negated for U^dag)
+// Rotations on register position K from the staged shear factors (al, be); ADJ rotates by -phi.
+// RY = [[c, -s], [s, c]] rotates (re a0, re a1) and (im a0, im a1).
 template <typename R, int NA, int K, bool ADJ>
-__device__ __forceinline__ void rz_k(cx<R>* a, R c, R s) {
+__device__ __forceinline__ void ry_k(cx<R>* a, R al, R be) {
+  if constexpr (ADJ) { al = -al; be = -be; }
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
-    const bool b = (ri >> K) & 1;
-    const R t = (b != ADJ) ? s : -s;
-    phase_mul_inplace(a[ri], c, t);
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    shear3(a[ri].r, a[rj].r, al, be);
+    shear3(a[ri].i, a[rj].i, al, be);
   }
 }
 
-template <typename R, int NA, bool ADJ>
-__device__ __forceinline__ void rz_thr(cx<R>* a, R c, R s, bool b) {
-  const R t = (b != ADJ) ? s : -s;
+// RX = [[c, -i s], [-i s, c]] rotates (im a1, re a0) and (im a0, re a1).
+template <typename R, int NA, int K, bool ADJ>
+__device__ __forceinline__ void rx_k(cx<R>* a, R al, R be) {
+  if constexpr (ADJ) { al = -al; be = -be; }
 #pragma unroll
-  for (int ri = 0; ri < NA; ++ri) phase_mul_inplace(a[ri], c, t);
+  for (int ri = 0; ri < NA; ++ri) {
+    if (ri & (1 << K)) continue;
+    const int rj = ri | (1 << K);
+    shear3(a[rj].i, a[ri].r, al, be);
+    shear3(a[ri].i, a[rj].r, al, be);
+  }
+}
+
+// RZ = diag(c - i s, c + i s): bit 0 rotates (im z, re z), bit 1 rotates (re z, im z).
+template <typename R, int NA, int K, bool ADJ>
+__device__ __forceinline__ void rz_k(cx<R>* a, R al, R be) {
+  if constexpr (ADJ) { al = -al; be = -be; }
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    if ((ri >> K) & 1) shear3(a[ri].r, a[ri].i, al, be);
+    else shear3(a[ri].i, a[ri].r, al, be);
+  }
+}
+
+// RZ on a thread bit b: every amplitude rotates (re z, im z) by phi (b = 1) or -phi (b = 0).
+template <typename R, int NA, bool ADJ>
+__device__ __forceinline__ void rz_thr(cx<R>* a, R al, R be, bool b) {
+  if (b == ADJ) { al = -al; be = -be; }
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) shear3(a[ri].r, a[ri].i, al, be);
+}
+
+// a <- -a (the sign carried by rotations staged with FOPF_FLIP)
+template <typename R, int NA>
+__device__ __forceinline__ void negate_all(cx<R>* a) {
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) a[ri] = cx<R>{-a[ri].r, -a[ri].i};
 }
 
 // Exchange two values in their registers (v_swap_b32). Written as an exchange of SSA values, a
@@ -451,52 +457,52 @@ __device__ __forceinline__ double prod_im_all(const cx<R>* f, const cx<R>* l) {
 // un-application, then U^dag on both states; otherwise U on f alone.
 // ---------------------------------------------------------------------------------------------
 template <typename R, int RB, bool BWD, int K>
-__device__ __forceinline__ double op_ry(R c, R s, cx<R>* f, cx<R>* l) {
+__device__ __forceinline__ double op_ry(R al, R be, cx<R>* f, cx<R>* l) {
   constexpr int NA = 1 << RB;
   double p = 0.0;
   if constexpr (K < RB) {
     if constexpr (BWD) p = prod_ry_k<R, NA, K>(f, l);
-    ry_k<R, NA, K, BWD>(f, c, s);
-    if constexpr (BWD) ry_k<R, NA, K, true>(l, c, s);
+    ry_k<R, NA, K, BWD>(f, al, be);
+    if constexpr (BWD) ry_k<R, NA, K, true>(l, al, be);
   }
   return p;
 }
 
 template <typename R, int RB, bool BWD, int K>
-__device__ __forceinline__ double op_rx(R c, R s, cx<R>* f, cx<R>* l) {
+__device__ __forceinline__ double op_rx(R al, R be, cx<R>* f, cx<R>* l) {
   constexpr int NA = 1 << RB;
   double p = 0.0;
   if constexpr (K < RB) {
     if constexpr (BWD) p = prod_rx_k<R, NA, K>(f, l);
-    rx_k<R, NA, K, BWD>(f, c, s);
-    if constexpr (BWD) rx_k<R, NA, K, true>(l, c, s);
+    rx_k<R, NA, K, BWD>(f, al, be);
+    if constexpr (BWD) rx_k<R, NA, K, true>(l, al, be);
   }
   return p;
 }
 
 template <typename R, int RB, bool BWD, int K>
-__device__ __forceinline__ double op_rz(R c, R s, cx<R>* f, cx<R>* l) {
+__device__ __forceinline__ double op_rz(R al, R be, cx<R>* f, cx<R>* l) {
   constexpr int NA = 1 << RB;
   double p = 0.0;
   if constexpr (K < RB) {
     if constexpr (BWD) p = prod_rz_k<R, NA, K>(f, l);
-    rz_k<R, NA, K, BWD>(f, c, s);
-    if constexpr (BWD) rz_k<R, NA, K, true>(l, c, s);
+    rz_k<R, NA, K, BWD>(f, al, be);
+    if constexpr (BWD) rz_k<R, NA, K, true>(l, al, be);
   }
   return p;
 }
 
 // RZ on a thread bit b: Z = (-1)^b on all of the thread's amplitudes
 template <typename R, int RB, bool BWD>
-__device__ __forceinline__ double op_rz_thr(R c, R s, cx<R>* f, cx<R>* l, bool b) {
+__device__ __forceinline__ double op_rz_thr(R al, R be, cx<R>* f, cx<R>* l, bool b) {
   constexpr int NA = 1 << RB;
   double p = 0.0;
   if constexpr (BWD) {
     const double v = 0.5 * prod_im_all<R, NA>(f, l);
     p = b ? -v : v;
   }
-  rz_thr<R, NA, BWD>(f, c, s, b);
-  if constexpr (BWD) rz_thr<R, NA, true>(l, c, s, b);
+  rz_thr<R, NA, BWD>(f, al, be, b);
+  if constexpr (BWD) rz_thr<R, NA, true>(l, al, be, b);
   return p;
 }
 
@@ -604,22 +610,26 @@ __device__ __forceinline__ double re_w_k(int type, const cx<R>* f, const cx<R>* 
 }
 
 // A rotation macro: RB rotations about one axis, one per register position, in straight-line
-// code. Position 0 is the head (cos/sin c0, s0); the cos/sin of positions 1 .. RB - 1 are staged
-// from record `mem` of the pass on. The product of position K goes to prod[K] (reverse sweep).
+// code. Position 0 is the head (shear factors al0, be0); the factors of positions 1 .. RB - 1
+// are staged from record `mem` of the pass on (with their FOPF_FLIP, toggled into flip). The
+// product of position K goes to prod[K] (reverse sweep).
 template <typename R, int RB, bool BWD, int AXIS, int K = 0>
-__device__ __forceinline__ void rot_macro_k(R c0, R s0, const OpStage* mem, cx<R>* f, cx<R>* l,
-                                            double* prod) {
+__device__ __forceinline__ void rot_macro_k(R al0, R be0, const OpStage* mem, cx<R>* f, cx<R>* l,
+                                            double* prod, int& flip) {
   if constexpr (K < RB) {
-    R c = c0, s = s0;
+    R al = al0, be = be0;
     if constexpr (K > 0) {
-      const double2 cs = *reinterpret_cast<const double2*>(&mem[K - 1].c);
-      c = (R)cs.x;
-      s = (R)cs.y;
+      const double2 ab = *reinterpret_cast<const double2*>(&mem[K - 1].alpha);
+      al = (R)ab.x;
+      be = (R)ab.y;
+      const uint32_t w1 = __builtin_amdgcn_readfirstlane(
+          reinterpret_cast<const uint32_t*>(&mem[K - 1].op)[1]);
+      flip ^= ((w1 >> 24) & FOPF_FLIP) ? 1 : 0;
     }
-    if constexpr (AXIS == FOP_RY) prod[K] = op_ry<R, RB, BWD, K>(c, s, f, l);
-    else if constexpr (AXIS == FOP_RX) prod[K] = op_rx<R, RB, BWD, K>(c, s, f, l);
-    else prod[K] = op_rz<R, RB, BWD, K>(c, s, f, l);
-    rot_macro_k<R, RB, BWD, AXIS, K + 1>(c0, s0, mem, f, l, prod);
+    if constexpr (AXIS == FOP_RY) prod[K] = op_ry<R, RB, BWD, K>(al, be, f, l);
+    else if constexpr (AXIS == FOP_RX) prod[K] = op_rx<R, RB, BWD, K>(al, be, f, l);
+    else prod[K] = op_rz<R, RB, BWD, K>(al, be, f, l);
+    rot_macro_k<R, RB, BWD, AXIS, K + 1>(al0, be0, mem, f, l, prod, flip);
   }
 }
 
@@ -644,12 +654,15 @@ __device__ __forceinline__ void rot_macro_k(R c0, R s0, const OpStage* mem, cx<R
   QSV_KK1(T, 2, FN, __VA_ARGS__) QSV_KK1(T, 3, FN, __VA_ARGS__)                     \
   QSV_KK1(T, 4, FN, __VA_ARGS__)
 
+// (c, s) are a rotation's staged shear factors; flip collects the sign of the rotations run as
+// -1 times a rotation (FOPF_FLIP).
 template <typename R, int RB, bool BWD>
 __device__ __forceinline__ void lean_step(const FusedOp& op, R c, R s, const GateRec* rec,
                                           const OpStage* sops, cx<R>* f, cx<R>* l, uint32_t tdep,
-                                          double* prod) {
+                                          double* prod, int& flip) {
   static_assert(RB <= 5, "op codes hold register positions below 5");
   double& p = prod[0];
+  if (op.type <= FOP_RZ && (op.flags & FOPF_FLIP)) flip ^= 1;
   switch (op.opc) {
     QSV_K5(FOP_RY, 0, op_ry, c, s, f, l)
     QSV_K5(FOP_RX, 0, op_rx, c, s, f, l)
@@ -672,15 +685,15 @@ __device__ __forceinline__ void lean_step(const FusedOp& op, R c, R s, const Gat
       break;
     case QSV_OPC(FOP_RY, QSV_V_MACRO):
       if constexpr (RB <= kMaxMacroRegBits)
-        rot_macro_k<R, RB, BWD, FOP_RY>(c, s, sops + op.k1, f, l, prod);
+        rot_macro_k<R, RB, BWD, FOP_RY>(c, s, sops + op.k1, f, l, prod, flip);
       break;
     case QSV_OPC(FOP_RX, QSV_V_MACRO):
       if constexpr (RB <= kMaxMacroRegBits)
-        rot_macro_k<R, RB, BWD, FOP_RX>(c, s, sops + op.k1, f, l, prod);
+        rot_macro_k<R, RB, BWD, FOP_RX>(c, s, sops + op.k1, f, l, prod, flip);
       break;
     case QSV_OPC(FOP_RZ, QSV_V_MACRO):
       if constexpr (RB <= kMaxMacroRegBits)
-        rot_macro_k<R, RB, BWD, FOP_RZ>(c, s, sops + op.k1, f, l, prod);
+        rot_macro_k<R, RB, BWD, FOP_RZ>(c, s, sops + op.k1, f, l, prod, flip);
       break;
     default:
       break;
@@ -1081,14 +1094,25 @@ __device__ __forceinline__ void stage_pass(const PassItem& I, OpStage* sops, Pha
     const U4 w = ((const QSV_GLOBAL U4*)(I.ops + I.pd.op_begin))[i];
     const uint4 raw = make_uint4(w.x, w.y, w.z, w.w);
     const int type = (int)(raw.x & 0xffu);
-    double c = 0.0, s = 0.0;
+    double al = 0.0, be = 0.0;
+    uint4 staged = raw;
     if (type <= FOP_RZ) {  // RY m[2] = s, RX m[1] = -i s, RZ m[0] = c - i s
       const QSV_GLOBAL double* m = rec_words(I.recs + (int32_t)raw.w);
-      c = m[0];
-      s = type == FOP_RY ? m[4] : type == FOP_RX ? -m[3] : -m[1];
+      const double c = m[0];
+      const double s = type == FOP_RY ? m[4] : type == FOP_RX ? -m[3] : -m[1];
+      // shear factors of the rotation by phi (cos phi = c >= 0), or of -1 times the rotation by
+      // phi - pi (cos = -c, sin = -s): alpha = -tan(phi/2) = -s / (1 + c), beta = sin(phi)
+      if (c >= 0.0) {
+        al = -s / (1.0 + c);
+        be = s;
+      } else {
+        al = s / (1.0 - c);
+        be = -s;
+        staged.y |= (uint32_t)FOPF_FLIP << 24;
+      }
     }
-    *reinterpret_cast<uint4*>(&sops[i].op) = raw;
-    *reinterpret_cast<double2*>(&sops[i].c) = make_double2(c, s);
+    *reinterpret_cast<uint4*>(&sops[i].op) = staged;
+    *reinterpret_cast<double2*>(&sops[i].alpha) = make_double2(al, be);
   }
   static_assert(sizeof(PhaseDesc) == 12, "PhaseDesc moves as three words");
   const QSV_GLOBAL uint32_t* ph = (const QSV_GLOBAL uint32_t*)(I.phases + I.pd.phase_begin);
@@ -1105,7 +1129,7 @@ __device__ __forceinline__ uint4 staged_words(const OpStage* sops, int k) {
   return *reinterpret_cast<const uint4*>(&sops[k].op);
 }
 __device__ __forceinline__ double2 staged_cs(const OpStage* sops, int k) {
-  return *reinterpret_cast<const double2*>(&sops[k].c);
+  return *reinterpret_cast<const double2*>(&sops[k].alpha);
 }
 __device__ __forceinline__ FusedOp uniform_op(uint4 raw) {
   const uint32_t w0 = __builtin_amdgcn_readfirstlane(raw.x);
@@ -1277,6 +1301,7 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
       }
       Layout<RB> cur = LL;
       int k = 0;
+      int flip = 0;
       uint4 nraw = staged_words(sops, 0);
       double2 ncs = staged_cs(sops, 0);
       for (int ph = 0; ph < n_ph; ++ph) {
@@ -1304,10 +1329,12 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
             apply_general<R, RB, false>(op, rec, a, cur);
           } else {
             double unused[kMaxMacroRegBits];
-            lean_step<R, RB, false>(op, (R)cs.x, (R)cs.y, rec, sops, a, nullptr, cur.tdep, unused);
+            lean_step<R, RB, false>(op, (R)cs.x, (R)cs.y, rec, sops, a, nullptr, cur.tdep, unused,
+                                    flip);
           }
         }
       }
+      if (flip) negate_all<R, G::NA>(a);
       if (!same_layout<RB>(cur, LS.rb)) relayout<R, RB>(a, cur, LS, lds);
       if (lamv) {
 #pragma unroll
@@ -1420,6 +1447,8 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
       }
       Layout<RB> cur = LL;
       int k = 0;
+      // phi and lambda carry the same sign from flipped rotations, so products are unaffected
+      int flip = 0;
       uint4 nraw = staged_words(sops, 0);
       double2 ncs = staged_cs(sops, 0);
       for (int ph = 0; ph < n_ph; ++ph) {
@@ -1468,7 +1497,8 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
               apply_general<R, RB, true>(op, rec, l, cur);
             } else {
               if (cx_entries && op.np) prod_im[0] = lean_product_im<R, RB>(op, f, l, cur.tdep);
-              lean_step<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, sops, f, l, cur.tdep, prod);
+              lean_step<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, sops, f, l, cur.tdep, prod,
+                                     flip);
             }
             if (!cx_entries) {
 #pragma unroll
@@ -1495,6 +1525,10 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
       }
       // the tile's last, partial batch
       if (!cx_entries && (I.pd.n_slots & 3)) batch_flush(pb, (I.pd.n_slots - 1) >> 2, lane, acc0, acc1);
+      if (flip) {
+        negate_all<R, G::NA>(f);
+        negate_all<R, G::NA>(l);
+      }
       if (!same_layout<RB>(cur, LS.rb)) {
         if constexpr (SPLIT) {
           relayout<R, RB>(f, cur, LS, lds);

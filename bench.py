@@ -114,7 +114,13 @@ class Batched:
         self.units = len(probs)
 
     def autotune(self, geometry=None):
-        return None
+        if geometry:
+            for h in self.batch.handles:
+                h.set_fusion(1, *geometry)
+            return (1, geometry[0], geometry[1], -1.0)
+        t = self.batch.autotune()
+        log(f"batch autotune: mode {t[0]} r={t[1]} w={t[2]}: {t[3]:.3f} ms")
+        return t
 
     def step(self):
         self.batch.adjoint_gradient(self.theta, self.e, self.g)

@@ -510,6 +510,43 @@ class Batch:
     def sync(self):
         self.handles[0].sync()
 
+    # tile geometries (reg_qubits, threads_log2) of the fused kernels, as qsv_set_fusion accepts
+    GEOMETRIES = {"c128": [(2, 8), (3, 8), (4, 8), (2, 9), (3, 9), (2, 6), (3, 6)],
+                  "c64": [(2, 8), (3, 8), (4, 8), (2, 9), (3, 9), (4, 9), (2, 6), (3, 6)]}
+
+    def autotune(self, repeats: int = 3):
+        """Time the batched gradient in every tile geometry that fits every circuit (and the
+        one-wave or automatic mode) and keep the fastest for all handles; returns
+        (mode, reg_qubits, threads_log2, ms per batch). The batch runs one common geometry (its
+        passes of all circuits launch together)."""
+        torch = _torch()
+        th = self.theta_flat()
+        e = torch.empty(len(self.handles), dtype=torch.float64, device=self.device)
+        g = torch.empty(max(self.n_params, 1), dtype=torch.float64, device=self.device)
+        n_min = min(h.n for h in self.handles)
+        dt = self.handles[0].dtype
+        cands = [(-1, 0, 0)] + [(1, r, w) for r, w in self.GEOMETRIES[dt] if r + w <= n_min]
+        best = None
+        stream = self.handles[0].stream  # the batched call runs on the first handle's stream
+        for c in cands:
+            for h in self.handles:
+                h.set_fusion(*c)
+            self.adjoint_gradient(th, e, g)   # builds the schedules
+            torch.cuda.synchronize(self.device)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(repeats):
+                self.adjoint_gradient(th, e, g)
+            b.record(stream)
+            b.synchronize()
+            ms = a.elapsed_time(b) / repeats
+            if best is None or ms < best[3]:
+                best = (*c, ms)
+        for h in self.handles:
+            h.set_fusion(*best[:3])
+        return best
+
     def set_graphs(self, on: bool = True):
         self.handles[0].set_graphs(on)
 

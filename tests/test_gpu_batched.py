@@ -263,3 +263,23 @@ def test_wave_batch_reference(Q, orc, dtype):
                 scale = max(np.max(np.abs(g_ref), initial=0), 1e-5 * np.abs(p.coeffs).sum())
                 assert p.n_params == 0 or np.max(np.abs(gb - g_ref)) <= 2e-4 * scale, b
         batch.close()
+
+
+def test_batch_autotune(Q, orc):
+    """The batch geometry autotuner times every geometry that fits every circuit, keeps the
+    fastest on all handles, and the gradients in that geometry still match the oracle."""
+    probs = small_batch(6, B=4)
+    batch = Q.Batch(probs)
+    mode, r, w, ms = batch.autotune(repeats=1)
+    assert ms > 0 and mode in (-1, 1)
+    if mode == 1:
+        assert (r, w) in Q.Batch.GEOMETRIES["c128"] and r + w <= min(p.n_qubits for p in probs)
+        assert all(h.get_fusion() == (1, r, w) for h in batch.handles)
+    e, g = batch.adjoint_gradient(batch.theta_flat())
+    batch.sync()
+    e, g = e.cpu().numpy(), g.cpu().numpy()
+    for b, p in enumerate(probs):
+        e_ref, g_ref = orc.adjoint_gradient(p.n_qubits, p.gates, p.theta, p.codes, p.coeffs)
+        assert abs(e[b] - e_ref.real) <= 1e-10
+        assert np.max(np.abs(g[batch.theta_off[b]: batch.theta_off[b] + p.n_params] - g_ref)) <= 1e-10
+    batch.close()

@@ -154,3 +154,18 @@ def test_debug_fail_launch_rejects_negative():
     with pytest.raises(qsv.QsvError):
         qsv.debug_fail_launch(-1)
     qsv.debug_fail_launch(0)
+
+
+@pytest.mark.parametrize("name", ["qsv_adjoint_gradient_batched", "qsv_reference_gradient_batched"])
+def test_batched_entry_points_reject_bad_batches(name):
+    """Both batched entry points check the batch size and their host arrays before touching any
+    handle or device memory."""
+    fn = getattr(qsv.lib(), name)
+    z = ctypes.c_void_p(0)
+    one = (ctypes.c_int32 * 1)(1)
+    off = (ctypes.c_int64 * 1)(0)
+    for n_batch in (0, -3):
+        assert fn(n_batch, z, z, z, z, z, z, z, z, z) == qsv.QSV_ERR_INVALID_ARG
+    # NULL states / gates / counts
+    assert fn(1, z, z, one, z, off, one, z, z, z) == qsv.QSV_ERR_INVALID_ARG
+    assert "NULL" in qsv.lib().qsv_last_error().decode()

@@ -360,7 +360,7 @@ qsv_status qsv_timing_read(qsv_state* s, qsv_kernel_stat* out, int32_t max_out, 
                 and W_c^dag on one wave, and the steps of Algorithm 1 inside the chunks run for
                 all chunks at once. Circuits with a non-unitary gate run mode 2;
      mode = -1  automatic (the default): for the gradient of states of at most 6 qubits mode 3
-                from 192 gates on (at most 5 qubits, unitary gates), else mode 2; otherwise fused
+                from 96 gates on (at most 5 qubits, unitary gates), else mode 2; otherwise fused
                 with a size-dependent geometry. qsv_autotune picks among all modes by
                 measurement. */
 qsv_status qsv_set_fusion(qsv_state* s, int32_t mode, int32_t reg_qubits, int32_t threads_log2);

@@ -1128,7 +1128,7 @@ static bool wave_path(const qsv_state* s) {
 
 // Circuits long enough for the chunked sweep to pay for forming the chunk operators (about
 // 2^n gate applications per gate): the automatic mode takes it from this many gates on.
-static constexpr int kWaveChunkMinGates = 192;
+static constexpr int kWaveChunkMinGates = 96;
 
 // The chunked variant (launch_wave_chunked) of a one-wave gradient: mode 3, or the automatic
 // mode for long circuits; every gate unitary (phi is carried back by W_c^dag).

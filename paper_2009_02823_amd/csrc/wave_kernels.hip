@@ -452,7 +452,7 @@ __device__ __forceinline__ C apply_h(const WaveJob& J, C psi, int lane, double* 
   __syncthreads();
   scratch[lane] = lane < nl ? psi.r * lam.r + psi.i * lam.i : 0.0;
   __syncthreads();
-  if (lane == 0) {
+  if (lane == 0 && energy) {
     double e = 0;
     for (int l = 0; l < nl; ++l) e += scratch[l];
     energy[0] = e;
@@ -462,12 +462,29 @@ __device__ __forceinline__ C apply_h(const WaveJob& J, C psi, int lane, double* 
 }
 
 // gradient entries: 2 Re of the sum of a parameter's slots, in sweep order (slot sums written by
-// other lanes or waves: the caller makes them visible first)
+// other lanes or waves: the caller makes them visible first). Eight parameters per lane at a
+// time, so that their dependent loads (slot range, first slot, its sum) are in flight together.
 __device__ __forceinline__ void gradient_entries(const WaveJob& J, int lane) {
-  for (int p = lane; p < J.n_theta; p += 64) {
-    double t = 0;
-    for (int o = J.param_ptr[p]; o < J.param_ptr[p + 1]; ++o) t += J.slot_sum[J.occ[o]];
-    J.grad[p] = 2.0 * t;
+  constexpr int U = 8;
+  for (int p0 = lane; p0 < J.n_theta; p0 += 64 * U) {
+    int b[U], e[U], o[U];
+    double t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + 64 * u;
+      b[u] = p < J.n_theta ? J.param_ptr[p] : 0;
+      e[u] = p < J.n_theta ? J.param_ptr[p + 1] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) o[u] = b[u] < e[u] ? J.occ[b[u]] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = o[u] >= 0 ? J.slot_sum[o[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      for (int k = b[u] + 1; k < e[u]; ++k) t[u] += J.slot_sum[J.occ[k]];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (p0 + 64 * u < J.n_theta) J.grad[p0 + 64 * u] = 2.0 * t[u];
   }
 }
 
@@ -537,9 +554,9 @@ __global__ void __launch_bounds__(64) k_wave_adjoint(const WaveJob* __restrict__
 //     states, 64 / 2^n of them per wave (lane = row + 2^n * column within the wave). W_c is stored
 //     twice: A_c[j * N + r] = W_c[r][j] and B_c[j * N + r] = W_c[j][r], so that the products W v
 //     (from A) and W^dag v (from B, conjugated) read each j's entries with consecutive lanes.
-//  2. k_wave_chunk_chain (one wave): psi = W_C-1 ... W_0 |in>, lambda = H psi, E; then for
+//  2. k_wave_chunk_chain (two waves): psi = W_C-1 ... W_0 |in>, lambda = H psi, E; then for
 //     c = C-1 .. 0 it records (phi, lambda) at the end of chunk c and un-applies the chunk,
-//     phi <- W_c^dag phi, lambda <- W_c^dag lambda (every gate unitary).
+//     phi <- W_c^dag phi (wave 0), lambda <- W_c^dag lambda (wave 1) (every gate unitary).
 //  3. k_wave_chunk_sweep: chunk c's steps of the reverse sweep from its recorded (phi, lambda),
 //     for all chunks at once; its product slots start after those of the later chunks. The last
 //     wave to finish forms the gradient entries.
@@ -620,11 +637,14 @@ __device__ __forceinline__ C mv_apply(const double2 m[Mv<NQ>::JN], bool adj, C v
   return acc;
 }
 
+// Two waves: both carry psi forward (the same steps, each in its own registers), then wave 0
+// carries phi and wave 1 lambda back, each recording its state at the chunk boundaries.
 template <typename R, int NQ>
-__global__ void __launch_bounds__(64) k_wave_chunk_chain(WaveJob J, WaveChunks K) {
+__global__ void __launch_bounds__(128) k_wave_chunk_chain(WaveJob J, WaveChunks K) {
   constexpr int N = 1 << NQ, JN = Mv<NQ>::JN;
-  __shared__ double2 vb[64];
-  const int lane = threadIdx.x;
+  __shared__ double2 vbuf[2][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double2* vb = vbuf[wave];
   const int C_ = K.n_chunks;
   const size_t NN = (size_t)N * N;
   C psi = load_in<R>(J, lane);
@@ -637,18 +657,15 @@ __global__ void __launch_bounds__(64) k_wave_chunk_chain(WaveJob J, WaveChunks K
     for (int t = 0; t < JN; ++t) mc[t] = mn[t];
   }
   if (lane >= N) psi = C{0, 0};
-  C lam = apply_h(J, psi, lane, reinterpret_cast<double*>(vb), J.energy);
-  C phi = psi;
+  C lam = apply_h(J, psi, lane, reinterpret_cast<double*>(vb), wave == 0 ? J.energy : nullptr);
+  C v = wave == 0 ? psi : lam;  // phi (wave 0) or lambda (wave 1)
+  double2* rec = wave == 0 ? K.phi : K.lam;
   mv_load<NQ>(K.B + (C_ - 1) * NN, lane, mc);
   for (int c = C_ - 1; c >= 0; --c) {
-    if (lane < N) {
-      K.phi[(size_t)c * N + lane] = make_double2(phi.r, phi.i);
-      K.lam[(size_t)c * N + lane] = make_double2(lam.r, lam.i);
-    }
+    if (lane < N) rec[(size_t)c * N + lane] = make_double2(v.r, v.i);
     if (c == 0) break;
     mv_load<NQ>(K.B + (c - 1) * NN, lane, mn);
-    phi = mv_apply<NQ>(mc, true, phi, lane, vb);
-    lam = mv_apply<NQ>(mc, true, lam, lane, vb);
+    v = mv_apply<NQ>(mc, true, v, lane, vb);
 #pragma unroll
     for (int t = 0; t < JN; ++t) mc[t] = mn[t];
   }
@@ -829,11 +846,11 @@ hipError_t launch_wave_chunked(const WaveJob& J, const WaveChunks& K, hipStream_
   const int waves = ((1 << n) + per_wave - 1) / per_wave;
   hipLaunchKernelGGL((k_wave_chunk_ops<R>), dim3(waves, K.n_chunks), dim3(64), 0, st, J, K);
   switch (n) {
-    case 1: hipLaunchKernelGGL((k_wave_chunk_chain<R, 1>), dim3(1), dim3(64), 0, st, J, K); break;
-    case 2: hipLaunchKernelGGL((k_wave_chunk_chain<R, 2>), dim3(1), dim3(64), 0, st, J, K); break;
-    case 3: hipLaunchKernelGGL((k_wave_chunk_chain<R, 3>), dim3(1), dim3(64), 0, st, J, K); break;
-    case 4: hipLaunchKernelGGL((k_wave_chunk_chain<R, 4>), dim3(1), dim3(64), 0, st, J, K); break;
-    default: hipLaunchKernelGGL((k_wave_chunk_chain<R, 5>), dim3(1), dim3(64), 0, st, J, K); break;
+    case 1: hipLaunchKernelGGL((k_wave_chunk_chain<R, 1>), dim3(1), dim3(128), 0, st, J, K); break;
+    case 2: hipLaunchKernelGGL((k_wave_chunk_chain<R, 2>), dim3(1), dim3(128), 0, st, J, K); break;
+    case 3: hipLaunchKernelGGL((k_wave_chunk_chain<R, 3>), dim3(1), dim3(128), 0, st, J, K); break;
+    case 4: hipLaunchKernelGGL((k_wave_chunk_chain<R, 4>), dim3(1), dim3(128), 0, st, J, K); break;
+    default: hipLaunchKernelGGL((k_wave_chunk_chain<R, 5>), dim3(1), dim3(128), 0, st, J, K); break;
   }
   hipLaunchKernelGGL((k_wave_chunk_sweep<R>), dim3(K.n_chunks), dim3(64), 0, st, J, K);
   return hipGetLastError();

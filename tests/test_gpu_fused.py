@@ -225,7 +225,7 @@ def test_chunked_sweep(Q, orc, dtype, n):
                         assert np.max(np.abs(g - g_ref)) <= 2e-4 * max(
                             np.max(np.abs(g_ref)), 1e-5 * np.abs(coeffs).sum())
                     results.append((e, g))
-        if G >= 192:  # the automatic mode ran the chunked kernels too
+        if G >= 96:  # the automatic mode ran the chunked kernels too
             assert results[-1][0] == results[0][0] and np.array_equal(results[-1][1], results[0][1])
 
 

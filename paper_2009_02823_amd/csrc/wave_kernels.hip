@@ -12,15 +12,17 @@
 // A state this small leaves the sweep bound by the latency of its dependent steps, so the design
 // keeps every step short:
 //  - gate data is read 64 gates ahead, one gate per lane (kind and qubits packed in one word,
-//    cos and sin of a rotation's half angle), and broadcast with v_readlane when the gate runs;
+//    cos and sin of a rotation's half angle formed from theta), and broadcast with v_readlane
+//    when the gate runs;
 //  - rotations about X, Y, Z, CNOT and CZ have their own paths; the partner amplitude across a
 //    qubit comes from a DPP lane permutation or a permlane swap (no LDS round trip), one code path
-//    per qubit; other gates read their matrices from the gate records and exchange amplitudes
-//    with ds_bpermute;
-//  - the products of 32 consecutive slots are staged in LDS, one row per slot, and each row is
-//    then summed by one lane in lane order, so no product goes to memory per lane;
+//    per qubit; other gates read their matrices from the gate records (scalar loads) and exchange
+//    amplitudes with ds_bpermute;
+//  - the products of kRows consecutive slots are staged in LDS, one row per slot, and each row
+//    is then summed by one lane in lane order, so no product goes to memory per lane;
 //  - the gradient entries (sums of a parameter's slots in sweep order) and the energy (lane parts
 //    in lane order) are formed by the same wave at the end: one launch per gradient.
+// The same steps serve the chunked sweep of one long circuit and Algorithm 2 (further below).
 #include "qsv_device.h"
 #include "sv_kernels.h"
 

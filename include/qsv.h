@@ -394,6 +394,8 @@ typedef struct {
   int32_t n_macros;
   int32_t n_direct_loads;   /* passes that load their tiles in the first phase's layout        */
   int32_t n_direct_stores;  /* passes that store their tiles from the last phase's layout      */
+  int32_t n_diag_blocks;    /* diagonal blocks (RZ and CZ gates on register bits run as one
+                               diagonal matrix per thread; formed for reg_qubits <= 4)         */
 } qsv_schedule_info;
 
 qsv_status qsv_schedule_describe(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates,

@@ -44,7 +44,7 @@ enum FusedOpType : uint8_t {
 
 // A tile bit referenced by an op (control or diagonal bit) is either a register bit of the phase
 // (flag set, register position in ks0/ks1) or a thread bit (its value is constant per thread).
-enum : uint8_t { FOPF_S0_REG = 1, FOPF_S1_REG = 2, FOPF_MACRO = 4, FOPF_FLIP = 8 };
+enum : uint8_t { FOPF_S0_REG = 1, FOPF_S1_REG = 2, FOPF_MACRO = 4, FOPF_FLIP = 8, FOPF_DIAG = 16 };
 // FOPF_FLIP is set when a pass is staged (never by the scheduler): a rotation whose half angle
 // has a negative cosine runs as -1 times a rotation by the half angle minus pi (see OpStage).
 
@@ -54,6 +54,18 @@ enum : uint8_t { FOPF_S0_REG = 1, FOPF_S1_REG = 2, FOPF_MACRO = 4, FOPF_FLIP = 8
 // pass, from op index k1 of the pass on. The head's np counts the products of all r
 // (consecutive local slots). Only for r <= kMaxMacroRegBits.
 constexpr int kMaxMacroRegBits = 4;
+
+// Diagonal blocks: consecutive diagonal gates of a phase whose bits are all register bits (RZ,
+// and CZ with both bits in registers) commute and act as one diagonal matrix d on the thread's
+// 2^r amplitudes. A head (type FOP_RZ, flag FOPF_DIAG, op code QSV_OPC(FOP_RZ, QSV_V_DIAG))
+// stands for them: its s0 member records (the gates, in run order) sit after the executed ops
+// of the pass from op index k1 on; np counts the RZ members (their products, consecutive local
+// slots from lslot) and gate holds their register positions, four bits each. When the pass is
+// staged, d is computed from the members into table ks1 of the pass (2^r complex entries).
+// Products of the reverse sweep are taken once for the block: Z of a member and the other
+// members commute, so Im <lambda|Z_k|phi> is the same at every point of the block.
+// Only for r <= kMaxMacroRegBits; at most kMaxDiagBlocks blocks per pass.
+constexpr int kMaxDiagBlocks = 24;
 
 struct FusedOp {
   uint8_t type;
@@ -78,6 +90,7 @@ struct FusedOp {
 #define QSV_V_CTL_THREAD 48
 #define QSV_V_THREAD 63
 #define QSV_V_MACRO 32  // RX/RY/RZ: a rotation macro head
+#define QSV_V_DIAG 36   // RZ: a diagonal block head
 
 // Tiles of a pass are loaded in the first phase's layout (stored from the last phase's) instead
 // of the direct layout when that phase keeps the contiguous runs on the low lane bits (none of
@@ -97,7 +110,7 @@ struct PassDesc {
   int32_t n_outer;                // N - t
   int8_t tile[kMaxTileBits];      // physical qubit of tile bit s (ascending)
   uint8_t io_flags;               // PASS_LOAD_FIRST_PHASE | PASS_STORE_LAST_PHASE
-  int8_t pad0;
+  int8_t n_diag;                  // diagonal blocks (their tables are staged with the pass)
   int8_t outer[40];               // physical qubits outside the tile (ascending)
   int32_t phase_begin, phase_end; // into the phase table
   int32_t op_begin;               // into the op table (phase op_end values are relative)

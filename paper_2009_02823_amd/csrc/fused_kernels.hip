@@ -633,6 +633,58 @@ __device__ __forceinline__ void rot_macro_k(R al0, R be0, const OpStage* mem, cx
   }
 }
 
+// Sums S[k] = sum over ri of (-1)^(bit k of ri) w[ri] for every register position k, by halving
+// butterflies: at level k the partial sums over the lower bits pair up by bit k.
+template <int NA, int K = 0>
+__device__ __forceinline__ void walsh_singles(const double* w, double* S) {
+  if constexpr (NA >= 2) {
+    double a[NA / 2], d[NA / 2];
+#pragma unroll
+    for (int j = 0; j < NA / 2; ++j) {
+      a[j] = w[2 * j] + w[2 * j + 1];
+      d[j] = w[2 * j] - w[2 * j + 1];
+    }
+    S[K] = tree_sum<NA / 2>(d);
+    walsh_singles<NA / 2, K + 1>(a, S);
+  }
+}
+
+// A diagonal block (FOPF_DIAG head): amplitude ri times entry d[ri] of the block's staged table
+// (the product of its RZ and CZ gates); the reverse sweep multiplies phi and lambda by the
+// conjugate. The product of RZ member j, on register position p_j (four bits each in op.gate),
+// is (1/2) sum over ri of (-1)^(bit p_j of ri) Im(conj(lambda) phi) (see prod_rz_k).
+template <typename R, int RB, bool BWD>
+__device__ __forceinline__ void diag_block(const FusedOp& op, const typename Vec2<R>::T* d,
+                                           cx<R>* f, cx<R>* l, double* prod) {
+  constexpr int NA = 1 << RB;
+  if constexpr (BWD) {
+    double w[NA], S[RB];
+#pragma unroll
+    for (int ri = 0; ri < NA; ++ri) w[ri] = im_cm(l[ri].r, l[ri].i, f[ri].r, f[ri].i);
+    walsh_singles<NA>(w, S);
+#pragma unroll
+    for (int j = 0; j < kMaxMacroRegBits; ++j) {
+      if (j >= op.np) break;
+      const int pj = (op.gate >> (4 * j)) & 15;
+      double v = S[0];
+#pragma unroll
+      for (int k = 1; k < RB; ++k) v = pj == k ? S[k] : v;
+      prod[j] = 0.5 * v;
+    }
+  }
+#pragma unroll
+  for (int ri = 0; ri < NA; ++ri) {
+    const typename Vec2<R>::T e = d[ri];
+    const R er = e.x, ei = BWD ? -e.y : e.y;
+    const cx<R> a = f[ri];
+    f[ri] = cx<R>{a.r * er - a.i * ei, a.r * ei + a.i * er};
+    if constexpr (BWD) {
+      const cx<R> b = l[ri];
+      l[ri] = cx<R>{b.r * er - b.i * ei, b.r * ei + b.i * er};
+    }
+  }
+}
+
 // One lean op, dispatched on its op code by a single switch whose cases are all fully
 // specialised: no nested per-position branches whose joins would copy the amplitude registers.
 // The op's products (reverse sweep) go to prod[0], or prod[0 .. RB) for a rotation macro, whose
@@ -658,8 +710,9 @@ __device__ __forceinline__ void rot_macro_k(R al0, R be0, const OpStage* mem, cx
 // -1 times a rotation (FOPF_FLIP).
 template <typename R, int RB, bool BWD>
 __device__ __forceinline__ void lean_step(const FusedOp& op, R c, R s, const GateRec* rec,
-                                          const OpStage* sops, cx<R>* f, cx<R>* l, uint32_t tdep,
-                                          double* prod, int& flip) {
+                                          const OpStage* sops, const typename Vec2<R>::T* sdiag,
+                                          cx<R>* f, cx<R>* l, uint32_t tdep, double* prod,
+                                          int& flip) {
   static_assert(RB <= 5, "op codes hold register positions below 5");
   double& p = prod[0];
   if (op.type <= FOP_RZ && (op.flags & FOPF_FLIP)) flip ^= 1;
@@ -694,6 +747,10 @@ __device__ __forceinline__ void lean_step(const FusedOp& op, R c, R s, const Gat
     case QSV_OPC(FOP_RZ, QSV_V_MACRO):
       if constexpr (RB <= kMaxMacroRegBits)
         rot_macro_k<R, RB, BWD, FOP_RZ>(c, s, sops + op.k1, f, l, prod, flip);
+      break;
+    case QSV_OPC(FOP_RZ, QSV_V_DIAG):
+      if constexpr (RB <= kMaxMacroRegBits)
+        diag_block<R, RB, BWD>(op, sdiag + op.ks1 * (1 << RB), f, l, prod);
       break;
     default:
       break;
@@ -1082,10 +1139,33 @@ __device__ __forceinline__ uint64_t next_in_mask(uint64_t b, uint64_t mask) {
   return (b - mask) & mask;
 }
 
+// An RZ member of a diagonal block, run on its own (complex-entry sweeps): its staged (c, s)
+// become the shear factors and FOPF_FLIP as the staging gives them to other rotations.
+__device__ __forceinline__ void diag_member_shears(FusedOp& op, double2& cs) {
+  if (op.type != FOP_RZ || !(op.flags & FOPF_DIAG)) return;
+  const double c = cs.x, s = cs.y;
+  if (c >= 0.0) {
+    cs = make_double2(-s / (1.0 + c), s);
+    op.flags &= (uint8_t)~FOPF_FLIP;
+  } else {
+    cs = make_double2(s / (1.0 - c), -s);
+    op.flags |= FOPF_FLIP;
+  }
+}
+
+// Raw words of staged op k (issued early; made uniform when the op is executed).
+__device__ __forceinline__ uint4 staged_words(const OpStage* sops, int k) {
+  return *reinterpret_cast<const uint4*>(&sops[k].op);
+}
+__device__ __forceinline__ double2 staged_cs(const OpStage* sops, int k) {
+  return *reinterpret_cast<const double2*>(&sops[k].alpha);
+}
+
 // Copies the pass's op records (with the cos/sin of the rotation angles) and phase descriptors to
 // LDS; every thread loads a share, so the whole op stream arrives in one round of loads.
+template <int RB, typename V>
 __device__ __forceinline__ void stage_pass(const PassItem& I, OpStage* sops, PhaseDesc* sph,
-                                           int tid, int nt) {
+                                           V* sdiag, int tid, int nt) {
   const int n_ops = I.pd.n_ops, n_ph = I.pd.phase_end - I.pd.phase_begin;
   for (int i = tid; i < n_ops; i += nt) {
     // the 16-byte op record moves as one word quadruple (type in the low byte of the first)
@@ -1096,13 +1176,18 @@ __device__ __forceinline__ void stage_pass(const PassItem& I, OpStage* sops, Pha
     const int type = (int)(raw.x & 0xffu);
     double al = 0.0, be = 0.0;
     uint4 staged = raw;
-    if (type <= FOP_RZ) {  // RY m[2] = s, RX m[1] = -i s, RZ m[0] = c - i s
+    if (type <= FOP_RZ && (raw.z >> 16) != QSV_OPC(FOP_RZ, QSV_V_DIAG)) {
+      // RY m[2] = s, RX m[1] = -i s, RZ m[0] = c - i s
       const QSV_GLOBAL double* m = rec_words(I.recs + (int32_t)raw.w);
       const double c = m[0];
       const double s = type == FOP_RY ? m[4] : type == FOP_RX ? -m[3] : -m[1];
       // shear factors of the rotation by phi (cos phi = c >= 0), or of -1 times the rotation by
-      // phi - pi (cos = -c, sin = -s): alpha = -tan(phi/2) = -s / (1 + c), beta = sin(phi)
-      if (c >= 0.0) {
+      // phi - pi (cos = -c, sin = -s): alpha = -tan(phi/2) = -s / (1 + c), beta = sin(phi).
+      // An RZ member of a diagonal block keeps (c, s) (see diag_member_shears).
+      if ((raw.y >> 24) & FOPF_DIAG) {
+        al = c;
+        be = s;
+      } else if (c >= 0.0) {
         al = -s / (1.0 + c);
         be = s;
       } else {
@@ -1117,6 +1202,40 @@ __device__ __forceinline__ void stage_pass(const PassItem& I, OpStage* sops, Pha
   static_assert(sizeof(PhaseDesc) == 12, "PhaseDesc moves as three words");
   const QSV_GLOBAL uint32_t* ph = (const QSV_GLOBAL uint32_t*)(I.phases + I.pd.phase_begin);
   for (int i = tid; i < 3 * n_ph; i += nt) reinterpret_cast<uint32_t*>(sph)[i] = ph[i];
+  // diagonal blocks: entry ri of a head's table is the product over its members of
+  // exp(-i t Z/2)[bit] = c -+ i s (RZ on position ks0) and (-1)^(b0 b1) (CZ on ks0, ks1), from
+  // the members' staged (c, s) (a second round over LDS)
+  if constexpr (RB <= kMaxMacroRegBits) {
+    if (I.pd.n_diag > 0) {
+      lds_barrier();
+      constexpr int NA = 1 << RB;
+      for (int x = tid; x < n_ops * NA; x += nt) {
+        const int i = x / NA, ri = x % NA;
+        const uint4 h = staged_words(sops, i);
+        if ((h.z >> 16) != QSV_OPC(FOP_RZ, QSV_V_DIAG)) continue;
+        const int first = (int)((h.x >> 16) & 0xffu), n_mem = (int)(h.x >> 24);
+        double dr = 1.0, di = 0.0;
+        int sign = 0;
+        for (int m = 0; m < n_mem; ++m) {
+          const uint4 w = staged_words(sops, first + m);
+          const int ks0 = (int)(w.z & 0xffu), ks1 = (int)((w.z >> 8) & 0xffu);
+          if ((w.x & 0xffu) == FOP_RZ) {
+            const double2 cs = staged_cs(sops, first + m);
+            const double c = cs.x, sn = ((ri >> ks0) & 1) ? cs.y : -cs.y;
+            const double t = dr * c - di * sn;
+            di = dr * sn + di * c;
+            dr = t;
+          } else {
+            sign ^= (ri >> ks0) & (ri >> ks1) & 1;
+          }
+        }
+        V e;
+        e.x = sign ? -dr : dr;
+        e.y = sign ? -di : di;
+        sdiag[((h.z >> 8) & 0xffu) * NA + ri] = e;
+      }
+    }
+  }
 }
 
 static_assert(sizeof(FusedOp) == 16 && offsetof(FusedOp, s0) == 3 && offsetof(FusedOp, flags) == 7 &&
@@ -1124,13 +1243,6 @@ static_assert(sizeof(FusedOp) == 16 && offsetof(FusedOp, s0) == 3 && offsetof(Fu
                   offsetof(FusedOp, gate) == 12,
               "FusedOp is read from LDS as four words");
 
-// Raw words of staged op k (issued early; made uniform when the op is executed).
-__device__ __forceinline__ uint4 staged_words(const OpStage* sops, int k) {
-  return *reinterpret_cast<const uint4*>(&sops[k].op);
-}
-__device__ __forceinline__ double2 staged_cs(const OpStage* sops, int k) {
-  return *reinterpret_cast<const double2*>(&sops[k].alpha);
-}
 __device__ __forceinline__ FusedOp uniform_op(uint4 raw) {
   const uint32_t w0 = __builtin_amdgcn_readfirstlane(raw.x);
   const uint32_t w1 = __builtin_amdgcn_readfirstlane(raw.y);
@@ -1247,14 +1359,17 @@ __device__ __forceinline__ double lane63_value(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// The lean forward pass of 512-thread workgroups fits 128 VGPRs: four waves per SIMD, so two
+// workgroups share a CU (one's loads and stores overlap the other's gates).
 template <typename R, int RB, int W, bool GEN>
-__global__ void __launch_bounds__(1 << W)
+__global__ void __launch_bounds__(1 << W) __attribute__((amdgpu_waves_per_eu(W == 9 && !GEN ? 4 : 1)))
 k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64_t chunk) {
   using G = Geometry<RB, W>;
   using V = typename Vec2<R>::T;
   __shared__ V lds[1 << G::T];
   __shared__ OpStage sops[kMaxOpsPerPass + 1];
   __shared__ PhaseDesc sph[kMaxPhasesPerPass];
+  __shared__ V sdiag[RB <= kMaxMacroRegBits ? kMaxDiagBlocks << RB : 1];
   __shared__ double wsum[G::NW];
   const uint32_t tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -1296,7 +1411,7 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
         }
       }
       if (g == g0) {  // staged while the first tile's loads are in flight
-        stage_pass(I, sops, sph, (int)tid, G::NT);
+        stage_pass<RB, V>(I, sops, sph, sdiag, (int)tid, G::NT);
         lds_barrier();
       }
       Layout<RB> cur = LL;
@@ -1329,7 +1444,7 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
             apply_general<R, RB, false>(op, rec, a, cur);
           } else {
             double unused[kMaxMacroRegBits];
-            lean_step<R, RB, false>(op, (R)cs.x, (R)cs.y, rec, sops, a, nullptr, cur.tdep, unused,
+            lean_step<R, RB, false>(op, (R)cs.x, (R)cs.y, rec, sops, sdiag, a, nullptr, cur.tdep, unused,
                                     flip);
           }
         }
@@ -1386,6 +1501,7 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
   __shared__ V lds[SPLIT ? (1 << G::T) : (2 << G::T)];
   __shared__ OpStage sops[kMaxOpsPerPass + 1];
   __shared__ PhaseDesc sph[kMaxPhasesPerPass];
+  __shared__ V sdiag[RB <= kMaxMacroRegBits ? kMaxDiagBlocks << RB : 1];
   // per-wave slot sums, written after the item's last tile: they share the relayout buffer
   // (every wave has passed the barrier that ends its last relayout by then)
   static_assert(sizeof(lds) >= 2 * sizeof(double) * kMaxSlotsPerPass * G::NW,
@@ -1442,7 +1558,7 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
         }
       }
       if (g == g0) {  // staged while the first tile's loads are in flight
-        stage_pass(I, sops, sph, (int)tid, G::NT);
+        stage_pass<RB, V>(I, sops, sph, sdiag, (int)tid, G::NT);
         lds_barrier();
       }
       Layout<RB> cur = LL;
@@ -1482,11 +1598,16 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
             n_sub = RB;
             op.opc = QSV_OPC(op.type, 0);
             op.np = 1;
+          } else if (cx_entries && op.opc == QSV_OPC(FOP_RZ, QSV_V_DIAG)) {
+            n_sub = 1 + op.s0;  // the members one by one; the head itself does nothing
+            op.opc = 0xffff;
+            op.np = 0;
           }
           for (int sub = 0; sub < n_sub; ++sub) {
             if (sub > 0) {
               op = uniform_op(staged_words(sops, mem + sub - 1));
               cs = staged_cs(sops, mem + sub - 1);
+              diag_member_shears(op, cs);
             }
             const GateRec* rec = I.recs + op.gate;
             double prod[kMaxMacroRegBits] = {}, prod_im[kMaxMacroRegBits] = {};
@@ -1497,8 +1618,8 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
               apply_general<R, RB, true>(op, rec, l, cur);
             } else {
               if (cx_entries && op.np) prod_im[0] = lean_product_im<R, RB>(op, f, l, cur.tdep);
-              lean_step<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, sops, f, l, cur.tdep, prod,
-                                     flip);
+              lean_step<R, RB, true>(op, (R)cs.x, (R)cs.y, rec, sops, sdiag, f, l, cur.tdep,
+                                     prod, flip);
             }
             if (!cx_entries) {
 #pragma unroll

@@ -86,11 +86,89 @@ static uint64_t fill_tile(uint64_t T, int n, int t) {
 // straight-line op (one dispatch). The other r - 1 records (the kernel reads only their cos/sin)
 // are stored after the pass's executed ops, at the index the head's k1 names.
 static int rotation_axis(const FusedOp& op) {
+  if (op.flags & FOPF_DIAG) return 0;  // in a diagonal block
   if (op.type == FOP_RY) return 1;
   if (op.type == FOP_RX) return 2;
   if (op.type == FOP_RZ && (op.flags & FOPF_S0_REG)) return 3;
   if (op.type == FOP_RZ) return 4;  // RZ on a thread bit: commutes with the run, not a member
   return 0;
+}
+
+static bool is_diagonal(const FusedOp& op) {
+  return op.type == FOP_RZ || op.type == FOP_CZ || op.type == FOP_DIAG1 || op.type == FOP_PDIAG1 ||
+         op.type == FOP_DIAG2;
+}
+
+// Diagonal blocks. The diagonal gates of a run of consecutive diagonal gates commute, so the run
+// may execute in any order with the same products. Its RZ gates on register bits and its CZ
+// gates with both bits in registers are taken together (in run order, at most kMaxMacroRegBits
+// RZ at a time) as one diagonal matrix on the thread's 2^r amplitudes when that saves arithmetic: per
+// amplitude and state an RZ costs three FMAs (the shears), a CZ about one sign flip per two
+// amplitudes, a block one complex product (four) plus the load of its entry. A head entry (gate
+// index -1) precedes the block's members; the run's other diagonal gates follow the blocks.
+// blocks_left and records_left bound the blocks of the pass (LDS tables) and its staged records.
+static void form_diagonal_blocks(std::vector<std::pair<int, FusedOp>>& ops, bool backward,
+                                 int& blocks_left, int& records_left) {
+  std::vector<std::pair<int, FusedOp>> out;
+  out.reserve(ops.size() + 8);
+  size_t i = 0;
+  while (i < ops.size()) {
+    if (!is_diagonal(ops[i].second)) {
+      out.push_back(ops[i++]);
+      continue;
+    }
+    size_t j = i;
+    while (j < ops.size() && is_diagonal(ops[j].second)) ++j;
+    // members in run order, cut after every kMaxMacroRegBits-th RZ
+    std::vector<std::vector<std::pair<int, FusedOp>>> groups(1);
+    std::vector<std::pair<int, FusedOp>> rest;
+    int nr = 0;
+    for (size_t t = i; t < j; ++t) {
+      const FusedOp& op = ops[t].second;
+      const bool rz = op.type == FOP_RZ && (op.flags & FOPF_S0_REG);
+      const bool cz = op.type == FOP_CZ && (op.flags & FOPF_S0_REG) && (op.flags & FOPF_S1_REG);
+      if (!rz && !cz) {
+        rest.push_back(ops[t]);
+        continue;
+      }
+      if (rz && nr == kMaxMacroRegBits) {
+        groups.emplace_back();
+        nr = 0;
+      }
+      nr += rz;
+      groups.back().push_back(ops[t]);
+    }
+    for (auto& grp : groups) {
+      int g_rz = 0;
+      for (auto& e : grp) g_rz += e.second.type == FOP_RZ;
+      const int g_cz = (int)grp.size() - g_rz;
+      if (6 * g_rz + g_cz >= 12 && blocks_left > 0 && records_left > 0) {
+        FusedOp h;
+        std::memset(&h, 0, sizeof h);
+        h.type = FOP_RZ;
+        h.flags = FOPF_DIAG;
+        h.opc = (uint16_t)QSV_OPC(FOP_RZ, QSV_V_DIAG);
+        h.s0 = (uint8_t)grp.size();
+        h.np = (uint8_t)(backward ? g_rz : 0);
+        h.ks1 = (uint8_t)(kMaxDiagBlocks - blocks_left);
+        int m = 0;
+        for (auto& e : grp)
+          if (e.second.type == FOP_RZ) h.gate |= (int32_t)e.second.ks0 << (4 * m++);
+        --blocks_left;
+        --records_left;
+        out.emplace_back(-1, h);
+        for (auto& e : grp) {
+          out.push_back(e);
+          out.back().second.flags |= FOPF_DIAG;
+        }
+      } else {
+        for (auto& e : grp) out.push_back(e);
+      }
+    }
+    for (auto& e : rest) out.push_back(e);
+    i = j;
+  }
+  ops.swap(out);
 }
 
 static int register_position(const FusedOp& op) {
@@ -246,6 +324,7 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
     std::vector<int> prem(taken);
     std::vector<int> placed;
     int lslot = 0;
+    int blocks_left = kMaxDiagBlocks, records_left = kMaxOpsPerPass - (int)taken.size();
     // rotation macros: the members after a head are stored past the executed ops of the pass
     std::vector<FusedOp> members;
     std::vector<std::pair<size_t, size_t>> heads;  // (op index, first member in `members`)
@@ -380,18 +459,34 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
         if (op.type >= FOP_FIRST_GENERAL) pd.general = 1;
         emitted.emplace_back(k, op);
       }
-      if (macros && r <= kMaxMacroRegBits) form_rotation_macros(emitted, r);
-      int members_left = 0;
+      if (macros && r <= kMaxMacroRegBits) {
+        form_diagonal_blocks(emitted, backward, blocks_left, records_left);
+        form_rotation_macros(emitted, r);
+      }
+      int members_left = 0, block_left = 0;
+      size_t block_head = 0;
       for (auto& e : emitted) {
         const int k = e.first;
         FusedOp& op = e.second;
+        if (k < 0) {  // diagonal block head: its members follow
+          heads.emplace_back(out.ops.size(), members.size());
+          block_head = out.ops.size();
+          out.ops.push_back(op);
+          block_left = op.s0;
+          // the RZ members take consecutive local slots from here (the CZ members take none)
+          if (op.np) out.ops[block_head].lslot = (uint8_t)lslot;
+          continue;
+        }
         const int np = backward ? kind_nparams(gates[k].kind) : 0;
         if (np) {
           op.lslot = (uint8_t)lslot;
           for (int j = 0; j < np; ++j) out.slot_map.push_back(slot_of_gate[k] + j);
           lslot += np;
         }
-        if (op.flags & FOPF_MACRO) {  // products of all r positions, consecutive local slots
+        if (block_left > 0) {
+          members.push_back(op);
+          --block_left;
+        } else if (op.flags & FOPF_MACRO) {  // products of all r positions, consecutive local slots
           op.np = (uint8_t)(backward ? r : 0);
           op.opc = (uint16_t)QSV_OPC(op.type, QSV_V_MACRO);
           heads.emplace_back(out.ops.size(), members.size());
@@ -424,6 +519,7 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
       if (keeps_runs(out.phases[pd.phase_end - 1])) pd.io_flags |= PASS_STORE_LAST_PHASE;
     }
     pd.n_slots = lslot;
+    pd.n_diag = (int8_t)(kMaxDiagBlocks - blocks_left);
     const size_t n_exec = out.ops.size() - pd.op_begin;
     for (const auto& h : heads) out.ops[h.first].k1 = (uint8_t)(n_exec + h.second);
     out.ops.insert(out.ops.end(), members.begin(), members.end());

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2009_02823_amd import workloads as W
+from test_schedule_cpu import diagonal_layers
 
 pytestmark = pytest.mark.gpu
 
@@ -132,3 +133,48 @@ def test_batched(Q, orc):
         e_ref, g_ref = orc.adjoint_gradient(p.n_qubits, p.gates, p.theta, p.codes, p.coeffs)
         gb = g[batch.theta_off[b]: batch.theta_off[b] + p.n_params]
         check("c128", float(e[b]), gb, e_ref.real, g_ref, p.coeffs)
+
+
+def diag_problem(seed, n, layers=2, cz_repeat=1, h=8):
+    rng = np.random.default_rng(seed)
+    gates, P = diagonal_layers(rng, n, layers, cz_repeat)
+    theta = W.uniform_angles(rng, P)
+    codes = W.random_pauli_strings(rng, n, h)
+    coeffs = rng.standard_normal(h)
+    return gates, theta, codes, coeffs
+
+
+DIAG_GEOMS = {"c128": [(2, 6), (3, 6), (2, 8), (3, 8), (4, 8), (3, 9)],
+              "c64": [(2, 6), (3, 6), (2, 8), (3, 8), (4, 8), (3, 9), (4, 9)]}
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,cz_repeat", [(10, 1), (13, 1), (13, 13)])
+def test_diagonal_blocks(Q, orc, dtype, n, cz_repeat):
+    """RZ and CZ runs on register bits run as diagonal blocks (several RZ per block, blocks of
+    CZ alone): both sweeps against the oracle in every geometry."""
+    gates, theta, codes, coeffs = diag_problem(3400 + n + cz_repeat, n, cz_repeat=cz_repeat)
+    e_ref, g_ref = orc.adjoint_gradient(n, gates, theta, codes, coeffs)
+    for r, w in DIAG_GEOMS[dtype]:
+        assert Q.schedule_describe(n, gates, True, r, w, dtype)["n_diag_blocks"] > 0
+        with Q.StateVector(n, dtype) as sv:
+            sv.set_fusion(1, r, w)
+            e, g = sv.adjoint_gradient(gates, theta, codes, coeffs)
+            sv.sync()
+            check(dtype, float(e.cpu()[0]), g.cpu().numpy(), e_ref.real, g_ref, coeffs)
+
+
+@pytest.mark.parametrize("geom", [(2, 8), (3, 8), (4, 8)])
+def test_diagonal_blocks_nonhermitian(Q, orc, geom):
+    """Complex gradient entries run a block's members one by one."""
+    n = 11
+    gates, theta, codes, coeffs = diag_problem(3500, n)
+    c = coeffs + 1j * np.random.default_rng(3501).standard_normal(coeffs.shape[0])
+    e_ref, g_ref = orc.adjoint_gradient_nonhermitian(n, gates, theta, codes, c)
+    with Q.StateVector(n) as sv:
+        sv.set_fusion(1, *geom)
+        e, g = sv.adjoint_gradient_nonhermitian(gates, theta, codes, c)
+        sv.sync()
+        e, g = complex(e.cpu()[0]), g.cpu().numpy()
+    assert abs(e - e_ref) <= 1e-10
+    assert np.max(np.abs(g - g_ref)) <= 1e-10

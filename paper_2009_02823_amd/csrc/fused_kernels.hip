@@ -264,25 +264,37 @@ __device__ __forceinline__ void cnot_rr(cx<R>* a) {
 }
 
 // CNOT with the control on a thread bit: swap the target pairs of the threads whose bit is set.
+// A branch on the thread's bit (the swaps run under the exec mask of those lanes): one v_swap_b32
+// per word instead of two selects.
 template <typename R, int NA, int KT>
 __device__ __forceinline__ void cnot_tr(cx<R>* a, bool on) {
+  if (on) {
 #pragma unroll
-  for (int ri = 0; ri < NA; ++ri) {
-    if (ri & (1 << KT)) continue;
-    const int rj = ri | (1 << KT);
-    const cx<R> x = a[ri], y = a[rj];
-    a[ri] = sel(on, y, x);
-    a[rj] = sel(on, x, y);
+    for (int ri = 0; ri < NA; ++ri) {
+      if (ri & (1 << KT)) continue;
+      const int rj = ri | (1 << KT);
+      swap_inplace(a[ri].r, a[rj].r);
+      swap_inplace(a[ri].i, a[rj].i);
+    }
   }
+}
+
+// Flips the sign of x when sign = 0x80000000 (an XOR of the sign bit).
+__device__ __forceinline__ double flip_sign(double x, uint32_t sign) {
+  return __hiloint2double(__double2hiint(x) ^ (int)sign, __double2loint(x));
+}
+__device__ __forceinline__ float flip_sign(float x, uint32_t sign) {
+  return __int_as_float(__float_as_int(x) ^ (int)sign);
 }
 
 // Negate the amplitudes whose register bits in MASK are all set, when `on`.
 template <typename R, int NA, int MASK>
 __device__ __forceinline__ void neg_where(cx<R>* a, bool on) {
+  const uint32_t sign = on ? 0x80000000u : 0u;
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
     if ((ri & MASK) != MASK) continue;
-    a[ri] = sel(on, neg(a[ri]), a[ri]);
+    a[ri] = cx<R>{flip_sign(a[ri].r, sign), flip_sign(a[ri].i, sign)};
   }
 }
 

@@ -396,6 +396,8 @@ typedef struct {
   int32_t n_direct_stores;  /* passes that store their tiles from the last phase's layout      */
   int32_t n_diag_blocks;    /* diagonal blocks (RZ and CZ gates on register bits run as one
                                diagonal matrix per thread; formed for reg_qubits <= 4)         */
+  int32_t n_folded_cnots;   /* reverse sweep: CNOTs with both bits in registers that open a
+                               phase entered by a relayout (its reads permute the registers) */
 } qsv_schedule_info;
 
 qsv_status qsv_schedule_describe(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates,

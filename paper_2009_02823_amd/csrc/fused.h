@@ -101,7 +101,11 @@ enum : uint8_t { PASS_LOAD_FIRST_PHASE = 1, PASS_STORE_LAST_PHASE = 2 };
 struct PhaseDesc {
   int32_t op_end;                 // ops [previous op_end, op_end) of the pass
   int8_t regbit[kMaxRegBits];     // tile bit of each register position
-  int8_t pad[3];
+  uint8_t pad;
+  // 0, or (reverse sweep) the register-index map of CNOTs with both bits in registers that open
+  // the phase, taken into the relayout before it: register ri reads the element of index Q(ri), Q linear
+  // over GF(2) with Q(e_k) in bits 4k .. 4k + 3 (reg_qubits <= 4)
+  uint16_t rperm;
 };
 
 struct PassDesc {
@@ -169,6 +173,7 @@ struct Schedule {
   // ops[i] when the schedule has no rotation macros)
   std::vector<int32_t> order, pass_of, phase_of;
   std::vector<uint64_t> tile_mask, reg_mask;
+  int n_folded = 0;  // CNOTs taken into a relayout (PhaseDesc::rperm) instead of executed
 };
 
 // Builds the schedule of `gates` taken in order `seq` (gate indices). slot_of_gate[k] is the first

@@ -103,9 +103,23 @@ __device__ __forceinline__ uint32_t lds_index(const Layout<RB>& L, int ri) {
   return L.tsw ^ Swz<R>::f(reg_deposit<RB>(L, ri));
 }
 
+// Register index ri through a phase's rperm (PhaseDesc): 0 is the identity; otherwise the XOR of
+// the images Q(e_k) (bits 4k .. 4k + 3) of ri's set bits. Uniform.
+template <int RB>
+__device__ __forceinline__ int perm_index(uint32_t rperm, int ri) {
+  if (rperm == 0) return ri;
+  uint32_t v = 0;
+#pragma unroll
+  for (int k = 0; k < RB; ++k)
+    if ((ri >> k) & 1) v ^= (rperm >> (4 * k)) & 15u;
+  return (int)v;
+}
+
+// rperm: the reads take element Q(ri) into register ri (CNOTs on register bits folded into the
+// relayout; 0 for none).
 template <typename R, int RB>
 __device__ __forceinline__ void relayout(cx<R>* a, const Layout<RB>& from, const Layout<RB>& to,
-                                         typename Vec2<R>::T* lds) {
+                                         typename Vec2<R>::T* lds, uint32_t rperm = 0) {
   constexpr int NA = 1 << RB;
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
@@ -117,7 +131,7 @@ __device__ __forceinline__ void relayout(cx<R>* a, const Layout<RB>& from, const
   lds_barrier();
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
-    const typename Vec2<R>::T v = lds[lds_index<R, RB>(to, ri)];
+    const typename Vec2<R>::T v = lds[lds_index<R, RB>(to, perm_index<RB>(rperm, ri))];
     a[ri].r = v.x;
     a[ri].i = v.y;
   }
@@ -128,7 +142,7 @@ __device__ __forceinline__ void relayout(cx<R>* a, const Layout<RB>& from, const
 template <typename R, int RB>
 __device__ __forceinline__ void relayout2(cx<R>* a, cx<R>* b, const Layout<RB>& from,
                                           const Layout<RB>& to, typename Vec2<R>::T* lds,
-                                          int half) {
+                                          int half, uint32_t rperm = 0) {
   constexpr int NA = 1 << RB;
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
@@ -144,7 +158,7 @@ __device__ __forceinline__ void relayout2(cx<R>* a, cx<R>* b, const Layout<RB>& 
   lds_barrier();
 #pragma unroll
   for (int ri = 0; ri < NA; ++ri) {
-    const uint32_t x = lds_index<R, RB>(to, ri);
+    const uint32_t x = lds_index<R, RB>(to, perm_index<RB>(rperm, ri));
     const typename Vec2<R>::T v = lds[x], w = lds[half + x];
     a[ri].r = v.x;
     a[ri].i = v.y;
@@ -1277,7 +1291,8 @@ __device__ __forceinline__ FusedOp uniform_op(uint4 raw) {
 
 // Phase ph of the staged pass: its op end and register bits, as uniform values.
 template <int RB>
-__device__ __forceinline__ int uniform_phase(const PhaseDesc* sph, int ph, int8_t* rb) {
+__device__ __forceinline__ int uniform_phase(const PhaseDesc* sph, int ph, int8_t* rb,
+                                             uint32_t* rperm) {
   static_assert(sizeof(PhaseDesc) == 12, "PhaseDesc is read from LDS as three words");
   const uint32_t* p = reinterpret_cast<const uint32_t*>(sph + ph);
   const uint32_t w0 = __builtin_amdgcn_readfirstlane(p[0]);
@@ -1285,6 +1300,8 @@ __device__ __forceinline__ int uniform_phase(const PhaseDesc* sph, int ph, int8_
   const uint32_t w2 = __builtin_amdgcn_readfirstlane(p[2]);
 #pragma unroll
   for (int k = 0; k < RB; ++k) rb[k] = (int8_t)(((k < 4 ? w1 >> (8 * k) : w2 >> (8 * (k - 4)))) & 0xffu);
+  static_assert(offsetof(PhaseDesc, rperm) == 10, "rperm is the high half of the third word");
+  *rperm = w2 >> 16;
   return (int)w0;
 }
 
@@ -1433,7 +1450,8 @@ k_pass_fwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
       double2 ncs = staged_cs(sops, 0);
       for (int ph = 0; ph < n_ph; ++ph) {
         int8_t rb[RB];
-        const int op_end = uniform_phase<RB>(sph, ph, rb);
+        uint32_t rperm;  // 0: the forward schedule folds no CNOTs
+        const int op_end = uniform_phase<RB>(sph, ph, rb, &rperm);
         if (!same_layout<RB>(cur, rb)) {
           Layout<RB> nxt;
           make_layout<R, RB>(nxt, rb, tid);
@@ -1581,15 +1599,16 @@ k_pass_bwd(const PassItem* __restrict__ items, int n_items, int64_t total, int64
       double2 ncs = staged_cs(sops, 0);
       for (int ph = 0; ph < n_ph; ++ph) {
         int8_t rb[RB];
-        const int op_end = uniform_phase<RB>(sph, ph, rb);
+        uint32_t rperm;
+        const int op_end = uniform_phase<RB>(sph, ph, rb, &rperm);
         if (!same_layout<RB>(cur, rb)) {
           Layout<RB> nxt;
           make_layout<R, RB>(nxt, rb, tid);
           if constexpr (SPLIT) {
-            relayout<R, RB>(f, cur, nxt, lds);
-            relayout<R, RB>(l, cur, nxt, lds);
+            relayout<R, RB>(f, cur, nxt, lds, rperm);
+            relayout<R, RB>(l, cur, nxt, lds, rperm);
           } else {
-            relayout2<R, RB>(f, l, cur, nxt, lds, 1 << G::T);
+            relayout2<R, RB>(f, l, cur, nxt, lds, 1 << G::T, rperm);
           }
           cur = nxt;
         }

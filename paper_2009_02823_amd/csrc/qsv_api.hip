@@ -2396,6 +2396,7 @@ extern "C" qsv_status qsv_schedule_describe(int32_t n, const qsv_gate* gates, in
   for (size_t i = 0; i < sc.phases.size(); ++i) out->reg_mask[i] = sc.reg_mask[i];
   out->n_macros = 0;
   for (const FusedOp& op : sc.ops) out->n_macros += (op.flags & FOPF_MACRO) ? 1 : 0;
+  out->n_folded_cnots = sc.n_folded;
   out->n_diag_blocks = 0;
   for (const FusedOp& op : sc.ops)
     out->n_diag_blocks += op.opc == QSV_OPC(FOP_RZ, QSV_V_DIAG) ? 1 : 0;

@@ -325,6 +325,7 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
     std::vector<int> placed;
     int lslot = 0;
     int blocks_left = kMaxDiagBlocks, records_left = kMaxOpsPerPass - (int)taken.size();
+    uint32_t prev_R = 0;  // register bits of the previous phase of the pass
     // rotation macros: the members after a head are stored past the executed ops of the pass
     std::vector<FusedOp> members;
     std::vector<std::pair<size_t, size_t>> heads;  // (op index, first member in `members`)
@@ -462,7 +463,38 @@ bool build_schedule(int n, const std::vector<GateDesc>& gates, const std::vector
       if (macros && r <= kMaxMacroRegBits) {
         form_diagonal_blocks(emitted, backward, blocks_left, records_left);
         form_rotation_macros(emitted, r);
+        // reverse sweep: CNOTs with both bits in registers that open a phase entered by a
+        // relayout permute the register indices; the relayout's reads take them (rperm) and they
+        // are not executed (in the forward sweep few CNOTs open a phase, and the permuted reads
+        // cost the forward pass more than they save)
+        if (backward && out.phases.size() > (size_t)pd.phase_begin && R != prev_R) {
+          size_t m = 0;
+          while (m < emitted.size() && emitted[m].second.type == FOP_CNOT &&
+                 (emitted[m].second.flags & FOPF_S0_REG))
+            ++m;
+          if (m > 0) {
+            uint32_t q = 0;
+            for (int k2 = 0; k2 < r; ++k2) {
+              uint32_t v = 1u << k2;
+              for (size_t j = m; j-- > 0;) {
+                const FusedOp& c = emitted[j].second;
+                v ^= ((v >> c.ks0) & 1u) << c.k0;
+              }
+              q |= v << (4 * k2);
+            }
+            P.rperm = (uint16_t)q;
+            out.n_folded += (int)m;
+            for (size_t j = 0; j < m; ++j) {
+              placed.push_back(emitted[j].first);
+              out.order.push_back(emitted[j].first);
+              out.pass_of.push_back(pass_id);
+              out.phase_of.push_back(phase_id);
+            }
+            emitted.erase(emitted.begin(), emitted.begin() + (long)m);
+          }
+        }
       }
+      prev_R = R;
       int members_left = 0, block_left = 0;
       size_t block_head = 0;
       for (auto& e : emitted) {

@@ -43,7 +43,7 @@ class ScheduleInfo(ctypes.Structure):
                 ("phase_of", ctypes.c_void_p), ("tile_mask", ctypes.c_void_p),
                 ("reg_mask", ctypes.c_void_p), ("n_macros", ctypes.c_int32),
                 ("n_direct_loads", ctypes.c_int32), ("n_direct_stores", ctypes.c_int32),
-                ("n_diag_blocks", ctypes.c_int32)]
+                ("n_diag_blocks", ctypes.c_int32), ("n_folded_cnots", ctypes.c_int32)]
 
 
 class PauliSum(ctypes.Structure):
@@ -201,7 +201,8 @@ def schedule_describe(n_qubits: int, gates, backward: bool, reg_qubits: int, thr
             "pass_of": pass_of[:G], "phase_of": phase_of[:G],
             "tile_mask": tile[:info.n_passes], "reg_mask": reg[:info.n_phases],
             "n_macros": info.n_macros, "n_direct_loads": info.n_direct_loads,
-            "n_direct_stores": info.n_direct_stores, "n_diag_blocks": info.n_diag_blocks}
+            "n_direct_stores": info.n_direct_stores, "n_diag_blocks": info.n_diag_blocks,
+            "n_folded_cnots": info.n_folded_cnots}
 
 
 def state_bytes(n_qubits: int, dtype: str = "c128") -> int:

@@ -227,3 +227,10 @@ def test_headline_schedule_forms_diagonal_blocks():
     gates = W.hea_circuit(30, 10)
     for backward in (False, True):
         assert qsv.schedule_describe(30, gates, backward, 4, 8)["n_diag_blocks"] > 0
+
+
+def test_headline_schedule_folds_register_cnots():
+    """The reverse sweep's CNOT ladders open phases entered by a relayout: most of the CNOTs
+    with both bits in registers become register permutations of that relayout."""
+    gates = W.hea_circuit(30, 10)
+    assert qsv.schedule_describe(30, gates, True, 4, 8)["n_folded_cnots"] > 100
